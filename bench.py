@@ -1,0 +1,196 @@
+#!/usr/bin/env python
+"""Benchmark: PCG-to-1e-8 solves of the SEM Poisson problem on one MI355X.
+
+Workload (default): 32x32x32 hexahedral box of [0,1]^3, vertices moved by
+0.05 sin(pi x) sin(pi y) sin(pi z), order N = 7 (11,089,567 unknowns), p-multigrid
+schedule (7,3,1), optimised 4th-kind Chebyshev-Jacobi smoothing of order 4 in a
+one-sided V-cycle, exact order-1 coarse solve, flexible CG to ||r|| <= 1e-8 ||b||,
+load 3 pi^2 sin sin sin plus 1e-3 relative U[-1,1] noise (seed 0).
+
+One step = one full solve from x0 = 0 with the right-hand side resident in HBM.
+Both forms are timed on the same GPU: the mixed-precision form (FP32 smoothing
+with BF16 geometric factors inside an FP64 flexible CG, FP64 coarse solve) is
+the reported `value`; the all-FP64 form is reported beside it.
+
+Prints one JSON line (see the fields below). `roofline` is for the dominant
+kernel, the element-local SEM operator, timed with HIP events on the stream
+the library launches on.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--m", type=int, default=32, help="elements per direction")
+    ap.add_argument("--order", type=int, default=7)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_solves(solver, b, steps, warmup):
+    import torch
+    info = None
+    for _ in range(warmup):
+        _, info = solver.solve(b, rtol=1e-8, maxit=500)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for _ in range(steps):
+        u, info = solver.solve(b, rtol=1e-8, maxit=500)
+        its.append(info.iterations)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return u, info, dt, its
+
+
+def time_kernel(fn, reps):
+    """Average duration of fn() (one kernel launch) with events on the current stream."""
+    import torch
+    fn()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    e.synchronize()
+    return s.elapsed_time(e) / reps * 1e-3
+
+
+def cpu_baseline(m, N, n_global):
+    """The oracle (numpy FP64) on the same workload: one flexible-CG iteration
+    (one V-cycle plus one operator application and the vector updates) timed on
+    the host. The lambda_max values do not change the cost and are set to 2."""
+    import workload as wl
+    from oracle import chebyshev as cheb, krylov, mg
+    V = wl.deformed_box(m, 0.05)
+    h = mg.sem_hierarchy(V, N, cheb.CHEB4_OPT, 4, 0, lmax=[2.0, 2.0])
+    box = h.extra["boxes"][0]
+    b = box.mass() * wl.manufactured_load(box.coords())
+    t0 = time.perf_counter()
+    krylov.pcg(box.apply, b, h.vcycle, 1e-8, 1, flexible=True)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(n_global / dt / 1e9, 6), "unit": "GDOF-iter/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"1 flexible-CG iteration (V-cycle + operator) on the {m}^3 N={N} box, {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import workload as wl
+    from paper_2210_03179_amd.solver import SemSolver
+
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    m, N = args.m, args.order
+    V = wl.deformed_box(m, 0.05)
+    t0 = time.perf_counter()
+    s64 = SemSolver(V, N=N, smoother="cheb4opt", pre=4, post=0, precision="fp64", krylov="fcg")
+    t_setup64 = time.perf_counter() - t0
+    log(f"fp64 setup {t_setup64:.1f} s, lambda_max {s64.lambda_max()}")
+    t0 = time.perf_counter()
+    smx = SemSolver(V, N=N, smoother="cheb4opt", pre=4, post=0, precision="mixed", krylov="fcg")
+    t_setupmx = time.perf_counter() - t0
+    log(f"mixed setup {t_setupmx:.1f} s")
+    n = s64.n
+    nloc = s64.n_local
+    f = wl.manufactured_load(s64.coords().cpu().numpy())
+    b0 = s64.mass_apply(torch.from_numpy(f).cuda()).cpu().numpy()
+    bh = b0 + 1e-3 * np.max(np.abs(b0)) * wl.uniform_noise(n, 0)
+    b = torch.from_numpy(bh).cuda()
+
+    u64, info64, dt64, its64 = time_solves(s64, b, args.steps, args.warmup)
+    log(f"fp64: {info64.iterations} its, {dt64 * 1e3:.2f} ms/solve")
+    umx, infomx, dtmx, itsmx = time_solves(smx, b, args.steps, args.warmup)
+    log(f"mixed: {infomx.iterations} its, {dtmx * 1e3:.2f} ms/solve")
+
+    def true_rel(u):
+        r = b - s64.apply_A(u)
+        return float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
+
+    rel64, relmx = true_rel(u64), true_rel(umx)
+    err_mx = float(torch.linalg.vector_norm(umx - u64) / torch.linalg.vector_norm(u64))
+
+    # dominant kernel: element-local operator, FP64 (48 B factors + 8 B output per local node,
+    # 8 B input per unknown) and the BF16/FP32 form (12 + 4 B per local node, 4 B per unknown)
+    u_rand = torch.rand(n, dtype=torch.float64, device="cuda")
+    w_loc = torch.empty(nloc, dtype=torch.float64, device="cuda")
+    t_ax64 = time_kernel(lambda: s64.apply_local(u_rand, w_loc), args.kernel_reps)
+    bytes64 = 56.0 * nloc + 8.0 * n
+    u32 = u_rand.float()
+    w32 = torch.empty(nloc, dtype=torch.float32, device="cuda")
+    t_axmx = time_kernel(lambda: smx.apply_local(u32, w32), args.kernel_reps)
+    bytesmx = 16.0 * nloc + 4.0 * n
+    t_apply = time_kernel(lambda: s64.apply_A(u_rand, w_loc[:n]), args.kernel_reps)
+    log(f"ax fp64 {t_ax64 * 1e6:.1f} us ({bytes64 / t_ax64 / 1e9:.0f} GB/s), "
+        f"ax bf16 {t_axmx * 1e6:.1f} us ({bytesmx / t_axmx / 1e9:.0f} GB/s), apply_A fp64 {t_apply * 1e6:.1f} us")
+
+    gdof_mx = n * infomx.iterations / dtmx / 1e9
+    gdof_64 = n * info64.iterations / dt64 / 1e9
+    ach = bytes64 / t_ax64 / 1e9
+    out = {
+        "metric": "PCG-to-1e-8 solve time & GDOF-iter/s; mixed/batched vs plain FP64 same GPU",
+        "value": round(gdof_mx, 4),
+        "unit": "GDOF-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dtmx * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+bf16 V-cycle / f64 Krylov",
+        "data": "synthetic",
+        "config": {"workload": f"SEM Poisson {m}^3 deformed hex box, N={N}, pMG ({N},{N // 2},1), "
+                               f"opt-4th Chebyshev (4,0) one-sided, FCG to 1e-8",
+                   "unknowns": n, "local_nodes": nloc, "parallelism": "single GPU"},
+        "iterations": infomx.iterations,
+        "true_relres": relmx,
+        "rel_diff_to_fp64_solution": err_mx,
+        "fp64": {"ms_per_solve": round(dt64 * 1e3, 4), "iterations": info64.iterations,
+                 "gdof_iter_per_s": round(gdof_64, 4), "true_relres": rel64},
+        "speedup_mixed_vs_fp64": round(dt64 / dtmx, 4),
+        "setup_s": {"fp64": round(t_setup64, 2), "mixed": round(t_setupmx, 2)},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "ax_local_kernel<7,double,double>", "kernel_us": round(t_ax64 * 1e6, 2),
+                     "bytes_per_launch": bytes64,
+                     "mixed_kernel": {"kernel": "ax_local_kernel<7,float,bf16>", "kernel_us": round(t_axmx * 1e6, 2),
+                                      "achieved": round(bytesmx / t_axmx / 1e9, 1)}},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(m, N, n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * semcheb — Chebyshev-smoothed p-multigrid preconditioned CG for the
+ * spectral-element Poisson problem, on AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Phillips & Fischer, "Optimal Chebyshev Smoothers and
+ * One-sided V-cycles" (arXiv 2210.03179):
+ *   - the discrete Poisson system A u = b with A SPD, a_ij = integral of
+ *     grad phi_i . grad phi_j over the domain (Sec. 1, eq. poisson);
+ *   - V-cycles with error propagator E_j of eq. recursive-v-cycle-err-prop,
+ *     symmetric (k,k) smoothing or one-sided fine-to-coarse (m,0) smoothing
+ *     (eq. recursive-ftc-err), exact solve on the coarsest level (M_l = A_l);
+ *   - Jacobi-scaled Chebyshev smoothers: 1st kind (Algorithm 1, lambda_min =
+ *     0.1 lambda_max or the correlation of eq. opt-lambda-min), 4th kind and
+ *     optimised 4th kind (Algorithm 2, beta_i from the supplementary Table
+ *     beta_coef);
+ *   - p-multigrid schedules N -> floor(N/2) -> 1 (Sec. 4.1, pMG);
+ *   - CG as the outer Krylov method (Sec. 6.1), here also in a flexible
+ *     (Polak-Ribiere) form for non-symmetric or reduced-precision cycles;
+ *   - the 2D finite-difference model problem with Galerkin geometric
+ *     multigrid (Sec. 3).
+ *
+ * Conventions (all entry points):
+ *   - Status codes are returned, never exceptions; sem_last_error() gives
+ *     the message of the last failure on a context, sem_global_error() the
+ *     message of the last failed setup call.
+ *   - "device" pointers are HIP device memory owned by the caller (for
+ *     example torch tensors), contiguous, of the documented length.
+ *     "host" pointers are ordinary host memory, read during the call only.
+ *   - Every call that takes a `stream` (a hipStream_t, NULL = default
+ *     stream) is ordered on that stream; only sem_solve and the setup calls
+ *     synchronise with the host.
+ *   - Global vectors hold the interior (non-Dirichlet) unknowns. For a box of
+ *     nex x ney x nez elements of order N they are the lattice nodes
+ *     (I, J, K), 1 <= I <= nex*N-1 (likewise J, K), stored with index
+ *     (I-1) + nx*((J-1) + ny*(K-1)), nx = nex*N-1, ny = ney*N-1.
+ *   - Element e = ex + nex*(ey + ney*ez); an element-local array has the
+ *     layout [e][k][j][i] with (N+1)^3 nodes per element, i fastest.
+ *   - The geometric factors G are stored [e][c][k][j][i] with the six
+ *     components c = (rr, rs, rt, ss, st, tt) of
+ *     w_i w_j w_k |J| (dr_a/dx)(dr_b/dx).
+ *   - The library owns every setup array: they are allocated at setup and
+ *     released by sem_destroy. Contexts are not thread safe; calls on one
+ *     context must not overlap.
+ */
+#ifndef SEMCHEB_H
+#define SEMCHEB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sem_ctx sem_ctx; /* opaque */
+
+typedef enum {
+  SEM_OK = 0,
+  SEM_EINVAL = -1,      /* invalid argument (sizes, orders, options) */
+  SEM_ENOMEM = -2,      /* device or host allocation failed */
+  SEM_EHIP = -3,        /* a HIP runtime call failed */
+  SEM_EMESH = -4,       /* an element has a non-positive Jacobian */
+  SEM_ENOTCONV = -5,    /* maxit reached; u holds the last iterate */
+  SEM_EBREAKDOWN = -6,  /* r.z <= 0 or p.Ap <= 0 in the Krylov method */
+  SEM_ENAN = -7,        /* NaN or Inf met in the right-hand side or a residual */
+  SEM_ENODEV = -8       /* no usable GPU (or a host-only context was given) */
+} sem_status;
+
+/* Smoother kinds (Sec. 2). */
+enum {
+  SEM_CHEB1 = 1,     /* 1st kind, lambda_min = 0.1 lambda_max ("1st-Cheb") */
+  SEM_CHEB1_OPT = 2, /* 1st kind, lambda_min by eq. opt-lambda-min */
+  SEM_CHEB4 = 4,     /* 4th kind, beta_i = 1 */
+  SEM_CHEB4_OPT = 5  /* optimised 4th kind, beta from Table beta_coef (order <= 16) */
+};
+enum { SEM_FP64 = 0, SEM_MIXED = 1 }; /* precision of the V-cycle */
+enum { SEM_PCG = 0, SEM_FCG = 1 };    /* Krylov method */
+
+#define SEM_MAX_LEVELS 8
+
+typedef struct {
+  int32_t N;                        /* finest polynomial order, 1..15 */
+  int32_t num_levels;               /* 0: default schedule N, floor(N/2), 1 */
+  int32_t orders[SEM_MAX_LEVELS];   /* decreasing orders, last must be 1 */
+  int32_t smoother;                 /* SEM_CHEB1 ... SEM_CHEB4_OPT */
+  int32_t pre_order;                /* m: order of pre-smoothing (0..32) */
+  int32_t post_order;               /* n: order of post-smoothing, 0 = one-sided */
+  int32_t precision;                /* SEM_FP64 or SEM_MIXED */
+  int32_t krylov;                   /* SEM_PCG or SEM_FCG */
+  int32_t num_lambda_max;           /* 0: estimate every smoothed level at setup */
+  double lambda_max[SEM_MAX_LEVELS];/* lambda_max(S_j A_j) per smoothed level */
+  double lambda_scale;              /* factor applied to estimated values (0 -> 1) */
+  int32_t device;                   /* HIP device ordinal; -1: host-only context */
+  int32_t coarse_planes;            /* planes per block of the coarse solve, 0 = auto */
+} sem_options;
+
+/* Structured hexahedral box mesh: (nex+1)(ney+1)(nez+1) vertices, x fastest.
+ * Element (ex,ey,ez) is the trilinear image of [-1,1]^3 under its 8 corner
+ * vertices; Dirichlet conditions hold on the whole boundary. */
+typedef struct {
+  int32_t nex, ney, nez;
+  const double *vertex_xyz; /* host, [(nez+1)][(ney+1)][(nex+1)][3] */
+} sem_box_mesh;
+
+/* Fills *opt with: N = 7, default schedule, SEM_CHEB4_OPT, (4,0), FP64,
+ * SEM_FCG, estimated lambda_max, lambda_scale 1, device 0. */
+void sem_options_default(sem_options *opt);
+
+/* Set up the SEM hierarchy on a box mesh: GLL data, geometric factors, Jacobi
+ * diagonals, transfers, lambda_max (Lanczos unless given), and the factored
+ * coarse (order 1) operator. Errors: SEM_EINVAL (orders, sizes, opt-4th order
+ * > 16), SEM_EMESH (det J <= 0), SEM_ENOMEM, SEM_EHIP, SEM_ENODEV. */
+sem_status sem_setup_box(const sem_box_mesh *mesh, const sem_options *opt, void *stream,
+                         sem_ctx **out);
+
+/* 2D finite-difference model problem of Sec. 3: [0,Lx]x[0,Ly], n intervals
+ * per direction (n-1 interior points, x fastest), 5-point operator, bilinear
+ * interpolation with coarsening factor `factor` (2 or 8) while the coarse
+ * interval count stays >= coarsest_n, Galerkin coarse operators
+ * (eq. galerkin-coarse-grid), dense exact solve on the coarsest level.
+ * opt->N, orders and precision are ignored. */
+sem_status sem_setup_fd2d(int32_t n, double Lx, double Ly, int32_t factor, int32_t coarsest_n,
+                          const sem_options *opt, void *stream, sem_ctx **out);
+
+/* Number of global unknowns, levels, and element-local nodes on the finest level
+ * (0 for the FD problem). Any output pointer may be NULL. */
+sem_status sem_sizes(const sem_ctx *ctx, int64_t *n_global, int32_t *num_levels, int64_t *n_local);
+
+/* Order, unknown count and lambda_max(S_j A_j) of level j (0 = finest). */
+sem_status sem_level_info(const sem_ctx *ctx, int32_t level, int32_t *order, int64_t *n,
+                          double *lambda_max);
+
+/* w = A u on the finest level (FP64). u, w: device, n_global doubles. */
+sem_status sem_apply_A(sem_ctx *ctx, const double *u, double *w, void *stream);
+
+/* Element-local operator on the finest level: wL = A_L Q R^T u, i.e. the
+ * per-element sum_ab D_a^T (G_ab o D_b u_e) before direct-stiffness summation
+ * (Sec. 1, a_ij; the tensor-product form of the SEM operator).
+ * precision SEM_FP64: u double[n_global], wL double[E (N+1)^3], FP64 factors.
+ * precision SEM_MIXED: u float[n_global], wL float[E (N+1)^3], BF16 factors
+ * (only on a SEM_MIXED context). Device pointers. */
+sem_status sem_apply_local(sem_ctx *ctx, int32_t precision, const void *u, void *wL, void *stream);
+
+/* z = M^{-1} r: one V-cycle (eq. recursive-v-cycle-err-prop, or eq.
+ * recursive-ftc-err when post_order = 0) in the context's precision.
+ * r, z: device, n_global doubles. */
+sem_status sem_vcycle(sem_ctx *ctx, const double *r, double *z, void *stream);
+
+/* Solve A u = b by PCG/FCG preconditioned with one V-cycle per iteration,
+ * until ||r_k||_2 <= rtol ||b||_2 (recurrence residual) or maxit iterations.
+ * b: device, n_global doubles. u: device, n_global doubles; on entry the
+ * initial guess x0 (zero vector for the paper's setting), on exit the
+ * iterate. iters, relres: host outputs (may be NULL). history: host array
+ * of maxit+1 doubles receiving ||r_k||_2, k = 0..iters (may be NULL).
+ * Returns SEM_ENOTCONV when maxit is reached, SEM_EBREAKDOWN when r.z <= 0
+ * or p.Ap <= 0, SEM_ENAN on a non-finite residual. */
+sem_status sem_solve(sem_ctx *ctx, const double *b, double *u, double rtol, int32_t maxit,
+                     int32_t *iters, double *relres, double *history, void *stream);
+
+/* Coordinates of the global unknowns: xyz device, 3*n_global doubles, [g][3]. */
+sem_status sem_coords(sem_ctx *ctx, double *xyz, void *stream);
+
+/* b = B f with B the assembled diagonal mass matrix (GLL quadrature of
+ * w_i w_j w_k |J|). f, b: device, n_global doubles (may alias). */
+sem_status sem_mass_apply(sem_ctx *ctx, const double *f, double *b, void *stream);
+
+/* Copy the finest-level FP64 geometric factors out of / into the context.
+ * G: device, E*6*(N+1)^3 doubles, layout [e][c][k][j][i]. Setting factors
+ * changes A for apply_A, solve and the adjoint contraction; the
+ * preconditioner (diagonals, lambda_max, coarse levels) keeps its setup data. */
+sem_status sem_get_factors(sem_ctx *ctx, double *G, void *stream);
+sem_status sem_set_factors(sem_ctx *ctx, const double *G, void *stream);
+
+/* Adjoint contraction for L(u) with A(G) u = B f and adjoint lambda = A^{-1} dL/du:
+ * dG[e][aa][node] = -(D_a lambda_L)(D_a u_L),
+ * dG[e][ab][node] = -[(D_a lambda_L)(D_b u_L) + (D_b lambda_L)(D_a u_L)] (a != b),
+ * df = B lambda. lambda, u, df: device, n_global doubles; dG: device,
+ * E*6*(N+1)^3 doubles. Either output may be NULL. */
+sem_status sem_adjoint_contract(sem_ctx *ctx, const double *lambda, const double *u, double *dG,
+                                double *df, void *stream);
+
+/* Operator applications counted per level since setup or the last reset
+ * (the finest level includes the Krylov applies). counts: host, num_levels. */
+sem_status sem_apply_counts(const sem_ctx *ctx, int64_t *counts, int32_t num_levels);
+sem_status sem_reset_counts(sem_ctx *ctx);
+
+/* Host copies of setup arrays, for inspection and testing. `what` is one of
+ * "gll_nodes", "gll_weights", "deriv", "interp" (to level+1), "factors",
+ * "diag", "mass", "coords", "lambda_max", "coarse_matrix" (dense, small
+ * problems only). Returns SEM_EINVAL if `n` does not equal the array size,
+ * with the size written to *needed when it is not NULL. */
+sem_status sem_host_array(const sem_ctx *ctx, const char *what, int32_t level, double *out,
+                          int64_t n, int64_t *needed);
+
+/* beta_i^{(k)}, i = 1..k, of Table beta_coef into out[0..k-1]; k in 1..16. */
+sem_status sem_beta_table(int32_t k, double *out);
+
+sem_status sem_destroy(sem_ctx *ctx);
+const char *sem_last_error(const sem_ctx *ctx);
+const char *sem_global_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEMCHEB_H */

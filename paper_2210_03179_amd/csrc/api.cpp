@@ -1,0 +1,981 @@
+// C ABI of semcheb: setup of the p-multigrid hierarchy, the V-cycle driver, the
+// Krylov solver and the auxiliary entry points. All arithmetic of the solve runs
+// in the HIP kernels of kernels.hip; this file orchestrates launches on the
+// caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+using namespace semcheb;
+
+namespace {
+
+thread_local std::string g_err;
+
+#define HIPCHK(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      (ctx)->err = std::string(#call) + " failed: " + hipGetErrorString(e_);           \
+      return SEM_EHIP;                                                                 \
+    }                                                                                  \
+  } while (0)
+
+#define TRY(expr)                    \
+  do {                               \
+    sem_status st_ = (expr);         \
+    if (st_ != SEM_OK) return st_;   \
+  } while (0)
+
+template <typename T>
+sem_status dalloc(sem_ctx *c, T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return SEM_OK;
+  hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    c->err = "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed: " + hipGetErrorString(e);
+    *p = nullptr;
+    return SEM_ENOMEM;
+  }
+  c->allocations.push_back((void *)*p);
+  return SEM_OK;
+}
+
+template <typename T>
+sem_status upload(sem_ctx *c, T **p, const T *src, size_t count, hipStream_t s) {
+  TRY(dalloc(c, p, count));
+  if (count) HIPCHK(c, hipMemcpyAsync(*p, src, count * sizeof(T), hipMemcpyHostToDevice, s));
+  return SEM_OK;
+}
+
+sem_status upload_csr(sem_ctx *c, DevCsr &d, const Csr &h, bool with32, hipStream_t s) {
+  d.nrows = h.nrows;
+  TRY(upload(c, &d.rowptr, h.rowptr.data(), h.rowptr.size(), s));
+  TRY(upload(c, &d.col, h.col.data(), h.col.size(), s));
+  TRY(upload(c, &d.val64, h.val.data(), h.val.size(), s));
+  if (with32) {
+    std::vector<float> v(h.val.begin(), h.val.end());
+    TRY(upload(c, &d.val32, v.data(), v.size(), s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  return SEM_OK;
+}
+
+uint16_t to_bf16(double v) {
+  // round to nearest even on the float representation
+  float f = (float)v;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014) as a counter-based generator: value i of
+// stream `seed` is the mix of seed + (i+1) * golden gamma.
+double splitmix_uniform(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return ((z >> 11) * 0x1.0p-53) * 2.0 - 1.0;
+}
+
+bool valid_kind(int k) { return k == SEM_CHEB1 || k == SEM_CHEB1_OPT || k == SEM_CHEB4 || k == SEM_CHEB4_OPT; }
+
+sem_status validate_common(const sem_options *o, std::string &err) {
+  if (!valid_kind(o->smoother)) { err = "unknown smoother kind"; return SEM_EINVAL; }
+  if (o->pre_order < 0 || o->pre_order > 32 || o->post_order < 0 || o->post_order > 32) {
+    err = "smoothing orders must lie in 0..32";
+    return SEM_EINVAL;
+  }
+  if (o->pre_order + o->post_order < 1) { err = "pre_order + post_order must be >= 1"; return SEM_EINVAL; }
+  if (o->smoother == SEM_CHEB4_OPT && (o->pre_order > 16 || o->post_order > 16)) {
+    err = "optimised 4th-kind coefficients are tabulated for orders <= 16";
+    return SEM_EINVAL;
+  }
+  if (o->precision != SEM_FP64 && o->precision != SEM_MIXED) { err = "unknown precision"; return SEM_EINVAL; }
+  if (o->krylov != SEM_PCG && o->krylov != SEM_FCG) { err = "unknown Krylov method"; return SEM_EINVAL; }
+  if (o->num_lambda_max < 0 || o->num_lambda_max > SEM_MAX_LEVELS) { err = "bad num_lambda_max"; return SEM_EINVAL; }
+  if (o->lambda_scale < 0) { err = "lambda_scale must be >= 0"; return SEM_EINVAL; }
+  return SEM_OK;
+}
+
+// ------------------------------------------------------------------ typed accessors
+template <typename T> struct V;
+template <> struct V<double> {
+  static double *&b(Level &L) { return L.b64; }
+  static double *&x(Level &L) { return L.x64; }
+  static double *&r(Level &L) { return L.r64; }
+  static double *&d(Level &L) { return L.d64; }
+  static double *&w(Level &L) { return L.w64; }
+  static const double *inv(const Level &L) { return L.invdiag64; }
+  static const double *J(const Level &L) { return L.J64; }
+  static const double *val(const DevCsr &A) { return A.val64; }
+};
+template <> struct V<float> {
+  static float *&b(Level &L) { return L.b32; }
+  static float *&x(Level &L) { return L.x32; }
+  static float *&r(Level &L) { return L.r32; }
+  static float *&d(Level &L) { return L.d32; }
+  static float *&w(Level &L) { return L.w32; }
+  static const float *inv(const Level &L) { return L.invdiag32; }
+  static const float *J(const Level &L) { return L.J32; }
+  static const float *val(const DevCsr &A) { return A.val32; }
+};
+
+// operator on level L: SEM -> element-local result in w (length E (N+1)^3),
+// FD -> global result in w.
+template <typename T>
+void apply_level(Level &L, const T *u, T *w, hipStream_t s) {
+  L.applies++;
+  if (L.type == LVL_SEM) launch_ax(L, u, w, s);
+  else launch_csr(L.A, V<T>::val(L.A), u, (const T *)nullptr, w, 0, s);
+}
+
+// Order-k Chebyshev smoothing of A x = b on level L (Algorithms 1 and 2).
+// zero_guess: x starts at 0 (k-1 applies); otherwise from the current x (k applies).
+template <typename T>
+void smooth(const sem_ctx *c, Level &L, int k, bool zero_guess, hipStream_t s) {
+  if (k <= 0) return;
+  T *b = V<T>::b(L), *x = V<T>::x(L), *r = V<T>::r(L), *d = V<T>::d(L), *w = V<T>::w(L);
+  const T *inv = V<T>::inv(L);
+  const double lmax = L.lmax;
+  const int kind = c->opt.smoother;
+  if (kind == SEM_CHEB4 || kind == SEM_CHEB4_OPT) {
+    const double *beta = kind == SEM_CHEB4_OPT ? beta_row(k) : nullptr;
+    auto B = [&](int i) { return beta ? beta[i - 1] : 1.0; };  // beta_i, 1-based
+    const double c0 = (4.0 / 3.0) * (1.0 / lmax);
+    if (zero_guess) {
+      launch_cheb<T>(L, nullptr, b, nullptr, nullptr, d, x, inv, 0.0, c0, B(1),
+                     CHEB_R_FROM_B | CHEB_D_INIT | CHEB_X_INIT, 4, s);
+    } else {
+      apply_level<T>(L, x, w, s);
+      launch_cheb<T>(L, w, b, nullptr, r, d, x, inv, 0.0, c0, B(1),
+                     CHEB_R_FROM_B | CHEB_SUB_AD | CHEB_D_INIT | CHEB_WRITE_R, 4, s);
+    }
+    for (int i = 1; i < k; ++i) {
+      apply_level<T>(L, d, w, s);
+      const bool from_b = zero_guess && i == 1;
+      const double a = (2.0 * i - 1.0) / (2.0 * i + 3.0);
+      const double bc = ((8.0 * i + 4.0) / (2.0 * i + 3.0)) * (1.0 / lmax);
+      launch_cheb<T>(L, w, b, r, r, d, x, inv, a, bc, B(i + 1),
+                     CHEB_SUB_AD | CHEB_WRITE_R | (from_b ? CHEB_R_FROM_B : 0), 4, s);
+    }
+  } else {
+    const double frac = kind == SEM_CHEB1 ? 0.1 : 1.69 / (std::pow((double)k, 1.68) + 2.11 * k + 1.98);
+    const double lmin = frac * lmax;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    if (zero_guess) {
+      launch_cheb<T>(L, nullptr, b, nullptr, r, d, x, inv, 0.0, 1.0 / theta, 1.0,
+                     CHEB_R_FROM_B | CHEB_S_ON_R | CHEB_D_INIT | CHEB_X_INIT | CHEB_WRITE_R, 1, s);
+    } else {
+      apply_level<T>(L, x, w, s);
+      launch_cheb<T>(L, w, b, nullptr, r, d, x, inv, 0.0, 1.0 / theta, 1.0,
+                     CHEB_R_FROM_B | CHEB_S_ON_R | CHEB_SUB_AD | CHEB_D_INIT | CHEB_WRITE_R, 1, s);
+    }
+    for (int i = 1; i < k; ++i) {
+      apply_level<T>(L, d, w, s);
+      const double rho_new = 1.0 / (2.0 * sigma - rho);
+      launch_cheb<T>(L, w, b, r, r, d, x, inv, rho_new * rho, 2.0 * rho_new / delta, 1.0,
+                     CHEB_SUB_AD | CHEB_WRITE_R, 1, s);
+      rho = rho_new;
+    }
+  }
+}
+
+void coarse_solve64(sem_ctx *c, const double *b, double *x, hipStream_t s) {
+  CoarseSolver &C = c->coarse;
+  if (C.n == 0) return;
+  if (C.dense) {
+    launch_gemv(C.n, C.n, C.Minv, b, nullptr, x, 0, s);
+    return;
+  }
+  const int nb = (int)C.start.size() - 1;
+  double *y = C.y, *t = C.t;
+  // forward: y_0 = b_0, y_b = b_b - L_b y_{b-1}
+  hipMemcpyAsync(y, b, (C.start[1] - C.start[0]) * sizeof(double), hipMemcpyDeviceToDevice, s);
+  for (int q = 1; q < nb; ++q) {
+    const int64_t P = C.start[q + 1] - C.start[q], Pp = C.start[q] - C.start[q - 1];
+    launch_gemv(P, Pp, C.Lb[q], y + C.start[q - 1], b + C.start[q], y + C.start[q], 1, s);
+  }
+  // backward: x_last = M y_last, x_b = M_b (y_b - U_b x_{b+1})
+  {
+    const int q = nb - 1;
+    const int64_t P = C.start[q + 1] - C.start[q];
+    launch_gemv(P, P, C.Mb[q], y + C.start[q], nullptr, x + C.start[q], 0, s);
+  }
+  for (int q = nb - 2; q >= 0; --q) {
+    const int64_t P = C.start[q + 1] - C.start[q];
+    launch_csr<double>(C.Ub[q], C.Ub[q].val64, x + C.start[q + 1], y + C.start[q], t + C.start[q], 1, s);
+    launch_gemv(P, P, C.Mb[q], t + C.start[q], nullptr, x + C.start[q], 0, s);
+  }
+}
+
+template <typename T>
+void coarse_solve(sem_ctx *c, Level &L, hipStream_t s);
+template <>
+void coarse_solve<double>(sem_ctx *c, Level &L, hipStream_t s) {
+  coarse_solve64(c, L.b64, L.x64, s);
+}
+template <>
+void coarse_solve<float>(sem_ctx *c, Level &L, hipStream_t s) {
+  CoarseSolver &C = c->coarse;
+  if (C.n == 0) return;
+  launch_convert(C.n, L.b32, C.b, s);
+  coarse_solve64(c, C.b, C.x, s);
+  launch_convert(C.n, C.x, L.x32, s);
+}
+
+// One V-cycle on level j: x_j = V_j(b_j) (eq. recursive-v-cycle-err-prop; one-sided
+// when post_order = 0, eq. recursive-ftc-err).
+template <typename T>
+void vcycle(sem_ctx *c, int j, hipStream_t s) {
+  Level &L = c->levels[j];
+  if (j == (int)c->levels.size() - 1) {
+    coarse_solve<T>(c, L, s);
+    return;
+  }
+  const int pre = c->opt.pre_order, post = c->opt.post_order;
+  T *b = V<T>::b(L), *x = V<T>::x(L), *r = V<T>::r(L), *w = V<T>::w(L);
+  if (pre > 0) {
+    smooth<T>(c, L, pre, true, s);
+    apply_level<T>(L, x, w, s);
+    launch_resid_weight<T>(L, w, b, r, s);
+  } else {
+    hipMemsetAsync(x, 0, L.n * sizeof(T), s);
+    launch_resid_weight<T>(L, (const T *)nullptr, b, r, s);
+  }
+  Level &C = c->levels[j + 1];
+  if (L.type == LVL_SEM) {
+    launch_restrict<T>(L, C, r, V<T>::J(L), V<T>::w(C), s);
+    launch_dss<T>(C, V<T>::w(C), V<T>::b(C), s);
+  } else {
+    launch_csr<T>(L.R, V<T>::val(L.R), r, (const T *)nullptr, V<T>::b(C), 0, s);
+  }
+  vcycle<T>(c, j + 1, s);
+  if (L.type == LVL_SEM) launch_prolong<T>(L, C, V<T>::x(C), V<T>::J(L), x, s);
+  else launch_csr<T>(L.P, V<T>::val(L.P), V<T>::x(C), (const T *)nullptr, x, 2, s);
+  if (post > 0) smooth<T>(c, L, post, false, s);
+}
+
+// z = M^{-1} r through the context's precision.
+void vcycle_top(sem_ctx *c, const double *r, double *z, hipStream_t s) {
+  Level &L0 = c->levels[0];
+  if (c->opt.precision == SEM_MIXED) {
+    launch_convert(L0.n, r, L0.b32, s);
+    vcycle<float>(c, 0, s);
+    launch_convert(L0.n, L0.x32, z, s);
+  } else {
+    double *sb = L0.b64, *sx = L0.x64;
+    L0.b64 = const_cast<double *>(r);
+    L0.x64 = z;
+    vcycle<double>(c, 0, s);
+    L0.b64 = sb;
+    L0.x64 = sx;
+  }
+}
+
+// w = A u on the finest level with a reduction partial of p . w when p is given.
+void fine_apply(sem_ctx *c, const double *u, double *w, const double *p, hipStream_t s) {
+  Level &L0 = c->levels[0];
+  L0.applies++;
+  if (L0.type == LVL_SEM) {
+    launch_ax(L0, u, L0.w64, s);
+    if (p) launch_dss_dot(L0, L0.w64, w, p, c->partials, kReduceBlocks, s);
+    else launch_dss<double>(L0, L0.w64, w, s);
+  } else {
+    launch_csr<double>(L0.A, L0.A.val64, u, nullptr, w, 0, s);
+    if (p) launch_dots<double>(L0.n, 1, p, w, nullptr, nullptr, nullptr, nullptr, c->partials, kReduceBlocks, s);
+  }
+}
+
+sem_status read_scalars(sem_ctx *c, hipStream_t s) {
+  HIPCHK(c, hipMemcpyAsync(c->pinned, c->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return SEM_OK;
+}
+
+// Largest eigenvalue of S A on level j by Lanczos on S^{1/2} A S^{1/2} (FP64).
+sem_status lanczos(sem_ctx *c, int j, double &out, hipStream_t s) {
+  Level &L = c->levels[j];
+  const int64_t n = L.n;
+  double *q = c->kr, *qp = c->kr2, *wv = c->kz, *v = c->kw, *sq = c->kp;
+  std::vector<double> h(n);
+  {
+    std::vector<double> inv(n);
+    HIPCHK(c, hipMemcpy(inv.data(), L.invdiag64, n * sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; ++i) h[i] = std::sqrt(inv[i]);
+    HIPCHK(c, hipMemcpy(sq, h.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    double nrm = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      h[i] = splitmix_uniform(0x5EC7EB5ull + j, (uint64_t)i);
+      nrm += h[i] * h[i];
+    }
+    nrm = std::sqrt(nrm);
+    for (int64_t i = 0; i < n; ++i) h[i] /= nrm;
+    HIPCHK(c, hipMemcpy(q, h.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  }
+  std::vector<double> al, be;
+  double prev = 0.0, top = 0.0, beta_prev = 0.0;
+  int stable = 0;
+  for (int it = 0; it < 300; ++it) {
+    launch_mul(n, sq, q, v, s);
+    if (L.type == LVL_SEM) {
+      launch_ax(L, v, L.w64, s);
+      launch_dss<double>(L, L.w64, wv, s);
+    } else {
+      launch_csr<double>(L.A, L.A.val64, v, nullptr, wv, 0, s);
+    }
+    launch_mul(n, sq, wv, wv, s);
+    launch_dots<double>(n, 1, q, wv, nullptr, nullptr, nullptr, nullptr, c->partials, kReduceBlocks, s);
+    launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_TMP, FIN_NONE, s);
+    TRY(read_scalars(c, s));
+    const double a = c->pinned[S_TMP];
+    launch_axpby(n, 1.0, wv, -a, q, wv, s);
+    if (it > 0) launch_axpby(n, 1.0, wv, -beta_prev, qp, wv, s);
+    launch_dots<double>(n, 1, wv, wv, nullptr, nullptr, nullptr, nullptr, c->partials, kReduceBlocks, s);
+    launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_TMP, FIN_NONE, s);
+    TRY(read_scalars(c, s));
+    const double bn = std::sqrt(c->pinned[S_TMP]);
+    al.push_back(a);
+    top = tridiag_max_eig(al, be);
+    if (!std::isfinite(top)) { c->err = "Lanczos produced a non-finite value"; return SEM_ENAN; }
+    if (it > 0 && std::fabs(top - prev) <= 1e-10 * std::fabs(top)) {
+      if (++stable >= 3) break;
+    } else {
+      stable = 0;
+    }
+    prev = top;
+    if (!(bn > 1e-300)) break;
+    be.push_back(bn);
+    // q_prev <- q, q <- w / beta
+    launch_axpby(n, 1.0 / bn, wv, 0.0, nullptr, qp, s);
+    std::swap(q, qp);
+    beta_prev = bn;
+  }
+  out = top;
+  return SEM_OK;
+}
+
+sem_status alloc_level_vectors(sem_ctx *c, Level &L, bool mixed, bool coarse) {
+  const int64_t wlen = L.type == LVL_SEM ? L.L : L.n;
+  if (!mixed) {
+    TRY(dalloc(c, &L.b64, L.n));
+    TRY(dalloc(c, &L.x64, L.n));
+    if (!coarse) {
+      TRY(dalloc(c, &L.r64, L.n));
+      TRY(dalloc(c, &L.d64, L.n));
+    }
+    TRY(dalloc(c, &L.w64, wlen));
+  } else {
+    TRY(dalloc(c, &L.b32, L.n));
+    TRY(dalloc(c, &L.x32, L.n));
+    if (!coarse) {
+      TRY(dalloc(c, &L.r32, L.n));
+      TRY(dalloc(c, &L.d32, L.n));
+    }
+    TRY(dalloc(c, &L.w32, wlen));
+  }
+  return SEM_OK;
+}
+
+sem_status alloc_krylov(sem_ctx *c, int64_t n) {
+  TRY(dalloc(c, &c->kr, n));
+  TRY(dalloc(c, &c->kr2, n));
+  TRY(dalloc(c, &c->kz, n));
+  TRY(dalloc(c, &c->kp, n));
+  TRY(dalloc(c, &c->kw, n));
+  TRY(dalloc(c, &c->scal, S_COUNT));
+  TRY(dalloc(c, &c->partials, (size_t)kReduceBlocks * 3));
+  HIPCHK(c, hipHostMalloc((void **)&c->pinned, S_COUNT * sizeof(double), hipHostMallocDefault));
+  return SEM_OK;
+}
+
+sem_status estimate_lambdas(sem_ctx *c, hipStream_t s) {
+  const int ns = (int)c->levels.size() - 1;  // smoothed levels
+  for (int j = 0; j < ns; ++j) {
+    if (c->opt.num_lambda_max > 0) {
+      if (j >= c->opt.num_lambda_max || !(c->opt.lambda_max[j] > 0)) {
+        c->err = "lambda_max must be given (positive) for every smoothed level";
+        return SEM_EINVAL;
+      }
+      c->levels[j].lmax = c->opt.lambda_max[j];
+    } else if (!c->host_only) {
+      double lm = 0;
+      TRY(lanczos(c, j, lm, s));
+      const double sc = c->opt.lambda_scale > 0 ? c->opt.lambda_scale : 1.0;
+      c->levels[j].lmax = lm * sc;
+    }
+  }
+  return SEM_OK;
+}
+
+sem_status init_device(sem_ctx *c, hipStream_t s) {
+  if (c->host_only) return SEM_OK;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= c->device) {
+    c->err = "no HIP device " + std::to_string(c->device) + " available";
+    return SEM_ENODEV;
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  (void)s;
+  return SEM_OK;
+}
+
+sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipStream_t s, sem_ctx *c) {
+  c->kind = LVL_SEM;
+  c->opt = *opt;
+  c->host_only = opt->device < 0;
+  c->device = opt->device < 0 ? 0 : opt->device;
+  TRY(validate_common(opt, c->err));
+  if (!mesh || !mesh->vertex_xyz || mesh->nex < 2 || mesh->ney < 2 || mesh->nez < 2) {
+    c->err = "mesh needs at least 2 elements per direction and vertex coordinates";
+    return SEM_EINVAL;
+  }
+  if (opt->N < 1 || opt->N > 12) { c->err = "order N must lie in 1..12"; return SEM_EINVAL; }
+  std::vector<int> orders;
+  if (opt->num_levels == 0) {
+    orders.push_back(opt->N);
+    if (opt->N / 2 >= 1 && opt->N / 2 < opt->N) orders.push_back(opt->N / 2);
+    if (orders.back() > 1) orders.push_back(1);
+  } else {
+    if (opt->num_levels < 1 || opt->num_levels > SEM_MAX_LEVELS) { c->err = "bad num_levels"; return SEM_EINVAL; }
+    for (int j = 0; j < opt->num_levels; ++j) orders.push_back(opt->orders[j]);
+    if (orders[0] != opt->N) { c->err = "orders[0] must equal N"; return SEM_EINVAL; }
+    for (size_t j = 1; j < orders.size(); ++j)
+      if (orders[j] >= orders[j - 1] || orders[j] < 1) { c->err = "orders must decrease"; return SEM_EINVAL; }
+    if (orders.back() != 1) { c->err = "the coarsest order must be 1"; return SEM_EINVAL; }
+  }
+  TRY(init_device(c, s));
+  const int nl = (int)orders.size();
+  c->host_levels.resize(nl);
+  for (int j = 0; j < nl; ++j) TRY(build_box_level(*mesh, orders[j], c->host_levels[j], c->err));
+  c->host_interp.resize(nl);
+  for (int j = 0; j + 1 < nl; ++j) c->host_interp[j] = make_interp(c->host_levels[j].gll, c->host_levels[j + 1].gll);
+  // coarse operator: assembled order-1 matrix, block tridiagonal in z-planes
+  const BoxLevelHost &H = c->host_levels.back();
+  Csr Ac = assemble_q1(H);
+  const int64_t plane = (int64_t)H.nx * H.ny;
+  int gp = opt->coarse_planes;
+  if (gp <= 0) gp = (H.n <= 4096) ? H.nz : 1;
+  gp = std::min(gp, H.nz);
+  std::vector<int64_t> start;
+  for (int k = 0; k < H.nz; k += gp) start.push_back((int64_t)k * plane);
+  start.push_back(H.n);
+  BlockTri bt;
+  if (!block_tridiag_factor(Ac, start, bt, c->err)) return SEM_EINVAL;
+  if (H.n <= 4096) {
+    c->coarse.host_dense.assign((size_t)H.n * H.n, 0.0);
+    for (int64_t r = 0; r < H.n; ++r)
+      for (int64_t p = Ac.rowptr[r]; p < Ac.rowptr[r + 1]; ++p) c->coarse.host_dense[r * H.n + Ac.col[p]] = Ac.val[p];
+  }
+  c->coarse.n = H.n;
+  c->coarse.dense = (start.size() == 2);
+  c->coarse.start = start;
+
+  // levels
+  c->levels.resize(nl);
+  for (int j = 0; j < nl; ++j) {
+    const BoxLevelHost &h = c->host_levels[j];
+    Level &L = c->levels[j];
+    L.type = LVL_SEM;
+    L.N = h.N;
+    L.n1 = h.n1;
+    L.nex = h.nex; L.ney = h.ney; L.nez = h.nez;
+    L.nx = h.nx; L.ny = h.ny; L.nz = h.nz;
+    L.E = h.E; L.L = h.L; L.n = h.n;
+  }
+  if (c->host_only) {
+    if (opt->num_lambda_max > 0) TRY(estimate_lambdas(c, s));
+    return SEM_OK;
+  }
+  const bool mixed = opt->precision == SEM_MIXED;
+  for (int j = 0; j < nl; ++j) {
+    const BoxLevelHost &h = c->host_levels[j];
+    Level &L = c->levels[j];
+    const bool coarse = j == nl - 1;
+    TRY(upload(c, &L.G64, h.G.data(), h.G.size(), s));
+    TRY(upload(c, &L.D64, h.gll.D.data(), h.gll.D.size(), s));
+    std::vector<float> D32(h.gll.D.begin(), h.gll.D.end());
+    TRY(upload(c, &L.D32, D32.data(), D32.size(), s));
+    std::vector<double> inv(h.n);
+    for (int64_t i = 0; i < h.n; ++i) inv[i] = 1.0 / h.diag[i];
+    TRY(upload(c, &L.invdiag64, inv.data(), inv.size(), s));
+    std::vector<float> inv32(inv.begin(), inv.end());
+    TRY(upload(c, &L.invdiag32, inv32.data(), inv32.size(), s));
+    if (mixed && !coarse) {
+      std::vector<uint16_t> gb(h.G.size());
+      for (size_t q = 0; q < gb.size(); ++q) gb[q] = to_bf16(h.G[q]);
+      TRY(upload(c, &L.Gbf, gb.data(), gb.size(), s));
+      HIPCHK(c, hipStreamSynchronize(s));
+    }
+    if (!coarse) {
+      const std::vector<double> &J = c->host_interp[j];
+      TRY(upload(c, &L.J64, J.data(), J.size(), s));
+      std::vector<float> J32(J.begin(), J.end());
+      TRY(upload(c, &L.J32, J32.data(), J32.size(), s));
+    }
+    if (j == 0) {
+      TRY(upload(c, &L.mass, h.mass.data(), h.mass.size(), s));
+      TRY(upload(c, &L.coords, h.coords.data(), h.coords.size(), s));
+      // FP64 work vectors of the finest level are always needed (apply_A, Lanczos)
+      if (mixed) {
+        TRY(dalloc(c, &L.w64, L.L));
+      }
+    }
+    TRY(alloc_level_vectors(c, L, mixed, coarse));
+    if (mixed && j > 0 && !coarse) {
+      // FP64 work vectors for Lanczos on coarser levels
+      TRY(dalloc(c, &L.w64, L.L));
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  // coarse factors
+  CoarseSolver &C = c->coarse;
+  if (C.n > 0) {
+    TRY(dalloc(c, &C.b, C.n));
+    TRY(dalloc(c, &C.x, C.n));
+    TRY(dalloc(c, &C.y, C.n));
+    TRY(dalloc(c, &C.t, C.n));
+    if (C.dense) {
+      TRY(upload(c, &C.Minv, bt.Minv[0].data(), bt.Minv[0].size(), s));
+    } else {
+      const int nb = (int)start.size() - 1;
+      C.Mb.assign(nb, nullptr);
+      C.Lb.assign(nb, nullptr);
+      C.Ub.assign(nb, DevCsr{});
+      for (int q = 0; q < nb; ++q) {
+        TRY(upload(c, &C.Mb[q], bt.Minv[q].data(), bt.Minv[q].size(), s));
+        if (q > 0) TRY(upload(c, &C.Lb[q], bt.Lmat[q].data(), bt.Lmat[q].size(), s));
+        if (q + 1 < nb) TRY(upload_csr(c, C.Ub[q], bt.Up[q], false, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+      }
+    }
+  }
+  TRY(alloc_krylov(c, c->levels[0].n));
+  HIPCHK(c, hipStreamSynchronize(s));
+  TRY(estimate_lambdas(c, s));
+  for (auto &L : c->levels) L.applies = 0;
+  return SEM_OK;
+}
+
+Csr transpose(const Csr &A) {
+  Csr T;
+  T.nrows = A.ncols;
+  T.ncols = A.nrows;
+  T.rowptr.assign(T.nrows + 1, 0);
+  for (int32_t cidx : A.col) T.rowptr[cidx + 1]++;
+  for (int64_t r = 0; r < T.nrows; ++r) T.rowptr[r + 1] += T.rowptr[r];
+  T.col.resize(A.col.size());
+  T.val.resize(A.val.size());
+  std::vector<int64_t> pos(T.rowptr.begin(), T.rowptr.end() - 1);
+  for (int64_t r = 0; r < A.nrows; ++r)
+    for (int64_t p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p) {
+      const int64_t q = pos[A.col[p]]++;
+      T.col[q] = (int32_t)r;
+      T.val[q] = A.val[p];
+    }
+  return T;
+}
+
+sem_status setup_fd_impl(int n, double Lx, double Ly, int factor, int coarsest_n, const sem_options *opt,
+                         hipStream_t s, sem_ctx *c) {
+  c->kind = LVL_FD;
+  c->opt = *opt;
+  c->host_only = opt->device < 0;
+  c->device = opt->device < 0 ? 0 : opt->device;
+  TRY(validate_common(opt, c->err));
+  if (opt->precision != SEM_FP64) { c->err = "the FD problem runs in FP64"; return SEM_EINVAL; }
+  if (n < 2 || n > 8192 || !(Lx > 0) || !(Ly > 0) || (factor != 2 && factor != 4 && factor != 8) ||
+      coarsest_n < 2) {
+    c->err = "invalid FD problem parameters";
+    return SEM_EINVAL;
+  }
+  TRY(init_device(c, s));
+  build_fd_hierarchy(n, Lx, Ly, factor, coarsest_n, c->fd_host);
+  const int nl = (int)c->fd_host.size();
+  c->levels.resize(nl);
+  for (int j = 0; j < nl; ++j) {
+    Level &L = c->levels[j];
+    L.type = LVL_FD;
+    L.n = c->fd_host[j].m;
+    L.N = c->fd_host[j].n;
+  }
+  std::vector<double> Ac((size_t)c->fd_host.back().m * c->fd_host.back().m, 0.0);
+  {
+    const Csr &A = c->fd_host.back().A;
+    for (int64_t r = 0; r < A.nrows; ++r)
+      for (int64_t p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p) Ac[r * A.ncols + A.col[p]] = A.val[p];
+  }
+  c->coarse.host_dense = Ac;
+  c->coarse.n = c->fd_host.back().m;
+  c->coarse.dense = true;
+  if (!spd_inverse(Ac, c->coarse.n)) { c->err = "coarse FD matrix is not SPD"; return SEM_EINVAL; }
+  if (c->host_only) {
+    if (opt->num_lambda_max > 0) TRY(estimate_lambdas(c, s));
+    return SEM_OK;
+  }
+  for (int j = 0; j < nl; ++j) {
+    Level &L = c->levels[j];
+    const FdLevelHost &h = c->fd_host[j];
+    TRY(upload_csr(c, L.A, h.A, false, s));
+    std::vector<double> inv(h.m);
+    for (int64_t r = 0; r < h.A.nrows; ++r)
+      for (int64_t p = h.A.rowptr[r]; p < h.A.rowptr[r + 1]; ++p)
+        if (h.A.col[p] == r) inv[r] = 1.0 / h.A.val[p];
+    TRY(upload(c, &L.invdiag64, inv.data(), inv.size(), s));
+    if (j + 1 < nl) {
+      TRY(upload_csr(c, L.P, h.P, false, s));
+      Csr R = transpose(h.P);
+      TRY(upload_csr(c, L.R, R, false, s));
+    }
+    TRY(alloc_level_vectors(c, L, false, j == nl - 1));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  TRY(upload(c, &c->coarse.Minv, Ac.data(), Ac.size(), s));
+  TRY(alloc_krylov(c, c->levels[0].n));
+  HIPCHK(c, hipStreamSynchronize(s));
+  TRY(estimate_lambdas(c, s));
+  for (auto &L : c->levels) L.applies = 0;
+  return SEM_OK;
+}
+
+sem_status need_device(sem_ctx *c) {
+  if (!c) return SEM_EINVAL;
+  if (c->host_only) {
+    c->err = "host-only context: no device data";
+    return SEM_ENODEV;
+  }
+  if (hipSetDevice(c->device) != hipSuccess) {
+    c->err = "hipSetDevice failed";
+    return SEM_EHIP;
+  }
+  return SEM_OK;
+}
+
+void release(sem_ctx *c) {
+  if (!c) return;
+  if (!c->host_only) {
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    for (void *p : c->allocations) hipFree(p);
+    if (c->pinned) hipHostFree(c->pinned);
+  }
+  c->allocations.clear();
+  delete c;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+void sem_options_default(sem_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->N = 7;
+  o->num_levels = 0;
+  o->smoother = SEM_CHEB4_OPT;
+  o->pre_order = 4;
+  o->post_order = 0;
+  o->precision = SEM_FP64;
+  o->krylov = SEM_FCG;
+  o->num_lambda_max = 0;
+  o->lambda_scale = 1.0;
+  o->device = 0;
+  o->coarse_planes = 0;
+}
+
+sem_status sem_setup_box(const sem_box_mesh *mesh, const sem_options *opt, void *stream, sem_ctx **out) {
+  if (!out || !opt) { g_err = "null argument"; return SEM_EINVAL; }
+  *out = nullptr;
+  sem_ctx *c = new sem_ctx();
+  sem_status st = setup_box_impl(mesh, opt, (hipStream_t)stream, c);
+  if (st != SEM_OK) {
+    g_err = c->err;
+    release(c);
+    return st;
+  }
+  *out = c;
+  return SEM_OK;
+}
+
+sem_status sem_setup_fd2d(int32_t n, double Lx, double Ly, int32_t factor, int32_t coarsest_n,
+                          const sem_options *opt, void *stream, sem_ctx **out) {
+  if (!out || !opt) { g_err = "null argument"; return SEM_EINVAL; }
+  *out = nullptr;
+  sem_ctx *c = new sem_ctx();
+  sem_status st = setup_fd_impl(n, Lx, Ly, factor, coarsest_n, opt, (hipStream_t)stream, c);
+  if (st != SEM_OK) {
+    g_err = c->err;
+    release(c);
+    return st;
+  }
+  *out = c;
+  return SEM_OK;
+}
+
+sem_status sem_sizes(const sem_ctx *c, int64_t *n_global, int32_t *num_levels, int64_t *n_local) {
+  if (!c) return SEM_EINVAL;
+  if (n_global) *n_global = c->levels.empty() ? 0 : c->levels[0].n;
+  if (num_levels) *num_levels = (int32_t)c->levels.size();
+  if (n_local) *n_local = (c->kind == LVL_SEM && !c->levels.empty()) ? c->levels[0].L : 0;
+  return SEM_OK;
+}
+
+sem_status sem_level_info(const sem_ctx *c, int32_t j, int32_t *order, int64_t *n, double *lmax) {
+  if (!c || j < 0 || j >= (int32_t)c->levels.size()) return SEM_EINVAL;
+  if (order) *order = c->levels[j].N;
+  if (n) *n = c->levels[j].n;
+  if (lmax) *lmax = c->levels[j].lmax;
+  return SEM_OK;
+}
+
+sem_status sem_apply_A(sem_ctx *c, const double *u, double *w, void *stream) {
+  TRY(need_device(c));
+  if (!u || !w) { c->err = "null vector"; return SEM_EINVAL; }
+  fine_apply(c, u, w, nullptr, (hipStream_t)stream);
+  HIPCHK(c, hipGetLastError());
+  return SEM_OK;
+}
+
+sem_status sem_apply_local(sem_ctx *c, int32_t precision, const void *u, void *wL, void *stream) {
+  TRY(need_device(c));
+  if (c->kind != LVL_SEM || !u || !wL) { c->err = "element-local apply needs a SEM context and vectors"; return SEM_EINVAL; }
+  const Level &L0 = c->levels[0];
+  if (precision == SEM_FP64) {
+    launch_ax(L0, (const double *)u, (double *)wL, (hipStream_t)stream);
+  } else if (precision == SEM_MIXED && L0.Gbf) {
+    launch_ax(L0, (const float *)u, (float *)wL, (hipStream_t)stream);
+  } else {
+    c->err = "precision not available on this context";
+    return SEM_EINVAL;
+  }
+  HIPCHK(c, hipGetLastError());
+  return SEM_OK;
+}
+
+sem_status sem_vcycle(sem_ctx *c, const double *r, double *z, void *stream) {
+  TRY(need_device(c));
+  if (!r || !z || r == z) { c->err = "r and z must be distinct device vectors"; return SEM_EINVAL; }
+  vcycle_top(c, r, z, (hipStream_t)stream);
+  HIPCHK(c, hipGetLastError());
+  return SEM_OK;
+}
+
+sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_t maxit, int32_t *iters,
+                     double *relres, double *history, void *stream) {
+  TRY(need_device(c));
+  hipStream_t s = (hipStream_t)stream;
+  if (!b || !u || maxit < 0 || !(rtol >= 0)) { c->err = "invalid solve arguments"; return SEM_EINVAL; }
+  const int64_t n = c->levels[0].n;
+  const bool flexible = c->opt.krylov == SEM_FCG;
+  double *r = c->kr, *r2 = c->kr2, *z = c->kz, *p = c->kp, *w = c->kw;
+  if (iters) *iters = 0;
+  if (relres) *relres = 0.0;
+  // ||b||^2 and ||u0||^2
+  launch_dots<double>(n, 2, b, b, u, u, nullptr, nullptr, c->partials, kReduceBlocks, s);
+  launch_finalize(kReduceBlocks, 2, c->partials, c->scal, S_BB, FIN_NONE, s);
+  TRY(read_scalars(c, s));
+  const double bb = c->pinned[S_BB], uu = c->pinned[S_BB + 1];
+  if (!std::isfinite(bb) || !std::isfinite(uu)) { c->err = "non-finite right-hand side or initial guess"; return SEM_ENAN; }
+  const double bnorm = std::sqrt(bb);
+  if (uu == 0.0) {
+    HIPCHK(c, hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    fine_apply(c, u, w, nullptr, s);
+    launch_axpby(n, 1.0, b, -1.0, w, r, s);
+  }
+  launch_dots<double>(n, 1, r, r, nullptr, nullptr, nullptr, nullptr, c->partials, kReduceBlocks, s);
+  launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_RR, FIN_NONE, s);
+  TRY(read_scalars(c, s));
+  double rn = std::sqrt(c->pinned[S_RR]);
+  if (history) history[0] = rn;
+  if (bnorm == 0.0) {
+    if (uu != 0.0) HIPCHK(c, hipMemsetAsync(u, 0, n * sizeof(double), s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return SEM_OK;
+  }
+  if (rn <= rtol * bnorm) {
+    if (relres) *relres = rn / bnorm;
+    return SEM_OK;
+  }
+  vcycle_top(c, r, z, s);
+  launch_dots<double>(n, 1, r, z, nullptr, nullptr, nullptr, nullptr, c->partials, kReduceBlocks, s);
+  launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_RZ, FIN_INIT_RZ, s);
+  HIPCHK(c, hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  sem_status status = SEM_ENOTCONV;
+  int it = 0;
+  for (it = 1; it <= maxit; ++it) {
+    fine_apply(c, p, w, p, s);
+    launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_PW, FIN_NONE, s);
+    launch_update_xr(n, c->scal, u, p, r, w, r2, c->partials, kReduceBlocks, s);
+    launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_RR, FIN_NONE, s);
+    TRY(read_scalars(c, s));
+    const double rz = c->pinned[S_RZ], pw = c->pinned[S_PW], rr = c->pinned[S_RR];
+    if (!std::isfinite(rr) || !std::isfinite(pw) || !std::isfinite(rz)) {
+      c->err = "non-finite value in the Krylov iteration";
+      status = SEM_ENAN;
+      break;
+    }
+    if (!(rz > 0.0) || !(pw > 0.0)) {
+      c->err = "Krylov breakdown (r.z <= 0 or p.Ap <= 0)";
+      status = SEM_EBREAKDOWN;
+      break;
+    }
+    std::swap(r, r2);  // r: new residual, r2: previous residual
+    rn = std::sqrt(rr);
+    if (history) history[it] = rn;
+    if (iters) *iters = it;
+    if (relres) *relres = rn / bnorm;
+    if (rn <= rtol * bnorm) {
+      status = SEM_OK;
+      break;
+    }
+    if (it == maxit) break;
+    vcycle_top(c, r, z, s);
+    if (flexible) {
+      launch_dots<double>(n, 2, z, r, z, r2, nullptr, nullptr, c->partials, kReduceBlocks, s);
+      launch_finalize(kReduceBlocks, 2, c->partials, c->scal, S_ZR, FIN_BETA_FCG, s);
+    } else {
+      launch_dots<double>(n, 1, z, r, nullptr, nullptr, nullptr, nullptr, c->partials, kReduceBlocks, s);
+      launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_ZR, FIN_BETA_PCG, s);
+    }
+    launch_update_p(n, c->scal, z, p, s);
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  HIPCHK(c, hipGetLastError());
+  if (status == SEM_ENOTCONV) c->err = "maximum number of iterations reached";
+  return status;
+}
+
+sem_status sem_coords(sem_ctx *c, double *xyz, void *stream) {
+  TRY(need_device(c));
+  if (c->kind != LVL_SEM || !xyz) { c->err = "coordinates exist for SEM problems only"; return SEM_EINVAL; }
+  HIPCHK(c, hipMemcpyAsync(xyz, c->levels[0].coords, c->levels[0].n * 3 * sizeof(double),
+                           hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return SEM_OK;
+}
+
+sem_status sem_mass_apply(sem_ctx *c, const double *f, double *b, void *stream) {
+  TRY(need_device(c));
+  if (c->kind != LVL_SEM || !f || !b) { c->err = "mass exists for SEM problems only"; return SEM_EINVAL; }
+  launch_mul(c->levels[0].n, c->levels[0].mass, f, b, (hipStream_t)stream);
+  HIPCHK(c, hipGetLastError());
+  return SEM_OK;
+}
+
+sem_status sem_get_factors(sem_ctx *c, double *G, void *stream) {
+  TRY(need_device(c));
+  if (c->kind != LVL_SEM || !G) { c->err = "factors exist for SEM problems only"; return SEM_EINVAL; }
+  const Level &L = c->levels[0];
+  HIPCHK(c, hipMemcpyAsync(G, L.G64, L.L * 6 * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return SEM_OK;
+}
+
+sem_status sem_set_factors(sem_ctx *c, const double *G, void *stream) {
+  TRY(need_device(c));
+  if (c->kind != LVL_SEM || !G) { c->err = "factors exist for SEM problems only"; return SEM_EINVAL; }
+  const Level &L = c->levels[0];
+  HIPCHK(c, hipMemcpyAsync(L.G64, G, L.L * 6 * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return SEM_OK;
+}
+
+sem_status sem_adjoint_contract(sem_ctx *c, const double *lam, const double *u, double *dG, double *df,
+                                void *stream) {
+  TRY(need_device(c));
+  if (c->kind != LVL_SEM || !lam || (!u && dG)) { c->err = "invalid adjoint arguments"; return SEM_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  if (dG && !launch_adjoint(c->levels[0], lam, u, dG, s)) { c->err = "unsupported order"; return SEM_EINVAL; }
+  if (df) launch_mul(c->levels[0].n, c->levels[0].mass, lam, df, s);
+  HIPCHK(c, hipGetLastError());
+  return SEM_OK;
+}
+
+sem_status sem_apply_counts(const sem_ctx *c, int64_t *counts, int32_t nl) {
+  if (!c || !counts || nl < (int32_t)c->levels.size()) return SEM_EINVAL;
+  for (size_t j = 0; j < c->levels.size(); ++j) counts[j] = c->levels[j].applies;
+  return SEM_OK;
+}
+
+sem_status sem_reset_counts(sem_ctx *c) {
+  if (!c) return SEM_EINVAL;
+  for (auto &L : c->levels) L.applies = 0;
+  return SEM_OK;
+}
+
+sem_status sem_host_array(const sem_ctx *c, const char *what, int32_t j, double *out, int64_t n,
+                          int64_t *needed) {
+  if (!c || !what) return SEM_EINVAL;
+  std::vector<double> tmp;
+  const std::vector<double> *src = nullptr;
+  const std::string w(what);
+  const bool sem = c->kind == LVL_SEM;
+  if (w == "lambda_max") {
+    for (auto &L : c->levels) tmp.push_back(L.lmax);
+    src = &tmp;
+  } else if (w == "coarse_matrix") {
+    src = &c->coarse.host_dense;
+  } else if (sem) {
+    if (j < 0 || j >= (int32_t)c->host_levels.size()) return SEM_EINVAL;
+    const BoxLevelHost &h = c->host_levels[j];
+    if (w == "gll_nodes") src = &h.gll.x;
+    else if (w == "gll_weights") src = &h.gll.w;
+    else if (w == "deriv") src = &h.gll.D;
+    else if (w == "interp") { if (j + 1 >= (int32_t)c->host_levels.size()) return SEM_EINVAL; src = &c->host_interp[j]; }
+    else if (w == "factors") src = &h.G;
+    else if (w == "diag") src = &h.diag;
+    else if (w == "mass") src = &h.mass;
+    else if (w == "coords") src = &h.coords;
+  } else {
+    if (j < 0 || j >= (int32_t)c->fd_host.size()) return SEM_EINVAL;
+    if (w == "diag") {
+      const Csr &A = c->fd_host[j].A;
+      tmp.assign(A.nrows, 0.0);
+      for (int64_t r = 0; r < A.nrows; ++r)
+        for (int64_t p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p)
+          if (A.col[p] == r) tmp[r] = A.val[p];
+      src = &tmp;
+    } else if (w == "matrix") {
+      const Csr &A = c->fd_host[j].A;
+      tmp.assign((size_t)A.nrows * A.ncols, 0.0);
+      for (int64_t r = 0; r < A.nrows; ++r)
+        for (int64_t p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p) tmp[r * A.ncols + A.col[p]] = A.val[p];
+      src = &tmp;
+    }
+  }
+  if (!src) return SEM_EINVAL;
+  if (needed) *needed = (int64_t)src->size();
+  if (n != (int64_t)src->size() || (!out && n > 0)) return SEM_EINVAL;
+  if (n) std::memcpy(out, src->data(), n * sizeof(double));
+  return SEM_OK;
+}
+
+sem_status sem_beta_table(int32_t k, double *out) {
+  const double *row = beta_row(k);
+  if (!row || !out) return SEM_EINVAL;
+  std::memcpy(out, row, k * sizeof(double));
+  return SEM_OK;
+}
+
+sem_status sem_destroy(sem_ctx *c) {
+  if (!c) return SEM_EINVAL;
+  release(c);
+  return SEM_OK;
+}
+
+const char *sem_last_error(const sem_ctx *c) { return c ? c->err.c_str() : g_err.c_str(); }
+const char *sem_global_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

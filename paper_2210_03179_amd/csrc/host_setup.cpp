@@ -1,0 +1,550 @@
+// Host-side setup of the semcheb hierarchy: GLL data, geometric factors, Jacobi
+// diagonals, the order-1 coarse operator and its block-tridiagonal factorisation,
+// and the 2D finite-difference Galerkin hierarchy. None of this runs per solve.
+#include <omp.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "internal.h"
+
+namespace semcheb {
+
+// ------------------------------------------------------------------ GLL
+// Legendre L_N(x) and L_{N-1}(x) by the three-term recurrence.
+static void legendre_pair(int N, double x, double &LN, double &LNm1) {
+  double p0 = 1.0, p1 = x;
+  if (N == 0) { LN = 1.0; LNm1 = 0.0; return; }
+  for (int k = 1; k < N; ++k) {
+    double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0);
+    p0 = p1;
+    p1 = p2;
+  }
+  LN = p1;
+  LNm1 = p0;
+}
+
+Gll make_gll(int N) {
+  Gll g;
+  g.N = N;
+  const int n1 = N + 1;
+  g.x.assign(n1, 0.0);
+  g.w.assign(n1, 0.0);
+  g.D.assign(n1 * n1, 0.0);
+  g.x[0] = -1.0;
+  g.x[N] = 1.0;
+  // interior nodes: roots of L_N'; Newton from the Chebyshev-Lobatto points, using
+  // L_N' = N (x L_N - L_{N-1}) / (x^2 - 1) and the Legendre equation for L_N''.
+  for (int i = 1; i < N; ++i) {
+    double x = -std::cos(M_PI * i / N);
+    for (int it = 0; it < 100; ++it) {
+      double LN, LNm1;
+      legendre_pair(N, x, LN, LNm1);
+      double d1 = N * (x * LN - LNm1) / (x * x - 1.0);
+      double d2 = (2.0 * x * d1 - N * (N + 1.0) * LN) / (1.0 - x * x);
+      double dx = d1 / d2;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    g.x[i] = x;
+  }
+  std::vector<double> LNv(n1);
+  for (int i = 0; i < n1; ++i) {
+    double LN, LNm1;
+    legendre_pair(N, g.x[i], LN, LNm1);
+    LNv[i] = LN;
+    g.w[i] = 2.0 / (N * (N + 1.0) * LN * LN);
+  }
+  for (int i = 0; i < n1; ++i)
+    for (int j = 0; j < n1; ++j)
+      if (i != j) g.D[i * n1 + j] = LNv[i] / (LNv[j] * (g.x[i] - g.x[j]));
+  g.D[0] = -N * (N + 1.0) / 4.0;
+  g.D[N * n1 + N] = N * (N + 1.0) / 4.0;
+  return g;
+}
+
+std::vector<double> make_interp(const Gll &f, const Gll &c) {
+  const int nf = f.N + 1, nc = c.N + 1;
+  std::vector<double> J(nf * nc);
+  for (int i = 0; i < nf; ++i)
+    for (int a = 0; a < nc; ++a) {
+      double v = 1.0;
+      for (int m = 0; m < nc; ++m)
+        if (m != a) v *= (f.x[i] - c.x[m]) / (c.x[a] - c.x[m]);
+      J[i * nc + a] = v;
+    }
+  return J;
+}
+
+// ------------------------------------------------------------------ geometry
+static inline int64_t vidx(const sem_box_mesh &m, int i, int j, int k) {
+  return (int64_t)i + (int64_t)(m.nex + 1) * ((int64_t)j + (int64_t)(m.ney + 1) * k);
+}
+
+sem_status build_box_level(const sem_box_mesh &mesh, int N, BoxLevelHost &L, std::string &err) {
+  L.N = N;
+  L.n1 = N + 1;
+  L.nex = mesh.nex;
+  L.ney = mesh.ney;
+  L.nez = mesh.nez;
+  L.nx = mesh.nex * N - 1;
+  L.ny = mesh.ney * N - 1;
+  L.nz = mesh.nez * N - 1;
+  L.E = (int64_t)mesh.nex * mesh.ney * mesh.nez;
+  const int n1 = L.n1, n3 = n1 * n1 * n1;
+  L.L = L.E * n3;
+  L.n = (int64_t)L.nx * L.ny * L.nz;
+  L.gll = make_gll(N);
+  const Gll &g = L.gll;
+  L.G.assign((size_t)L.E * 6 * n3, 0.0);
+  std::vector<double> Bl((size_t)L.L), dl((size_t)L.L), Xl((size_t)L.L * 3);
+  int bad = 0;
+
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+  for (int64_t e = 0; e < L.E; ++e) {
+    const int ex = (int)(e % L.nex), ey = (int)((e / L.nex) % L.ney), ez = (int)(e / ((int64_t)L.nex * L.ney));
+    double C[2][2][2][3];
+    for (int ck = 0; ck < 2; ++ck)
+      for (int cj = 0; cj < 2; ++cj)
+        for (int ci = 0; ci < 2; ++ci)
+          for (int d = 0; d < 3; ++d)
+            C[ck][cj][ci][d] = mesh.vertex_xyz[3 * vidx(mesh, ex + ci, ey + cj, ez + ck) + d];
+    std::vector<double> X(3 * n3);
+    for (int k = 0; k < n1; ++k)
+      for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n1; ++i) {
+          const double h[2][3] = {{(1 - g.x[i]) / 2, (1 - g.x[j]) / 2, (1 - g.x[k]) / 2},
+                                  {(1 + g.x[i]) / 2, (1 + g.x[j]) / 2, (1 + g.x[k]) / 2}};
+          for (int d = 0; d < 3; ++d) {
+            double s = 0;
+            for (int ck = 0; ck < 2; ++ck)
+              for (int cj = 0; cj < 2; ++cj)
+                for (int ci = 0; ci < 2; ++ci) s += h[ck][2] * h[cj][1] * h[ci][0] * C[ck][cj][ci][d];
+            X[3 * ((k * n1 + j) * n1 + i) + d] = s;
+          }
+        }
+    double *Ge = &L.G[(size_t)e * 6 * n3];
+    for (int k = 0; k < n1; ++k)
+      for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n1; ++i) {
+          const int q = (k * n1 + j) * n1 + i;
+          double Jm[3][3];  // Jm[d][a] = dx_d / dr_a
+          for (int d = 0; d < 3; ++d) {
+            double sr = 0, ss = 0, st = 0;
+            for (int l = 0; l < n1; ++l) {
+              sr += g.D[i * n1 + l] * X[3 * ((k * n1 + j) * n1 + l) + d];
+              ss += g.D[j * n1 + l] * X[3 * ((k * n1 + l) * n1 + i) + d];
+              st += g.D[k * n1 + l] * X[3 * ((l * n1 + j) * n1 + i) + d];
+            }
+            Jm[d][0] = sr;
+            Jm[d][1] = ss;
+            Jm[d][2] = st;
+          }
+          const double det = Jm[0][0] * (Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1]) -
+                             Jm[0][1] * (Jm[1][0] * Jm[2][2] - Jm[1][2] * Jm[2][0]) +
+                             Jm[0][2] * (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]);
+          if (!(det > 0.0)) bad += 1;
+          double Ji[3][3];  // Ji[a][d] = dr_a / dx_d (adjugate / det)
+          Ji[0][0] = (Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1]) / det;
+          Ji[0][1] = (Jm[0][2] * Jm[2][1] - Jm[0][1] * Jm[2][2]) / det;
+          Ji[0][2] = (Jm[0][1] * Jm[1][2] - Jm[0][2] * Jm[1][1]) / det;
+          Ji[1][0] = (Jm[1][2] * Jm[2][0] - Jm[1][0] * Jm[2][2]) / det;
+          Ji[1][1] = (Jm[0][0] * Jm[2][2] - Jm[0][2] * Jm[2][0]) / det;
+          Ji[1][2] = (Jm[0][2] * Jm[1][0] - Jm[0][0] * Jm[1][2]) / det;
+          Ji[2][0] = (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]) / det;
+          Ji[2][1] = (Jm[0][1] * Jm[2][0] - Jm[0][0] * Jm[2][1]) / det;
+          Ji[2][2] = (Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0]) / det;
+          const double B = g.w[i] * g.w[j] * g.w[k] * det;
+          static const int ca[6] = {0, 0, 0, 1, 1, 2}, cb[6] = {0, 1, 2, 1, 2, 2};
+          for (int c = 0; c < 6; ++c) {
+            double s = 0;
+            for (int d = 0; d < 3; ++d) s += Ji[ca[c]][d] * Ji[cb[c]][d];
+            Ge[c * n3 + q] = B * s;
+          }
+          Bl[(size_t)e * n3 + q] = B;
+          for (int d = 0; d < 3; ++d) Xl[3 * ((size_t)e * n3 + q) + d] = X[3 * q + d];
+        }
+    // local diagonal of sum_ab D_a^T G_ab D_b
+    for (int k = 0; k < n1; ++k)
+      for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n1; ++i) {
+          const int q = (k * n1 + j) * n1 + i;
+          double s = 0;
+          for (int l = 0; l < n1; ++l) {
+            const double a = g.D[l * n1 + i], b = g.D[l * n1 + j], c = g.D[l * n1 + k];
+            s += a * a * Ge[0 * n3 + (k * n1 + j) * n1 + l];
+            s += b * b * Ge[3 * n3 + (k * n1 + l) * n1 + i];
+            s += c * c * Ge[5 * n3 + (l * n1 + j) * n1 + i];
+          }
+          const double di = g.D[i * n1 + i], dj = g.D[j * n1 + j], dk = g.D[k * n1 + k];
+          s += 2.0 * (di * dj * Ge[1 * n3 + q] + di * dk * Ge[2 * n3 + q] + dj * dk * Ge[4 * n3 + q]);
+          dl[(size_t)e * n3 + q] = s;
+        }
+  }
+  if (bad) {
+    err = "mesh has " + std::to_string(bad) + " GLL points with non-positive Jacobian at order " +
+          std::to_string(N);
+    return SEM_EMESH;
+  }
+  // direct-stiffness summation of the diagonal and the mass; coordinates
+  L.diag.assign(L.n, 0.0);
+  L.mass.assign(L.n, 0.0);
+  L.coords.assign((size_t)L.n * 3, 0.0);
+  for (int64_t e = 0; e < L.E; ++e) {
+    const int ex = (int)(e % L.nex), ey = (int)((e / L.nex) % L.ney), ez = (int)(e / ((int64_t)L.nex * L.ney));
+    for (int k = 0; k < n1; ++k) {
+      const int K = ez * N + k;
+      if (K < 1 || K > L.nz) continue;
+      for (int j = 0; j < n1; ++j) {
+        const int J = ey * N + j;
+        if (J < 1 || J > L.ny) continue;
+        for (int i = 0; i < n1; ++i) {
+          const int I = ex * N + i;
+          if (I < 1 || I > L.nx) continue;
+          const int64_t gi = (I - 1) + (int64_t)L.nx * ((J - 1) + (int64_t)L.ny * (K - 1));
+          const size_t q = (size_t)e * n3 + (k * n1 + j) * n1 + i;
+          L.diag[gi] += dl[q];
+          L.mass[gi] += Bl[q];
+          for (int d = 0; d < 3; ++d) L.coords[3 * gi + d] = Xl[3 * q + d];
+        }
+      }
+    }
+  }
+  return SEM_OK;
+}
+
+Csr assemble_q1(const BoxLevelHost &L) {
+  // element matrices A_e[p][p'] = sum_q sum_ab (D_a)_{q,p} G_ab(q) (D_b)_{q,p'}
+  const int n1 = L.n1, n3 = n1 * n1 * n1;
+  const std::vector<double> &D = L.gll.D;
+  std::vector<std::map<int32_t, double>> rows(L.n);
+  std::vector<double> Ae(n3 * n3);
+  std::vector<double> Da(3 * n3 * n3);  // Da[a][q][p]
+  for (int q = 0; q < n3; ++q) {
+    const int qi = q % n1, qj = (q / n1) % n1, qk = q / (n1 * n1);
+    for (int p = 0; p < n3; ++p) {
+      const int pi = p % n1, pj = (p / n1) % n1, pk = p / (n1 * n1);
+      Da[(0 * n3 + q) * n3 + p] = (qj == pj && qk == pk) ? D[qi * n1 + pi] : 0.0;
+      Da[(1 * n3 + q) * n3 + p] = (qi == pi && qk == pk) ? D[qj * n1 + pj] : 0.0;
+      Da[(2 * n3 + q) * n3 + p] = (qi == pi && qj == pj) ? D[qk * n1 + pk] : 0.0;
+    }
+  }
+  static const int comp[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+  for (int64_t e = 0; e < L.E; ++e) {
+    const double *Ge = &L.G[(size_t)e * 6 * n3];
+    std::fill(Ae.begin(), Ae.end(), 0.0);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        for (int q = 0; q < n3; ++q) {
+          const double gq = Ge[comp[a][b] * n3 + q];
+          for (int p = 0; p < n3; ++p) {
+            const double da = Da[(a * n3 + q) * n3 + p];
+            if (da == 0.0) continue;
+            for (int pp = 0; pp < n3; ++pp) Ae[p * n3 + pp] += da * gq * Da[(b * n3 + q) * n3 + pp];
+          }
+        }
+    const int ex = (int)(e % L.nex), ey = (int)((e / L.nex) % L.ney), ez = (int)(e / ((int64_t)L.nex * L.ney));
+    std::vector<int64_t> gid(n3);
+    for (int p = 0; p < n3; ++p) {
+      const int I = ex * L.N + p % n1, J = ey * L.N + (p / n1) % n1, K = ez * L.N + p / (n1 * n1);
+      gid[p] = (I >= 1 && I <= L.nx && J >= 1 && J <= L.ny && K >= 1 && K <= L.nz)
+                   ? (I - 1) + (int64_t)L.nx * ((J - 1) + (int64_t)L.ny * (K - 1))
+                   : -1;
+    }
+    for (int p = 0; p < n3; ++p) {
+      if (gid[p] < 0) continue;
+      for (int pp = 0; pp < n3; ++pp)
+        if (gid[pp] >= 0) rows[gid[p]][(int32_t)gid[pp]] += Ae[p * n3 + pp];
+    }
+  }
+  Csr A;
+  A.nrows = A.ncols = L.n;
+  A.rowptr.assign(L.n + 1, 0);
+  for (int64_t r = 0; r < L.n; ++r) A.rowptr[r + 1] = A.rowptr[r] + (int64_t)rows[r].size();
+  A.col.reserve(A.rowptr[L.n]);
+  A.val.reserve(A.rowptr[L.n]);
+  for (int64_t r = 0; r < L.n; ++r)
+    for (auto &kv : rows[r]) {
+      A.col.push_back(kv.first);
+      A.val.push_back(kv.second);
+    }
+  return A;
+}
+
+// ------------------------------------------------------------------ dense SPD inverse
+bool spd_inverse(std::vector<double> &A, int64_t n) {
+  // Cholesky A = L L^T (L stored in the lower triangle of A), row-major.
+  for (int64_t j = 0; j < n; ++j) {
+    double s = A[j * n + j];
+    const double *Lj = &A[j * n];
+    for (int64_t k = 0; k < j; ++k) s -= Lj[k] * Lj[k];
+    if (!(s > 0.0)) return false;
+    const double djj = std::sqrt(s);
+    A[j * n + j] = djj;
+#pragma omp parallel for schedule(static) if (n - j > 256)
+    for (int64_t i = j + 1; i < n; ++i) {
+      const double *Li = &A[i * n];
+      double t = A[i * n + j];
+      for (int64_t k = 0; k < j; ++k) t -= Li[k] * Lj[k];
+      A[i * n + j] = t / djj;
+    }
+  }
+  // Rows of W = L^{-T}: W[j][i] = (L^{-1})[i][j], solved column by column of L^{-1}.
+  std::vector<double> W((size_t)n * n, 0.0);
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int64_t j = 0; j < n; ++j) {
+    double *x = &W[(size_t)j * n];
+    x[j] = 1.0 / A[j * n + j];
+    for (int64_t i = j + 1; i < n; ++i) {
+      const double *Li = &A[i * n];
+      double s = 0.0;
+      for (int64_t k = j; k < i; ++k) s -= Li[k] * x[k];
+      x[i] = s / Li[i];
+    }
+  }
+  // A^{-1} = L^{-T} L^{-1}: entry (i,j) = sum_{k >= max(i,j)} W[i][k] W[j][k]
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int64_t i = 0; i < n; ++i) {
+    const double *Wi = &W[(size_t)i * n];
+    for (int64_t j = i; j < n; ++j) {
+      const double *Wj = &W[(size_t)j * n];
+      double s = 0.0;
+      for (int64_t k = j; k < n; ++k) s += Wi[k] * Wj[k];
+      A[i * n + j] = s;
+    }
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < i; ++j) A[i * n + j] = A[j * n + i];
+  return true;
+}
+
+bool block_tridiag_factor(const Csr &A, const std::vector<int64_t> &start, BlockTri &out,
+                          std::string &err) {
+  const int nb = (int)start.size() - 1;
+  out.start = start;
+  out.Minv.assign(nb, {});
+  out.Lmat.assign(nb, {});
+  out.Up.assign(nb, {});
+  auto block_of = [&](int64_t idx) {
+    return (int)(std::upper_bound(start.begin(), start.end(), idx) - start.begin()) - 1;
+  };
+  // sub-blocks of A as CSR restricted to (rows of bi, cols of bj), cols local to bj
+  auto extract = [&](int bi, int bj) {
+    Csr S;
+    S.nrows = start[bi + 1] - start[bi];
+    S.ncols = start[bj + 1] - start[bj];
+    S.rowptr.assign(S.nrows + 1, 0);
+    for (int64_t r = start[bi]; r < start[bi + 1]; ++r) {
+      for (int64_t p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p) {
+        const int64_t c = A.col[p];
+        if (c >= start[bj] && c < start[bj + 1]) {
+          S.col.push_back((int32_t)(c - start[bj]));
+          S.val.push_back(A.val[p]);
+        }
+      }
+      S.rowptr[r - start[bi] + 1] = (int64_t)S.col.size();
+    }
+    return S;
+  };
+  // couplings beyond neighbouring blocks are not allowed
+  for (int64_t r = 0; r < A.nrows; ++r)
+    for (int64_t p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p)
+      if (std::abs(block_of(r) - block_of(A.col[p])) > 1) {
+        err = "coarse matrix is not block tridiagonal in the chosen blocking";
+        return false;
+      }
+  for (int b = 0; b < nb; ++b) {
+    const int64_t Pb = start[b + 1] - start[b];
+    std::vector<double> S((size_t)Pb * Pb, 0.0);
+    Csr Abb = extract(b, b);
+    for (int64_t r = 0; r < Pb; ++r)
+      for (int64_t p = Abb.rowptr[r]; p < Abb.rowptr[r + 1]; ++p) S[r * Pb + Abb.col[p]] += Abb.val[p];
+    if (b > 0) {
+      const int64_t Pp = start[b] - start[b - 1];
+      Csr Alo = extract(b, b - 1);   // A_{b,b-1}
+      Csr Aup = extract(b - 1, b);   // A_{b-1,b}
+      std::vector<double> &Lm = out.Lmat[b];
+      Lm.assign((size_t)Pb * Pp, 0.0);
+      const std::vector<double> &Mp = out.Minv[b - 1];
+#pragma omp parallel for schedule(static)
+      for (int64_t r = 0; r < Pb; ++r)
+        for (int64_t p = Alo.rowptr[r]; p < Alo.rowptr[r + 1]; ++p) {
+          const double v = Alo.val[p];
+          const double *Mrow = &Mp[(size_t)Alo.col[p] * Pp];
+          double *Lrow = &Lm[(size_t)r * Pp];
+          for (int64_t c = 0; c < Pp; ++c) Lrow[c] += v * Mrow[c];
+        }
+      // S -= L_b A_{b-1,b}
+#pragma omp parallel for schedule(static)
+      for (int64_t r = 0; r < Pb; ++r) {
+        const double *Lrow = &Lm[(size_t)r * Pp];
+        double *Srow = &S[(size_t)r * Pb];
+        for (int64_t q = 0; q < Pp; ++q) {
+          const double l = Lrow[q];
+          if (l == 0.0) continue;
+          for (int64_t p = Aup.rowptr[q]; p < Aup.rowptr[q + 1]; ++p) Srow[Aup.col[p]] -= l * Aup.val[p];
+        }
+      }
+    }
+    if (!spd_inverse(S, Pb)) {
+      err = "coarse Schur complement is not positive definite (block " + std::to_string(b) + ")";
+      return false;
+    }
+    out.Minv[b] = std::move(S);
+    if (b + 1 < nb) out.Up[b] = extract(b, b + 1);
+  }
+  return true;
+}
+
+// ------------------------------------------------------------------ FD hierarchy
+static Csr csr_from_map(int64_t nrows, int64_t ncols, std::vector<std::map<int32_t, double>> &rows) {
+  Csr A;
+  A.nrows = nrows;
+  A.ncols = ncols;
+  A.rowptr.assign(nrows + 1, 0);
+  for (int64_t r = 0; r < nrows; ++r) A.rowptr[r + 1] = A.rowptr[r] + (int64_t)rows[r].size();
+  for (int64_t r = 0; r < nrows; ++r)
+    for (auto &kv : rows[r]) {
+      A.col.push_back(kv.first);
+      A.val.push_back(kv.second);
+    }
+  return A;
+}
+
+static Csr csr_transpose(const Csr &A) {
+  std::vector<std::map<int32_t, double>> rows(A.ncols);
+  for (int64_t r = 0; r < A.nrows; ++r)
+    for (int64_t p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p) rows[A.col[p]][(int32_t)r] += A.val[p];
+  return csr_from_map(A.ncols, A.nrows, rows);
+}
+
+static Csr csr_matmul(const Csr &A, const Csr &B) {
+  std::vector<std::map<int32_t, double>> rows(A.nrows);
+  for (int64_t r = 0; r < A.nrows; ++r)
+    for (int64_t p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p) {
+      const int32_t k = A.col[p];
+      for (int64_t q = B.rowptr[k]; q < B.rowptr[k + 1]; ++q) rows[r][B.col[q]] += A.val[p] * B.val[q];
+    }
+  return csr_from_map(A.nrows, B.ncols, rows);
+}
+
+void build_fd_hierarchy(int n, double Lx, double Ly, int factor, int coarsest_n,
+                        std::vector<FdLevelHost> &out) {
+  out.clear();
+  FdLevelHost f;
+  f.n = n;
+  const int m = n - 1;
+  f.m = (int64_t)m * m;
+  const double hx = Lx / n, hy = Ly / n;
+  {
+    std::vector<std::map<int32_t, double>> rows(f.m);
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < m; ++i) {
+        const int32_t r = i + m * j;
+        rows[r][r] += 2.0 / (hx * hx) + 2.0 / (hy * hy);
+        if (i > 0) rows[r][r - 1] += -1.0 / (hx * hx);
+        if (i < m - 1) rows[r][r + 1] += -1.0 / (hx * hx);
+        if (j > 0) rows[r][r - m] += -1.0 / (hy * hy);
+        if (j < m - 1) rows[r][r + m] += -1.0 / (hy * hy);
+      }
+    f.A = csr_from_map(f.m, f.m, rows);
+  }
+  out.push_back(f);
+  while (out.back().n % factor == 0 && out.back().n / factor >= coarsest_n) {
+    const int nf = out.back().n, nc = nf / factor;
+    const int mf = nf - 1, mc = nc - 1;
+    // P = P1 (x) P1 with 1D hat weights 1 - |i - f I| / f
+    std::vector<std::map<int32_t, double>> rows((int64_t)mf * mf);
+    for (int J = 1; J <= mc; ++J)
+      for (int I = 1; I <= mc; ++I)
+        for (int j = std::max(1, factor * J - factor + 1); j <= std::min(mf, factor * J + factor - 1); ++j)
+          for (int i = std::max(1, factor * I - factor + 1); i <= std::min(mf, factor * I + factor - 1); ++i) {
+            const double wx = 1.0 - std::abs(i - factor * I) / (double)factor;
+            const double wy = 1.0 - std::abs(j - factor * J) / (double)factor;
+            if (wx > 0 && wy > 0) rows[(i - 1) + (int64_t)mf * (j - 1)][(I - 1) + mc * (J - 1)] += wx * wy;
+          }
+    out.back().P = csr_from_map((int64_t)mf * mf, (int64_t)mc * mc, rows);
+    FdLevelHost c;
+    c.n = nc;
+    c.m = (int64_t)mc * mc;
+    Csr PT = csr_transpose(out.back().P);
+    c.A = csr_matmul(PT, csr_matmul(out.back().A, out.back().P));
+    out.push_back(c);
+  }
+}
+
+// ------------------------------------------------------------------ tridiagonal eigenvalue
+double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &b) {
+  const int m = (int)a.size();
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  // Sturm count: number of eigenvalues < x
+  auto count = [&](double x) {
+    int c = 0;
+    double q = a[0] - x;
+    if (q < 0) ++c;
+    for (int i = 1; i < m; ++i) {
+      if (q == 0.0) q = 1e-300;
+      q = a[i] - x - b[i - 1] * b[i - 1] / q;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(hi), 1e-300); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count(mid) >= m) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// ------------------------------------------------------------------ beta table
+// Supplementary material, Table beta_coef (optimised 4th-kind Chebyshev smoother).
+static const double kBeta[] = {
+    1.12500000000000,
+    1.02387287570313, 1.26408905371085,
+    1.00842544782028, 1.08867839208730, 1.33753125909618,
+    1.00391310427285, 1.04035811188593, 1.14863498546254, 1.38268869241000,
+    1.00212930146164, 1.02173711549260, 1.07872433192603, 1.19810065292663, 1.41322542791682,
+    1.00128517255940, 1.01304293035233, 1.04678215124113, 1.11616489419675, 1.23829020218444,
+    1.43524297106744,
+    1.00083464397912, 1.00843949430122, 1.03008707768713, 1.07408384092003, 1.15036186707366,
+    1.27116474046139, 1.45186658649364,
+    1.00057246631197, 1.00577427662415, 1.02050187922941, 1.05019803444565, 1.10115572984941,
+    1.18086042806856, 1.29838585382576, 1.46486073151099,
+    1.00040960072832, 1.00412439506106, 1.01460212148266, 1.03561113626671, 1.07139972529194,
+    1.12688273710962, 1.20785219140729, 1.32121930716746, 1.47529642820699,
+    1.00030312229652, 1.00304840660796, 1.01077022715387, 1.02619011597640, 1.05231724933755,
+    1.09255743207549, 1.15083376663972, 1.23172250870894, 1.34060802024460, 1.48386124407011,
+    1.00023058595209, 1.00231675024028, 1.00817245396304, 1.01982986566342, 1.03950210235324,
+    1.06965042700541, 1.11305754295742, 1.17290876275564, 1.25288300576792, 1.35725579919519,
+    1.49101672564139,
+    1.00017947200828, 1.00180189139619, 1.00634861907307, 1.01537864566306, 1.03056942830760,
+    1.05376019693943, 1.08699862592072, 1.13259183097913, 1.19316273358172, 1.27171293675110,
+    1.37169337969799, 1.49708418575562,
+    1.00014241921559, 1.00142906932629, 1.00503028986298, 1.01216910518495, 1.02414874342792,
+    1.04238158880820, 1.06842008128700, 1.10399010936759, 1.15102748242645, 1.21171811910125,
+    1.28854264865128, 1.38432619380991, 1.50229418757368,
+    1.00011490538261, 1.00115246376914, 1.00405357333264, 1.00979590573153, 1.01941300472994,
+    1.03401425035436, 1.05480599606629, 1.08311420301813, 1.12040891660892, 1.16833095655446,
+    1.22872122288238, 1.30365305707817, 1.39546814053678, 1.50681646209583,
+    1.00009404750752, 1.00094291696343, 1.00331449056444, 1.00800294833816, 1.01584236259140,
+    1.02772083317705, 1.04459535422831, 1.06750761206125, 1.09760092545889, 1.13613855366157,
+    1.18452361426236, 1.24432087304475, 1.31728069083392, 1.40536543893560, 1.51077872501845,
+    1.00007794828179, 1.00078126847253, 1.00274487974401, 1.00662291017015, 1.01309858836971,
+    1.02289448329337, 1.03678321409983, 1.05559875719896, 1.08024848405560, 1.11172607131497,
+    1.15112543431072, 1.19965584614973, 1.25865841744946, 1.32962412656664, 1.41421360695576,
+    1.51427891730346,
+};
+
+const double *beta_row(int k) {
+  if (k < 1 || k > 16) return nullptr;
+  return &kBeta[(k - 1) * k / 2];
+}
+
+}  // namespace semcheb

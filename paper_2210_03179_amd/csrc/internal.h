@@ -1,0 +1,143 @@
+// Internal declarations of the semcheb library (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/semcheb.h"
+
+namespace semcheb {
+
+// ---------------------------------------------------------------- host setup data
+struct Gll {
+  int N = 0;
+  std::vector<double> x, w, D;  // nodes, weights, D[i*(N+1)+l] = l_l'(x_i)
+};
+Gll make_gll(int N);
+// J[i*(Nc+1)+a] = l_a^{(Nc)}(x_i^{(Nf)})
+std::vector<double> make_interp(const Gll &fine, const Gll &coarse);
+// Table beta_coef of the supplementary material, k = 1..16
+const double *beta_row(int k);
+
+// Structured box geometry of one order (SEM level), built on the host.
+struct BoxLevelHost {
+  int N = 0, n1 = 0;
+  int nex = 0, ney = 0, nez = 0;
+  int nx = 0, ny = 0, nz = 0;  // interior lattice sizes
+  int64_t E = 0, L = 0, n = 0;
+  Gll gll;
+  std::vector<double> G;       // [e][6][n1^3]
+  std::vector<double> diag;    // [n]
+  std::vector<double> mass;    // [n]
+  std::vector<double> coords;  // [n][3]
+};
+// Returns SEM_EMESH on a non-positive Jacobian.
+sem_status build_box_level(const sem_box_mesh &mesh, int N, BoxLevelHost &out, std::string &err);
+// Assembled order-1 operator in CSR (rows = n).
+struct Csr {
+  int64_t nrows = 0, ncols = 0;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+};
+Csr assemble_q1(const BoxLevelHost &lev);
+
+// Block-tridiagonal factorisation of an SPD matrix whose unknowns are grouped in
+// contiguous blocks with couplings only between neighbouring blocks.
+struct BlockTri {
+  std::vector<int64_t> start;               // block b covers [start[b], start[b+1])
+  std::vector<std::vector<double>> Minv;    // S_b^{-1}, dense row-major
+  std::vector<std::vector<double>> Lmat;    // A_{b,b-1} S_{b-1}^{-1}, dense (b >= 1)
+  std::vector<Csr> Up;                      // A_{b,b+1} (rows of b, cols local to b+1)
+};
+bool block_tridiag_factor(const Csr &A, const std::vector<int64_t> &start, BlockTri &out,
+                          std::string &err);
+bool spd_inverse(std::vector<double> &A, int64_t n);  // in place, false if not SPD
+
+// FD2D problem (Sec. 3) host data
+struct FdLevelHost {
+  int n = 0;  // intervals
+  int64_t m = 0;  // unknowns
+  Csr A;
+  Csr P;  // interpolation from the next coarser level (rows = m), empty on the last level
+};
+void build_fd_hierarchy(int n, double Lx, double Ly, int factor, int coarsest_n,
+                        std::vector<FdLevelHost> &out);
+
+// Largest eigenvalue of a symmetric tridiagonal matrix (diag a[0..m-1], offdiag b[0..m-2]).
+double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &b);
+
+// ---------------------------------------------------------------- device level data
+enum LevelType { LVL_SEM = 0, LVL_FD = 1 };
+
+struct DevCsr {
+  int64_t nrows = 0;
+  int64_t *rowptr = nullptr;
+  int32_t *col = nullptr;
+  double *val64 = nullptr;
+  float *val32 = nullptr;
+};
+
+struct Level {
+  LevelType type = LVL_SEM;
+  int N = 0, n1 = 0;
+  int nex = 0, ney = 0, nez = 0, nx = 0, ny = 0, nz = 0;
+  int64_t E = 0, L = 0, n = 0;
+  double lmax = 0.0;
+  // SEM
+  double *G64 = nullptr;      // [E][6][n1^3]
+  uint16_t *Gbf = nullptr;    // bf16 copy (mixed precision)
+  double *D64 = nullptr;      // (N+1)^2
+  float *D32 = nullptr;
+  double *J64 = nullptr;      // interpolation from the next level, (N+1) x (Nc+1)
+  float *J32 = nullptr;
+  double *mass = nullptr;     // assembled mass (finest level)
+  double *coords = nullptr;   // [n][3] (finest level)
+  // FD
+  DevCsr A, P, R;             // A_j; P: level j+1 -> j (rows n); R = P^T (rows n_{j+1})
+  // both
+  double *invdiag64 = nullptr;
+  float *invdiag32 = nullptr;
+  // work vectors in the V-cycle precision (only one of the pairs is used)
+  double *b64 = nullptr, *x64 = nullptr, *r64 = nullptr, *d64 = nullptr, *w64 = nullptr;
+  float *b32 = nullptr, *x32 = nullptr, *r32 = nullptr, *d32 = nullptr, *w32 = nullptr;
+  int64_t applies = 0;
+};
+
+struct CoarseSolver {
+  bool dense = true;
+  int64_t n = 0;
+  // dense inverse (FD, or a single block)
+  double *Minv = nullptr;
+  // block tridiagonal
+  std::vector<int64_t> start;
+  std::vector<double *> Mb, Lb;
+  std::vector<DevCsr> Ub;
+  double *b = nullptr, *y = nullptr, *x = nullptr, *t = nullptr;
+  std::vector<double> host_dense;  // small problems: assembled matrix for inspection
+};
+
+}  // namespace semcheb
+
+struct sem_ctx {
+  int kind = 0;  // semcheb::LVL_SEM or LVL_FD
+  sem_options opt{};
+  bool host_only = false;
+  int device = 0;
+  std::vector<semcheb::Level> levels;
+  std::vector<semcheb::BoxLevelHost> host_levels;  // SEM host data
+  std::vector<std::vector<double>> host_interp;
+  std::vector<semcheb::FdLevelHost> fd_host;
+  semcheb::CoarseSolver coarse;
+  // Krylov work (FP64, finest level)
+  double *kr = nullptr, *kr2 = nullptr, *kz = nullptr, *kp = nullptr, *kw = nullptr;
+  double *scal = nullptr;      // device scalars
+  double *partials = nullptr;  // reduction partials
+  double *pinned = nullptr;    // host-pinned scalar mirror
+  float *vin32 = nullptr;      // mixed-precision V-cycle input
+  std::string err;
+  std::vector<void *> allocations;
+};

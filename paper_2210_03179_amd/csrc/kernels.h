@@ -1,0 +1,62 @@
+// Launchers of the semcheb HIP kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace semcheb {
+
+// Chebyshev step flags (cheb kernel)
+enum {
+  CHEB_R_FROM_B = 1,  // residual input is the level right-hand side b
+  CHEB_S_ON_R = 2,    // multiply the residual input by diag(A)^{-1} (Algorithm 1 from b)
+  CHEB_SUB_AD = 4,    // subtract A d (mode 1: diag^{-1} A d)
+  CHEB_WRITE_R = 8,   // store the updated residual
+  CHEB_D_INIT = 16,   // previous direction is zero
+  CHEB_X_INIT = 32    // previous iterate is zero
+};
+
+// device scalar slots of the Krylov method
+enum { S_RZ = 0, S_PW = 1, S_RR = 2, S_ZR = 3, S_ZRO = 4, S_BB = 5, S_BETA = 6, S_TMP = 8, S_COUNT = 16 };
+// scalar operations done by the finalize kernel after the reduction
+enum { FIN_NONE = 0, FIN_INIT_RZ = 1, FIN_BETA_PCG = 2, FIN_BETA_FCG = 3 };
+
+constexpr int kReduceBlocks = 1024;  // fixed grid of the reduction kernels (deterministic sums)
+
+bool launch_ax(const Level &L, const double *u, double *wL, hipStream_t s);
+bool launch_ax(const Level &L, const float *u, float *wL, hipStream_t s);
+template <typename T>
+void launch_dss(const Level &L, const T *wL, T *out, hipStream_t s);
+void launch_dss_dot(const Level &L, const double *wL, double *out, const double *p, double *partials,
+                    int nblocks, hipStream_t s);
+template <typename T>
+void launch_cheb(const Level &L, const T *wsrc, const T *b, const T *r_in, T *r_out, T *d, T *x,
+                 const T *invdiag, double a, double bc, double c, int flags, int mode, hipStream_t s);
+template <typename T>
+void launch_resid_weight(const Level &L, const T *wL, const T *b, T *rw, hipStream_t s);
+template <typename T>
+void launch_restrict(const Level &F, const Level &C, const T *rw, const T *J, T *rcL, hipStream_t s);
+template <typename T>
+void launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *xf, hipStream_t s);
+template <typename T>
+void launch_csr(const DevCsr &A, const T *val, const T *x, const T *b, T *y, int mode, hipStream_t s);
+void launch_gemv(int64_t nrows, int64_t ncols, const double *M, const double *x, const double *b, double *y,
+                 int sub, hipStream_t s);
+template <typename T>
+void launch_dots(int64_t n, int nd, const T *x0, const T *y0, const T *x1, const T *y1, const T *x2,
+                 const T *y2, double *partials, int nblocks, hipStream_t s);
+void launch_finalize(int nblocks, int nd, const double *partials, double *scal, int slot, int op,
+                     hipStream_t s);
+void launch_update_xr(int64_t n, const double *scal, double *x, const double *p, const double *r,
+                      const double *w, double *rnew, double *partials, int nblocks, hipStream_t s);
+void launch_update_p(int64_t n, const double *scal, const double *z, double *p, hipStream_t s);
+void launch_convert(int64_t n, const double *in, float *out, hipStream_t s);
+void launch_convert(int64_t n, const float *in, double *out, hipStream_t s);
+void launch_axpby(int64_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s);
+void launch_mul(int64_t n, const double *a, const double *b, double *out, hipStream_t s);
+bool launch_adjoint(const Level &L, const double *lam, const double *u, double *dG, hipStream_t s);
+
+}  // namespace semcheb

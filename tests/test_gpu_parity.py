@@ -1,0 +1,247 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances (FP64): operator and transfers 1e-13 relative (max norm), V-cycle
+1e-12 relative (2-norm), PCG/FCG solves: identical iteration counts, every
+residual norm within 1e-12 ||b||, solution within 1e-12 relative. lambda_max
+is estimated by the oracle and handed to both sides, so the solve comparison
+does not depend on the two eigenvalue estimators, which are compared on their
+own.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workload as wl
+from oracle import adjoint, chebyshev as cheb, fd2d, krylov, mg
+from oracle.sem import SemBox
+from paper_2210_03179_amd import _lib as L
+from paper_2210_03179_amd.solver import SemSolver, FdSolver
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relmax(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+# ------------------------------------------------------------------ operator
+@pytest.mark.parametrize("m,N", [((2, 3, 2), N) for N in range(1, 13)] + [((8, 8, 8), 7), ((3, 2, 4), 5)])
+def test_apply_A_parity(m, N):
+    print(f"apply_A parity m={m} N={N}", flush=True)
+    V = wl.deformed_box(m, 0.05)
+    box = SemBox(V, N)
+    s = SemSolver(V, N=N, lambda_max=[1.0] * 8, orders=[N, 1] if N > 1 else None) if N > 1 else None
+    if s is None:
+        pytest.skip("order 1 alone has no smoothed level")
+    u = wl.uniform_noise(box.n, 11)
+    w = host(s.apply_A(dev(u)))
+    assert relmax(w, box.apply(u)) < 1e-13
+
+
+def test_apply_A_order1_and_deterministic():
+    V = wl.deformed_box((3, 3, 2), 0.05)
+    s = SemSolver(V, N=2, orders=[2, 1], lambda_max=[1.0])
+    box = SemBox(V, 2)
+    u = dev(wl.uniform_noise(box.n, 5))
+    a, b = host(s.apply_A(u)), host(s.apply_A(u))
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ V-cycle
+@pytest.fixture(scope="module")
+def small_case():
+    V = wl.deformed_box((3, 3, 4), 0.05)
+    N = 5
+    ref = mg.sem_hierarchy(V, N, cheb.CHEB4, 2, 2)
+    lmax = [lev.lmax for lev in ref.levels[:-1]]
+    return V, N, lmax
+
+
+@pytest.mark.parametrize("kind", ["cheb1", "cheb1opt", "cheb4", "cheb4opt"])
+@pytest.mark.parametrize("pre,post", [(4, 0), (2, 2), (3, 1), (1, 0), (0, 3)])
+def test_vcycle_parity(small_case, kind, pre, post):
+    print(f"vcycle parity {kind} ({pre},{post})", flush=True)
+    V, N, lmax = small_case
+    ref = mg.sem_hierarchy(V, N, kind, pre, post, lmax=lmax)
+    s = SemSolver(V, N=N, smoother=kind, pre=pre, post=post, lambda_max=lmax)
+    r = wl.uniform_noise(ref.levels[0].n, 3)
+    z = host(s.vcycle(dev(r)))
+    zo = ref.vcycle(r)
+    assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+    # fine-level operator applications per cycle: (pre - 1) + 1 + post from a zero guess
+    cnt = s.apply_counts()
+    expect0 = (pre - 1 + 1 if pre > 0 else 0) + post
+    assert cnt[0] == expect0
+    assert cnt[-1] == 0
+
+
+def test_lanczos_matches_oracle(small_case):
+    V, N, lmax = small_case
+    s = SemSolver(V, N=N)
+    got = s.lambda_max()
+    assert len(got) == len(lmax)
+    for a, b in zip(got, lmax):
+        assert abs(a - b) <= 1e-8 * b
+
+
+# ------------------------------------------------------------------ solves
+@pytest.fixture(scope="module")
+def cfg2():
+    """8x8x8 deformed box (amplitude 0.05), N=7, schedule (7,3,1), opt. 4th kind (4,0),
+    manufactured load plus 1e-3 relative U[-1,1] noise (seed 0)."""
+    V = wl.deformed_box(8, 0.05)
+    ref = mg.sem_hierarchy(V, 7, cheb.CHEB4_OPT, 4, 0)
+    box = ref.extra["boxes"][0]
+    b0 = box.mass() * wl.manufactured_load(box.coords())
+    b = b0 + 1e-3 * np.max(np.abs(b0)) * wl.uniform_noise(box.n, 0)
+    lmax = [lev.lmax for lev in ref.levels[:-1]]
+    return V, ref, box, b, lmax
+
+
+def _solve_parity(s, ref, Aop, b, flexible, tol=1e-8, maxit=200):
+    res = krylov.pcg(Aop, b, ref.vcycle, tol, maxit, flexible=flexible)
+    u, info = s.solve(dev(b), rtol=tol, maxit=maxit)
+    u = host(u)
+    assert info.converged and res.converged
+    assert info.iterations == res.iterations
+    h_o = np.array(res.history)
+    assert np.max(np.abs(info.history - h_o)) <= 1e-12 * h_o[0]
+    assert np.linalg.norm(u - res.x) <= 1e-12 * np.linalg.norm(res.x)
+    margin = (tol * h_o[0] - h_o[-1]) / (tol * h_o[0])
+    print(f"iterations {info.iterations}, last-iteration margin to tol {margin:.3e}", flush=True)
+    return u, info, res
+
+
+def test_cfg2_rhs_parity(cfg2):
+    V, ref, box, b, lmax = cfg2
+    s = SemSolver(V, N=7, lambda_max=lmax)
+    f = wl.manufactured_load(host(s.coords()))
+    bg = host(s.mass_apply(dev(f)))
+    assert relmax(bg, box.mass() * wl.manufactured_load(box.coords())) < 1e-14
+
+
+def test_cfg2_solve_parity(cfg2):
+    V, ref, box, b, lmax = cfg2
+    s = SemSolver(V, N=7, smoother="cheb4opt", pre=4, post=0, krylov="fcg", lambda_max=lmax)
+    s.reset_counts()
+    u, info, res = _solve_parity(s, ref, box.apply, b, flexible=True)
+    # fine-grid mat-vecs = iterations x (m + n + 1)
+    assert s.apply_counts()[0] == info.iterations * (4 + 0 + 1)
+
+
+@pytest.mark.parametrize("kind,pre,post,kry", [("cheb4", 2, 2, "pcg"), ("cheb1", 3, 3, "pcg"),
+                                               ("cheb1opt", 4, 0, "fcg"), ("cheb4opt", 2, 2, "fcg")])
+def test_small_solve_parity(small_case, kind, pre, post, kry):
+    V, N, lmax = small_case
+    ref = mg.sem_hierarchy(V, N, kind, pre, post, lmax=lmax)
+    box = ref.extra["boxes"][0]
+    b = box.mass() * wl.manufactured_load(box.coords()) + 1e-2 * wl.uniform_noise(box.n, 1)
+    s = SemSolver(V, N=N, smoother=kind, pre=pre, post=post, krylov=kry, lambda_max=lmax)
+    _solve_parity(s, ref, box.apply, b, flexible=(kry == "fcg"))
+
+
+def test_solve_nonzero_initial_guess(small_case):
+    V, N, lmax = small_case
+    s = SemSolver(V, N=N, lambda_max=lmax)
+    box = SemBox(V, N)
+    b = dev(wl.uniform_noise(box.n, 2))
+    x0 = dev(wl.uniform_noise(box.n, 3))
+    u, info = s.solve(b, x0=x0, rtol=1e-10)
+    assert info.converged
+    r0 = host(b) - box.apply(host(x0))
+    assert abs(info.history[0] - np.linalg.norm(r0)) <= 1e-12 * np.linalg.norm(r0)
+    assert np.linalg.norm(box.apply(host(u)) - host(b)) <= 2e-10 * np.linalg.norm(host(b))
+
+
+def test_solve_edge_cases(small_case):
+    V, N, lmax = small_case
+    s = SemSolver(V, N=N, lambda_max=lmax)
+    n = s.n
+    u, info = s.solve(torch.zeros(n, dtype=torch.float64, device="cuda"))
+    assert info.converged and info.iterations == 0 and float(u.abs().max()) == 0.0
+    b = dev(wl.uniform_noise(n, 4))
+    u, info = s.solve(b, rtol=1e-14, maxit=3)
+    assert info.status == L.SEM_ENOTCONV and info.iterations == 3
+    bad = b.clone()
+    bad[7] = float("nan")
+    with pytest.raises(L.SemError) as e:
+        s.solve(bad)
+    assert e.value.status == L.SEM_ENAN
+    # deterministic: two solves are bitwise identical
+    u1, _ = s.solve(b)
+    u2, _ = s.solve(b)
+    assert torch.equal(u1, u2)
+
+
+# ------------------------------------------------------------------ finite differences (config 1)
+@pytest.mark.parametrize("pre,post,kry", [(4, 0, "fcg"), (2, 2, "pcg"), (2, 2, "fcg")])
+def test_fd_cfg1_parity(pre, post, kry):
+    """2D FD, 63x63 interior, levels 63/31/15/7 Galerkin, 4th-kind Chebyshev, rhs U[-1,1] seed 0."""
+    ref = fd2d.fd_hierarchy(64, 2, cheb.CHEB4, pre, post, coarsest_n=8)
+    lmax = [lev.lmax for lev in ref.levels[:-1]]
+    s = FdSolver(n=64, factor=2, coarsest_n=8, smoother="cheb4", pre=pre, post=post, krylov=kry,
+                 lambda_max=lmax)
+    b = wl.fd_rhs(63, 0)
+    A = ref.extra["As"][0]
+    s.reset_counts()
+    u, info, res = _solve_parity(s, ref, lambda x: A @ x, b, flexible=(kry == "fcg"))
+    assert s.apply_counts()[0] == info.iterations * (pre + post + 1)
+
+
+def test_fd_lanczos_exact():
+    s = FdSolver(n=64, factor=2, coarsest_n=8)
+    assert abs(s.lambda_max()[0] - (1 + np.cos(np.pi / 64))) < 1e-9
+
+
+# ------------------------------------------------------------------ mixed precision
+def test_mixed_precision_reaches_fp64_residual(cfg2):
+    V, ref, box, b, lmax = cfg2
+    s = SemSolver(V, N=7, precision="mixed", krylov="fcg", lambda_max=lmax)
+    u, info = s.solve(dev(b), rtol=1e-8)
+    assert info.converged
+    uh = host(u)
+    true_rel = np.linalg.norm(b - box.apply(uh)) / np.linalg.norm(b)
+    assert true_rel <= 1.01e-8
+    s64 = SemSolver(V, N=7, lambda_max=lmax)
+    u64, info64 = s64.solve(dev(b), rtol=1e-8)
+    err = np.linalg.norm(uh - host(u64)) / np.linalg.norm(host(u64))
+    print(f"mixed: {info.iterations} its (fp64 {info64.iterations}), true rel res {true_rel:.2e}, "
+          f"||u-u64||/||u64|| {err:.2e}", flush=True)
+    assert err < 1e-7
+
+
+# ------------------------------------------------------------------ adjoint contraction
+def test_adjoint_contract_parity():
+    V = wl.deformed_box((3, 4, 3), 0.05)
+    N = 5
+    box = SemBox(V, N)
+    s = SemSolver(V, N=N, lambda_max=[2.0, 2.0])
+    lam = wl.uniform_noise(box.n, 8)
+    u = wl.uniform_noise(box.n, 9)
+    dG, df = s.adjoint_contract(dev(lam), dev(u))
+    ref = adjoint.contract(box, lam, u)
+    assert relmax(host(dG), ref) < 1e-13
+    assert relmax(host(df), box.mass() * lam) < 1e-15
+    G = s.factors()
+    assert relmax(host(G), box.G) < 1e-14
+
+
+@pytest.mark.parametrize("planes", [1, 2])
+def test_blocked_coarse_solve_parity(small_case, planes):
+    # the coarse order-1 solve split into blocks of z-planes (block-tridiagonal elimination)
+    V, N, lmax = small_case
+    ref = mg.sem_hierarchy(V, N, cheb.CHEB4, 2, 2, lmax=lmax)
+    s = SemSolver(V, N=N, smoother="cheb4", pre=2, post=2, lambda_max=lmax, coarse_planes=planes)
+    r = wl.uniform_noise(ref.levels[0].n, 6)
+    z = host(s.vcycle(dev(r)))
+    zo = ref.vcycle(r)
+    assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)

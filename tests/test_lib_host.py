@@ -1,0 +1,129 @@
+"""CPU checks of the native library: exported symbols, and the host-side setup
+(GLL data, geometric factors, diagonals, transfers, coarse operators, FD
+hierarchy, error codes) compared with the oracle. No GPU calls."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workload as wl
+from oracle import fd2d
+from oracle.gll import gll_nodes_weights, derivative_matrix, interpolation_matrix
+from oracle.sem import SemBox
+from paper_2210_03179_amd import _lib as L
+from paper_2210_03179_amd.solver import SemSolver, FdSolver, beta_table
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    header = open(os.path.join(ROOT, "include", "semcheb.h")).read()
+    declared = set(re.findall(r"\b(sem_[A-Za-z0-9_]+)\s*\(", header))
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(L.EXPORTS)
+
+
+def test_beta_table_matches_golden():
+    rows = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "beta_coef.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, i, v = line.split()
+            rows.setdefault(int(k), []).append(float(v))
+    for k, vals in rows.items():
+        assert beta_table(k) == vals
+    lib = L.load()
+    assert lib.sem_beta_table(17, (C.c_double * 17)()) == L.SEM_EINVAL
+
+
+@pytest.fixture(scope="module")
+def host_ctx():
+    V = wl.deformed_box((3, 2, 2), 0.05)
+    s = SemSolver(V, N=5, device=-1, lambda_max=[2.0, 2.0])
+    return V, s
+
+
+def test_host_levels_and_gll(host_ctx):
+    V, s = host_ctx
+    assert s.num_levels == 3
+    assert [s.level_info(j)[0] for j in range(3)] == [5, 2, 1]
+    for j, N in enumerate([5, 2, 1]):
+        x, w = gll_nodes_weights(N)
+        assert np.max(np.abs(s.host_array("gll_nodes", j) - x)) < 1e-15
+        assert np.max(np.abs(s.host_array("gll_weights", j) - w)) < 1e-15
+        assert np.max(np.abs(s.host_array("deriv", j) - derivative_matrix(N).ravel())) < 1e-13
+    assert np.max(np.abs(s.host_array("interp", 0) - interpolation_matrix(2, 5).ravel())) < 1e-15
+    assert np.max(np.abs(s.host_array("interp", 1) - interpolation_matrix(1, 2).ravel())) < 1e-15
+
+
+def test_host_geometry_matches_oracle(host_ctx):
+    V, s = host_ctx
+    for j, N in enumerate([5, 2, 1]):
+        box = SemBox(V, N)
+        G = s.host_array("factors", j).reshape(box.G.shape)
+        assert np.max(np.abs(G - box.G)) < 1e-14 * np.max(np.abs(box.G))
+        assert np.max(np.abs(s.host_array("diag", j) - box.diag())) < 1e-13 * np.max(box.diag())
+        assert np.max(np.abs(s.host_array("mass", j) - box.mass())) < 1e-15
+        assert np.max(np.abs(s.host_array("coords", j).reshape(-1, 3) - box.coords())) < 1e-15
+
+
+def test_host_coarse_matrix_matches_oracle(host_ctx):
+    V, s = host_ctx
+    box = SemBox(V, 1)
+    A = box.assemble().toarray()
+    Ah = s.host_array("coarse_matrix").reshape(box.n, box.n)
+    assert np.max(np.abs(Ah - A)) < 1e-14 * np.max(np.abs(A))
+
+
+def test_host_lambda_passthrough(host_ctx):
+    _, s = host_ctx
+    assert s.lambda_max() == [2.0, 2.0]
+
+
+def test_fd_host_hierarchy_matches_oracle():
+    s = FdSolver(n=32, Lx=2.0, factor=2, coarsest_n=4, device=-1, lambda_max=[1, 1, 1])
+    As, Ps, ns = fd2d.hierarchy_matrices(32, 2, 2.0, 1.0, coarsest_n=4)
+    assert s.num_levels == len(As)
+    for j, A in enumerate(As):
+        M = s.host_array("matrix", j).reshape(A.shape)
+        assert np.max(np.abs(M - A.toarray())) < 1e-12 * abs(A).max()
+    assert np.max(np.abs(s.host_array("coarse_matrix").reshape(As[-1].shape) - As[-1].toarray())) < 1e-10
+
+
+def test_error_codes():
+    V = wl.deformed_box(3, 0.05)
+    with pytest.raises(L.SemError) as e:
+        SemSolver(V, N=5, smoother="cheb4opt", pre=17, device=-1)
+    assert e.value.status == L.SEM_EINVAL
+    with pytest.raises(L.SemError) as e:
+        SemSolver(V, N=13, device=-1)
+    assert e.value.status == L.SEM_EINVAL
+    with pytest.raises(L.SemError) as e:
+        SemSolver(V, N=5, orders=[5, 3], device=-1)
+    assert e.value.status == L.SEM_EINVAL
+    with pytest.raises(L.SemError) as e:
+        SemSolver(wl.deformed_box((1, 2, 2), 0.05), N=3, device=-1)
+    assert e.value.status == L.SEM_EINVAL
+    with pytest.raises(L.SemError) as e:
+        SemSolver(V, N=5, pre=0, post=0, device=-1)
+    assert e.value.status == L.SEM_EINVAL
+    # an inverted element: swap two vertices of the lattice
+    bad = V.copy()
+    bad[1, 1, 1], bad[1, 1, 2] = V[1, 1, 2].copy(), V[1, 1, 1].copy()
+    with pytest.raises(L.SemError) as e:
+        SemSolver(bad, N=3, device=-1)
+    assert e.value.status == L.SEM_EMESH
+    with pytest.raises(L.SemError) as e:
+        FdSolver(n=64, factor=3, device=-1)
+    assert e.value.status == L.SEM_EINVAL
+
+
+def test_device_calls_on_host_context_fail_loudly(host_ctx):
+    _, s = host_ctx
+    lib = L.load()
+    st = lib.sem_apply_A(s._ctx, C.c_void_p(8), C.c_void_p(8), None)
+    assert st == L.SEM_ENODEV
