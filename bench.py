@@ -41,7 +41,37 @@ def parse():
     ap.add_argument("--order", type=int, default=7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="set up the FP64 and mixed contexts with fixed lambda_max and only launch the "
+                         "element-local operator --kernel-reps times each (short runs for profilers)")
     return ap.parse_args()
+
+
+def kernel_only(args):
+    import torch
+
+    import workload as wl
+    from paper_2210_03179_amd.solver import SemSolver
+    V = wl.deformed_box(args.m, 0.05)
+    lam = [2.0, 2.0]  # operator launches do not use lambda_max; skips the estimator's launches
+    s64 = SemSolver(V, N=args.order, precision="fp64", lambda_max=lam)
+    smx = SemSolver(V, N=args.order, precision="mixed", lambda_max=lam)
+    n, nloc = s64.n, s64.n_local
+    u = torch.rand(n, dtype=torch.float64, device="cuda")
+    w = torch.empty(nloc, dtype=torch.float64, device="cuda")
+    u32, w32 = u.float(), torch.empty(nloc, dtype=torch.float32, device="cuda")
+    t64 = time_kernel(lambda: s64.apply_local(u, w), args.kernel_reps)
+    tmx = time_kernel(lambda: smx.apply_local(u32, w32), args.kernel_reps)
+    # plain device copy of a known size (1 GiB read + 1 GiB written per launch): the reference
+    # against which the profiler's FETCH_SIZE / WRITE_SIZE counters are scaled
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    tcp = time_kernel(lambda: dst.copy_(src), 3)
+    print(json.dumps({"kernel_only": True, "unknowns": n, "local_nodes": nloc,
+                      "copy_bytes": 2 * src.numel() * 8, "copy_us": tcp * 1e6,
+                      "copy_GBs": 2 * src.numel() * 8 / tcp / 1e9,
+                      "ax_fp64_us": t64 * 1e6, "ax_fp64_GBs": (56.0 * nloc + 8.0 * n) / t64 / 1e9,
+                      "ax_bf16_us": tmx * 1e6, "ax_bf16_GBs": (16.0 * nloc + 4.0 * n) / tmx / 1e9}), flush=True)
 
 
 def log(msg):
@@ -110,6 +140,9 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
+    if args.kernel_only:
+        kernel_only(args)
+        return
     m, N = args.m, args.order
     V = wl.deformed_box(m, 0.05)
     t0 = time.perf_counter()

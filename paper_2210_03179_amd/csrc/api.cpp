@@ -202,23 +202,21 @@ void coarse_solve64(sem_ctx *c, const double *b, double *x, hipStream_t s) {
     return;
   }
   const int nb = (int)C.start.size() - 1;
-  double *y = C.y, *t = C.t;
-  // forward: y_0 = b_0, y_b = b_b - L_b y_{b-1}
-  hipMemcpyAsync(y, b, (C.start[1] - C.start[0]) * sizeof(double), hipMemcpyDeviceToDevice, s);
+  // forward: y_0 = b_0 (read in place), y_b = b_b - L_b y_{b-1}
+  auto yb = [&](int q) { return (q == 0 ? b : (const double *)C.y) + C.start[q]; };
   for (int q = 1; q < nb; ++q) {
     const int64_t P = C.start[q + 1] - C.start[q], Pp = C.start[q] - C.start[q - 1];
-    launch_gemv(P, Pp, C.Lb[q], y + C.start[q - 1], b + C.start[q], y + C.start[q], 1, s);
+    launch_gemv(P, Pp, C.Lb[q], yb(q - 1), b + C.start[q], C.y + C.start[q], 1, s);
   }
-  // backward: x_last = M y_last, x_b = M_b (y_b - U_b x_{b+1})
+  // backward: x_last = S^{-1} y_last, x_b = S_b^{-1} y_b - W_b x_{b+1}
   {
     const int q = nb - 1;
     const int64_t P = C.start[q + 1] - C.start[q];
-    launch_gemv(P, P, C.Mb[q], y + C.start[q], nullptr, x + C.start[q], 0, s);
+    launch_gemv(P, P, C.Mb[q], yb(q), nullptr, x + C.start[q], 0, s);
   }
   for (int q = nb - 2; q >= 0; --q) {
-    const int64_t P = C.start[q + 1] - C.start[q];
-    launch_csr<double>(C.Ub[q], C.Ub[q].val64, x + C.start[q + 1], y + C.start[q], t + C.start[q], 1, s);
-    launch_gemv(P, P, C.Mb[q], t + C.start[q], nullptr, x + C.start[q], 0, s);
+    const int64_t P = C.start[q + 1] - C.start[q], Pn = C.start[q + 2] - C.start[q + 1];
+    launch_gemv2(P, P, C.Mb[q], yb(q), Pn, C.Wb[q], x + C.start[q + 1], x + C.start[q], s);
   }
 }
 
@@ -264,18 +262,25 @@ void vcycle(sem_ctx *c, int j, hipStream_t s) {
     launch_csr<T>(L.R, V<T>::val(L.R), r, (const T *)nullptr, V<T>::b(C), 0, s);
   }
   vcycle<T>(c, j + 1, s);
-  if (L.type == LVL_SEM) launch_prolong<T>(L, C, V<T>::x(C), V<T>::J(L), x, s);
+  // a one-sided mixed cycle ends with this prolongation on the finest level: it
+  // writes the widened result z directly (c->zout) instead of updating x
+  double *zout = (j == 0 && post == 0) ? c->zout : nullptr;
+  if (L.type == LVL_SEM) launch_prolong<T>(L, C, V<T>::x(C), V<T>::J(L), x, zout, s);
   else launch_csr<T>(L.P, V<T>::val(L.P), V<T>::x(C), (const T *)nullptr, x, 2, s);
   if (post > 0) smooth<T>(c, L, post, false, s);
 }
 
-// z = M^{-1} r through the context's precision.
-void vcycle_top(sem_ctx *c, const double *r, double *z, hipStream_t s) {
+// z = M^{-1} r through the context's precision. In mixed precision the single-
+// precision copy of r may already be in place (r32_ready, written by the Krylov update).
+void vcycle_top(sem_ctx *c, const double *r, double *z, hipStream_t s, bool r32_ready = false) {
   Level &L0 = c->levels[0];
   if (c->opt.precision == SEM_MIXED) {
-    launch_convert(L0.n, r, L0.b32, s);
+    if (!r32_ready) launch_convert(L0.n, r, L0.b32, s);
+    const bool fused_out = c->opt.post_order == 0 && L0.type == LVL_SEM && c->levels.size() > 1;
+    c->zout = fused_out ? z : nullptr;
     vcycle<float>(c, 0, s);
-    launch_convert(L0.n, L0.x32, z, s);
+    c->zout = nullptr;
+    if (!fused_out) launch_convert(L0.n, L0.x32, z, s);
   } else {
     double *sb = L0.b64, *sx = L0.x64;
     L0.b64 = const_cast<double *>(r);
@@ -292,11 +297,14 @@ void fine_apply(sem_ctx *c, const double *u, double *w, const double *p, hipStre
   L0.applies++;
   if (L0.type == LVL_SEM) {
     launch_ax(L0, u, L0.w64, s);
-    if (p) launch_dss_dot(L0, L0.w64, w, p, c->partials, kReduceBlocks, s);
+    if (p) c->npartials = launch_dss_dot(L0, L0.w64, w, p, c->partials, s);
     else launch_dss<double>(L0, L0.w64, w, s);
   } else {
     launch_csr<double>(L0.A, L0.A.val64, u, nullptr, w, 0, s);
-    if (p) launch_dots<double>(L0.n, 1, p, w, nullptr, nullptr, nullptr, nullptr, c->partials, kReduceBlocks, s);
+    if (p) {
+      launch_dots<double>(L0.n, 1, p, w, nullptr, nullptr, nullptr, nullptr, c->partials, kReduceBlocks, s);
+      c->npartials = kReduceBlocks;
+    }
   }
 }
 
@@ -397,7 +405,7 @@ sem_status alloc_krylov(sem_ctx *c, int64_t n) {
   TRY(dalloc(c, &c->kp, n));
   TRY(dalloc(c, &c->kw, n));
   TRY(dalloc(c, &c->scal, S_COUNT));
-  TRY(dalloc(c, &c->partials, (size_t)kReduceBlocks * 3));
+  TRY(dalloc(c, &c->partials, std::max<size_t>((size_t)kReduceBlocks * 3, (size_t)(n / 256 + 2))));
   HIPCHK(c, hipHostMalloc((void **)&c->pinned, S_COUNT * sizeof(double), hipHostMallocDefault));
   return SEM_OK;
 }
@@ -444,6 +452,11 @@ sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipS
     return SEM_EINVAL;
   }
   if (opt->N < 1 || opt->N > 12) { c->err = "order N must lie in 1..12"; return SEM_EINVAL; }
+  if ((int64_t)(mesh->nex * (int64_t)opt->N) * (mesh->ney * (int64_t)opt->N) * (mesh->nez * (int64_t)opt->N) >=
+      (int64_t(1) << 31)) {
+    c->err = "more than 2^31 unknowns per system";
+    return SEM_EINVAL;
+  }
   std::vector<int> orders;
   if (opt->num_levels == 0) {
     orders.push_back(opt->N);
@@ -554,11 +567,11 @@ sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipS
       const int nb = (int)start.size() - 1;
       C.Mb.assign(nb, nullptr);
       C.Lb.assign(nb, nullptr);
-      C.Ub.assign(nb, DevCsr{});
+      C.Wb.assign(nb, nullptr);
       for (int q = 0; q < nb; ++q) {
         TRY(upload(c, &C.Mb[q], bt.Minv[q].data(), bt.Minv[q].size(), s));
         if (q > 0) TRY(upload(c, &C.Lb[q], bt.Lmat[q].data(), bt.Lmat[q].size(), s));
-        if (q + 1 < nb) TRY(upload_csr(c, C.Ub[q], bt.Up[q], false, s));
+        if (q + 1 < nb) TRY(upload(c, &C.Wb[q], bt.Wmat[q].data(), bt.Wmat[q].size(), s));
         HIPCHK(c, hipStreamSynchronize(s));
       }
     }
@@ -781,6 +794,7 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
   if (!b || !u || maxit < 0 || !(rtol >= 0)) { c->err = "invalid solve arguments"; return SEM_EINVAL; }
   const int64_t n = c->levels[0].n;
   const bool flexible = c->opt.krylov == SEM_FCG;
+  const bool mixed = c->opt.precision == SEM_MIXED && c->kind == LVL_SEM;
   double *r = c->kr, *r2 = c->kr2, *z = c->kz, *p = c->kp, *w = c->kw;
   if (iters) *iters = 0;
   if (relres) *relres = 0.0;
@@ -819,8 +833,8 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
   int it = 0;
   for (it = 1; it <= maxit; ++it) {
     fine_apply(c, p, w, p, s);
-    launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_PW, FIN_NONE, s);
-    launch_update_xr(n, c->scal, u, p, r, w, r2, c->partials, kReduceBlocks, s);
+    launch_finalize(c->npartials, 1, c->partials, c->scal, S_PW, FIN_NONE, s);
+    launch_update_xr(n, c->scal, u, p, r, w, r2, c->partials, kReduceBlocks, mixed ? c->levels[0].b32 : nullptr, s);
     launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_RR, FIN_NONE, s);
     TRY(read_scalars(c, s));
     const double rz = c->pinned[S_RZ], pw = c->pinned[S_PW], rr = c->pinned[S_RR];
@@ -844,7 +858,7 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
       break;
     }
     if (it == maxit) break;
-    vcycle_top(c, r, z, s);
+    vcycle_top(c, r, z, s, mixed);
     if (flexible) {
       launch_dots<double>(n, 2, z, r, z, r2, nullptr, nullptr, c->partials, kReduceBlocks, s);
       launch_finalize(kReduceBlocks, 2, c->partials, c->scal, S_ZR, FIN_BETA_FCG, s);

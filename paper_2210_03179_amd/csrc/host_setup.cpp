@@ -395,6 +395,25 @@ bool block_tridiag_factor(const Csr &A, const std::vector<int64_t> &start, Block
     out.Minv[b] = std::move(S);
     if (b + 1 < nb) out.Up[b] = extract(b, b + 1);
   }
+  // W_b = S_b^{-1} A_{b,b+1} (dense), so that x_b = S_b^{-1} y_b - W_b x_{b+1}
+  out.Wmat.assign(nb, {});
+  for (int b = 0; b + 1 < nb; ++b) {
+    const int64_t Pb = start[b + 1] - start[b], Pn = start[b + 2] - start[b + 1];
+    const Csr &U = out.Up[b];
+    const std::vector<double> &M = out.Minv[b];
+    std::vector<double> &W = out.Wmat[b];
+    W.assign((size_t)Pb * Pn, 0.0);
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < Pb; ++r) {
+      const double *Mrow = &M[(size_t)r * Pb];
+      double *Wrow = &W[(size_t)r * Pn];
+      for (int64_t q = 0; q < Pb; ++q) {
+        const double m = Mrow[q];
+        if (m == 0.0) continue;
+        for (int64_t p = U.rowptr[q]; p < U.rowptr[q + 1]; ++p) Wrow[U.col[p]] += m * U.val[p];
+      }
+    }
+  }
   return true;
 }
 

@@ -51,6 +51,7 @@ struct BlockTri {
   std::vector<int64_t> start;               // block b covers [start[b], start[b+1])
   std::vector<std::vector<double>> Minv;    // S_b^{-1}, dense row-major
   std::vector<std::vector<double>> Lmat;    // A_{b,b-1} S_{b-1}^{-1}, dense (b >= 1)
+  std::vector<std::vector<double>> Wmat;    // S_b^{-1} A_{b,b+1}, dense (b < nb-1)
   std::vector<Csr> Up;                      // A_{b,b+1} (rows of b, cols local to b+1)
 };
 bool block_tridiag_factor(const Csr &A, const std::vector<int64_t> &start, BlockTri &out,
@@ -114,8 +115,7 @@ struct CoarseSolver {
   double *Minv = nullptr;
   // block tridiagonal
   std::vector<int64_t> start;
-  std::vector<double *> Mb, Lb;
-  std::vector<DevCsr> Ub;
+  std::vector<double *> Mb, Lb, Wb;
   double *b = nullptr, *y = nullptr, *x = nullptr, *t = nullptr;
   std::vector<double> host_dense;  // small problems: assembled matrix for inspection
 };
@@ -136,8 +136,9 @@ struct sem_ctx {
   double *kr = nullptr, *kr2 = nullptr, *kz = nullptr, *kp = nullptr, *kw = nullptr;
   double *scal = nullptr;      // device scalars
   double *partials = nullptr;  // reduction partials
+  int npartials = 0;           // partials written by the last fused apply
   double *pinned = nullptr;    // host-pinned scalar mirror
-  float *vin32 = nullptr;      // mixed-precision V-cycle input
+  double *zout = nullptr;      // set during a mixed one-sided cycle: widened output target
   std::string err;
   std::vector<void *> allocations;
 };

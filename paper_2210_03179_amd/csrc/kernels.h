@@ -30,8 +30,9 @@ bool launch_ax(const Level &L, const double *u, double *wL, hipStream_t s);
 bool launch_ax(const Level &L, const float *u, float *wL, hipStream_t s);
 template <typename T>
 void launch_dss(const Level &L, const T *wL, T *out, hipStream_t s);
-void launch_dss_dot(const Level &L, const double *wL, double *out, const double *p, double *partials,
-                    int nblocks, hipStream_t s);
+// out = DSS(wL) and per-block partials of p . out; returns the number of partials written
+int launch_dss_dot(const Level &L, const double *wL, double *out, const double *p, double *partials,
+                   hipStream_t s);
 template <typename T>
 void launch_cheb(const Level &L, const T *wsrc, const T *b, const T *r_in, T *r_out, T *d, T *x,
                  const T *invdiag, double a, double bc, double c, int flags, int mode, hipStream_t s);
@@ -40,18 +41,21 @@ void launch_resid_weight(const Level &L, const T *wL, const T *b, T *rw, hipStre
 template <typename T>
 void launch_restrict(const Level &F, const Level &C, const T *rw, const T *J, T *rcL, hipStream_t s);
 template <typename T>
-void launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *xf, hipStream_t s);
+void launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *xf, double *zout, hipStream_t s);
 template <typename T>
 void launch_csr(const DevCsr &A, const T *val, const T *x, const T *b, T *y, int mode, hipStream_t s);
 void launch_gemv(int64_t nrows, int64_t ncols, const double *M, const double *x, const double *b, double *y,
                  int sub, hipStream_t s);
+// y = M1 x1 - M2 x2 (dense row-major, nrows rows)
+void launch_gemv2(int64_t nrows, int64_t n1c, const double *M1, const double *x1, int64_t n2c, const double *M2,
+                  const double *x2, double *y, hipStream_t s);
 template <typename T>
 void launch_dots(int64_t n, int nd, const T *x0, const T *y0, const T *x1, const T *y1, const T *x2,
                  const T *y2, double *partials, int nblocks, hipStream_t s);
 void launch_finalize(int nblocks, int nd, const double *partials, double *scal, int slot, int op,
                      hipStream_t s);
 void launch_update_xr(int64_t n, const double *scal, double *x, const double *p, const double *r,
-                      const double *w, double *rnew, double *partials, int nblocks, hipStream_t s);
+                      const double *w, double *rnew, double *partials, int nblocks, float *r32, hipStream_t s);
 void launch_update_p(int64_t n, const double *scal, const double *z, double *p, hipStream_t s);
 void launch_convert(int64_t n, const double *in, float *out, hipStream_t s);
 void launch_convert(int64_t n, const float *in, double *out, hipStream_t s);

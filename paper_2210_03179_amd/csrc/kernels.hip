@@ -46,12 +46,29 @@ __device__ __forceinline__ int copies_1d(int I, int N, int *el, int *loc) {
   return 1;
 }
 
-// Sum of the element-local copies of unknown g (direct stiffness summation).
+// Lattice coordinates (1-based) of unknown g; 32-bit arithmetic (n < 2^31 is checked at setup).
+struct Ijk {
+  int I, J, K;
+};
+__device__ __forceinline__ Ijk ijk_of(const Box &b, int64_t g) {
+  const unsigned gg = (unsigned)g, nx = (unsigned)b.nx, ny = (unsigned)b.ny;
+  const unsigned q = gg / nx;
+  return Ijk{(int)(gg - q * nx) + 1, (int)(q % ny) + 1, (int)(q / ny) + 1};
+}
+__device__ __forceinline__ void ijk_next(const Box &b, Ijk &c) {
+  if (++c.I > b.nx) {
+    c.I = 1;
+    if (++c.J > b.ny) {
+      c.J = 1;
+      ++c.K;
+    }
+  }
+}
+
+// Sum of the element-local copies of the unknown at lattice point c (direct stiffness summation).
 template <typename T>
-__device__ __forceinline__ T dss_at(const T *__restrict__ wL, const Box &b, int64_t g) {
-  const int I = (int)(g % b.nx) + 1;
-  const int J = (int)((g / b.nx) % b.ny) + 1;
-  const int K = (int)(g / ((int64_t)b.nx * b.ny)) + 1;
+__device__ __forceinline__ T dss_ijk(const T *__restrict__ wL, const Box &b, const Ijk &c) {
+  const int I = c.I, J = c.J, K = c.K;
   int exs[2], is[2], eys[2], js[2], ezs[2], ks[2];
   const int cx = copies_1d(I, b.N, exs, is);
   const int cy = copies_1d(J, b.N, eys, js);
@@ -68,21 +85,58 @@ __device__ __forceinline__ T dss_at(const T *__restrict__ wL, const Box &b, int6
   return s;
 }
 
-// 1 / (number of element copies) of unknown g: a power of two, so exact.
-__device__ __forceinline__ double inv_mult(const Box &b, int64_t g) {
-  const int I = (int)(g % b.nx) + 1;
-  const int J = (int)((g / b.nx) % b.ny) + 1;
-  const int K = (int)(g / ((int64_t)b.nx * b.ny)) + 1;
+template <typename T>
+__device__ __forceinline__ T dss_at(const T *__restrict__ wL, const Box &b, int64_t g) {
+  return dss_ijk(wL, b, ijk_of(b, g));
+}
+
+// 1 / (number of element copies) of an unknown: a power of two, so exact.
+__device__ __forceinline__ double inv_mult_ijk(const Box &b, const Ijk &c) {
   int m = 1;
-  if (I % b.N == 0) m *= 2;
-  if (J % b.N == 0) m *= 2;
-  if (K % b.N == 0) m *= 2;
+  if (c.I % b.N == 0) m *= 2;
+  if (c.J % b.N == 0) m *= 2;
+  if (c.K % b.N == 0) m *= 2;
   return 1.0 / m;
+}
+__device__ __forceinline__ double inv_mult(const Box &b, int64_t g) { return inv_mult_ijk(b, ijk_of(b, g)); }
+
+// VEC consecutive elements of a vector as one 16-byte access.
+template <typename T, int VEC>
+struct Pack {
+  T v[VEC];
+};
+template <typename T, int VEC>
+__device__ __forceinline__ Pack<T, VEC> ld(const T *__restrict__ p) {
+  typedef T vt __attribute__((ext_vector_type(VEC)));
+  const vt x = *reinterpret_cast<const vt *>(p);
+  Pack<T, VEC> r;
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) r.v[q] = x[q];
+  return r;
+}
+template <typename T, int VEC>
+__device__ __forceinline__ void st(T *__restrict__ p, const Pack<T, VEC> &r) {
+  typedef T vt __attribute__((ext_vector_type(VEC)));
+  vt x;
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) x[q] = r.v[q];
+  *reinterpret_cast<vt *>(p) = x;
 }
 
 __device__ __forceinline__ int64_t lattice_index(const Box &b, int I, int J, int K) {
   if (I < 1 || I > b.nx || J < 1 || J > b.ny || K < 1 || K > b.nz) return -1;
   return (I - 1) + (int64_t)b.nx * ((J - 1) + (int64_t)b.ny * (K - 1));
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on XCD
+// b mod 8). Remap so that XCD x processes the contiguous chunk x of the logical
+// block range: neighbouring elements, which share face values of the input,
+// then meet in the same L2. The tail beyond a multiple of 8 keeps identity order.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+  constexpr unsigned kXcd = 8;
+  const unsigned full = nb - nb % kXcd;
+  if (b >= full) return b;
+  return (b % kXcd) * (full / kXcd) + b / kXcd;
 }
 
 // ------------------------------------------------------------------ operator (element-local)
@@ -111,12 +165,13 @@ ax_local_kernel(Box b, int64_t E, const T *__restrict__ u, const GT *__restrict_
   const int le = t / S::tpe;
   const int ij = t - le * S::tpe;
   const int i = ij % n1, j = ij / n1;
-  const int64_t e = (int64_t)blockIdx.x * S::epb + le;
+  const int64_t e = (int64_t)xcd_block(blockIdx.x, gridDim.x) * S::epb + le;
   const bool active = (le < S::epb) && (e < E);
   for (int q = t; q < n1 * n1; q += S::block) sD[q] = Dm[q];
 
   T ureg[n1], wreg[n1];
-  T Di[n1], Dj[n1], DTi[n1], DTj[n1];
+  T Di[n1], Dj[n1];
+  [[maybe_unused]] T DTi[n1], DTj[n1];
   int ex = 0, ey = 0, ez = 0;
   if (active) {
     ex = (int)(e % b.nex);
@@ -138,31 +193,47 @@ ax_local_kernel(Box b, int64_t E, const T *__restrict__ u, const GT *__restrict_
   for (int l = 0; l < n1; ++l) {
     Di[l] = sD[i * n1 + l];
     Dj[l] = sD[j * n1 + l];
-    DTi[l] = sD[l * n1 + i];
-    DTj[l] = sD[l * n1 + j];
+    if constexpr (sizeof(T) == 4) {
+      DTi[l] = sD[l * n1 + i];
+      DTj[l] = sD[l * n1 + j];
+    }
   }
-  const GT *Ge = G + (active ? e : 0) * 6 * n3;
+  const GT *Ge = G + (active ? e : 0) * 6 * n3 + j * n1 + i;
   const int lec = active ? le : 0;
-#pragma unroll
+  // factors of plane 0; the loop prefetches plane k+1 while computing plane k
+  T g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0;
+  if (active) {
+    g0 = load_factor<GT, T>(Ge + 0 * n3);
+    g1 = load_factor<GT, T>(Ge + 1 * n3);
+    g2 = load_factor<GT, T>(Ge + 2 * n3);
+    g3 = load_factor<GT, T>(Ge + 3 * n3);
+    g4 = load_factor<GT, T>(Ge + 4 * n3);
+    g5 = load_factor<GT, T>(Ge + 5 * n3);
+  }
+#pragma unroll 1
   for (int k = 0; k < n1; ++k) {
-    if (active) su[lec][j][i] = ureg[k];
+    // register arrays are only indexed with compile-time indices (selects on k)
+    T uk = ureg[0];
+#pragma unroll
+    for (int l = 1; l < n1; ++l) uk = (l == k) ? ureg[l] : uk;
+    if (active) su[lec][j][i] = uk;
+    T h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0, h5 = 0;
+    if (active && k + 1 < n1) {
+      const int qn = (k + 1) * n1 * n1;
+      h0 = load_factor<GT, T>(Ge + 0 * n3 + qn);
+      h1 = load_factor<GT, T>(Ge + 1 * n3 + qn);
+      h2 = load_factor<GT, T>(Ge + 2 * n3 + qn);
+      h3 = load_factor<GT, T>(Ge + 3 * n3 + qn);
+      h4 = load_factor<GT, T>(Ge + 4 * n3 + qn);
+      h5 = load_factor<GT, T>(Ge + 5 * n3 + qn);
+    }
     __syncthreads();
     T ur = 0, us = 0, ut = 0;
 #pragma unroll
     for (int l = 0; l < n1; ++l) {
       ur += Di[l] * su[lec][j][l];
       us += Dj[l] * su[lec][l][i];
-      ut += sD[k * n1 + l] * ureg[l];
-    }
-    const int q = (k * n1 + j) * n1 + i;
-    T g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0;
-    if (active) {
-      g0 = load_factor<GT, T>(Ge + 0 * n3 + q);
-      g1 = load_factor<GT, T>(Ge + 1 * n3 + q);
-      g2 = load_factor<GT, T>(Ge + 2 * n3 + q);
-      g3 = load_factor<GT, T>(Ge + 3 * n3 + q);
-      g4 = load_factor<GT, T>(Ge + 4 * n3 + q);
-      g5 = load_factor<GT, T>(Ge + 5 * n3 + q);
+      ut += Dm[k * n1 + l] * ureg[l];  // wave-uniform: scalar loads
     }
     const T wr = g0 * ur + g1 * us + g2 * ut;
     const T ws = g1 * ur + g3 * us + g4 * ut;
@@ -174,10 +245,13 @@ ax_local_kernel(Box b, int64_t E, const T *__restrict__ u, const GT *__restrict_
     __syncthreads();
     T acc = 0;
 #pragma unroll
-    for (int l = 0; l < n1; ++l) acc += DTi[l] * sr[lec][j][l] + DTj[l] * ss[lec][l][i];
-    wreg[k] += acc;
+    for (int l = 0; l < n1; ++l) {
+      if constexpr (sizeof(T) == 4) acc += DTi[l] * sr[lec][j][l] + DTj[l] * ss[lec][l][i];
+      else acc += sD[l * n1 + i] * sr[lec][j][l] + sD[l * n1 + j] * ss[lec][l][i];
+    }
 #pragma unroll
-    for (int l = 0; l < n1; ++l) wreg[l] += sD[k * n1 + l] * wt;
+    for (int l = 0; l < n1; ++l) wreg[l] += ((l == k) ? acc : T(0)) + Dm[k * n1 + l] * wt;
+    g0 = h0; g1 = h1; g2 = h2; g3 = h3; g4 = h4; g5 = h5;
     __syncthreads();
   }
   if (active) {
@@ -194,12 +268,6 @@ __global__ void dss_kernel(Box b, int64_t n, const T *__restrict__ wL, T *__rest
   if (g < n) out[g] = dss_at(wL, b, g);
 }
 
-// out = DSS(wL) with a per-block partial of sum p*out (for p . A p).
-template <typename T>
-__global__ void __launch_bounds__(256)
-dss_dot_kernel(Box b, int64_t n, const T *__restrict__ wL, T *__restrict__ out,
-               const T *__restrict__ p, double *__restrict__ partials);
-
 // Block reduction of one double to thread 0 (fixed order).
 __device__ __forceinline__ double block_sum(double v, double *sm) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -213,17 +281,32 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
   return s;
 }
 
-template <typename T>
+// One thread per VEC consecutive unknowns (no grid-stride loop: every load of a
+// thread is independent of the others), one partial per block.
+template <typename T, int VEC>
 __global__ void __launch_bounds__(256)
 dss_dot_kernel(Box b, int64_t n, const T *__restrict__ wL, T *__restrict__ out,
                const T *__restrict__ p, double *__restrict__ partials) {
   __shared__ double sm[4];
   double acc = 0.0;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    const T v = dss_at(wL, b, g);
-    out[g] = v;
-    acc += (double)p[g] * (double)v;
+  const int64_t g0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  if (g0 < n) {
+    const bool full = g0 + VEC <= n;
+    Pack<T, VEC> pv, ov;
+    if (full) pv = ld<T, VEC>(p + g0);
+    else
+      for (int q = 0; q < VEC; ++q) pv.v[q] = g0 + q < n ? p[g0 + q] : T(0);
+    Ijk cc = ijk_of(b, g0);
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      ov.v[q] = (g0 + q < n) ? dss_ijk(wL, b, cc) : T(0);
+      acc += (double)pv.v[q] * (double)ov.v[q];
+      ijk_next(b, cc);
+    }
+    if (full) st<T, VEC>(out + g0, ov);
+    else
+      for (int q = 0; q < VEC; ++q)
+        if (g0 + q < n) out[g0 + q] = ov.v[q];
   }
   const double s = block_sum(acc, sm);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -234,39 +317,99 @@ dss_dot_kernel(Box b, int64_t n, const T *__restrict__ wL, T *__restrict__ out,
 //   if SUB_AD:  rr -= (mode 1 ? invdiag * Ad : Ad)
 //   dd = (D_INIT ? 0 : d) * a + bc * (mode 4 ? invdiag * rr : rr)
 //   x  = (X_INIT ? 0 : x) + c * dd
-template <typename T, bool SEM>
+// One thread updates VEC consecutive unknowns (16-byte accesses of the plain
+// vectors); the last thread handles a partial pack element by element.
+template <typename T, bool SEM, int VEC>
 __global__ void __launch_bounds__(256)
 cheb_kernel(Box b, int64_t n, const T *__restrict__ wsrc, const T *__restrict__ bvec,
             const T *__restrict__ r_in, T *__restrict__ r_out, T *__restrict__ d,
             T *__restrict__ x, const T *__restrict__ invdiag, T a, T bc, T c, int flags,
             int mode) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const T s = invdiag[g];
-  T rr = (flags & CHEB_R_FROM_B) ? bvec[g] : r_in[g];
-  if (flags & CHEB_S_ON_R) rr = s * rr;
-  if (flags & CHEB_SUB_AD) {
-    const T ad = SEM ? dss_at(wsrc, b, g) : wsrc[g];
-    rr = (mode == 1) ? rr - s * ad : rr - ad;
+  const int64_t g0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  if (g0 >= n) return;
+  const bool full = g0 + VEC <= n;
+  const int cnt = full ? VEC : (int)(n - g0);
+  const T *rsrc = (flags & CHEB_R_FROM_B) ? bvec : r_in;
+  Pack<T, VEC> s, rr, dd, xx, ad;
+  if (full) {
+    s = ld<T, VEC>(invdiag + g0);
+    rr = ld<T, VEC>(rsrc + g0);
+    if (!(flags & CHEB_D_INIT)) dd = ld<T, VEC>(d + g0);
+    if (!(flags & CHEB_X_INIT)) xx = ld<T, VEC>(x + g0);
+    if (!SEM && (flags & CHEB_SUB_AD)) ad = ld<T, VEC>(wsrc + g0);
+  } else {
+    for (int q = 0; q < cnt; ++q) {
+      s.v[q] = invdiag[g0 + q];
+      rr.v[q] = rsrc[g0 + q];
+      if (!(flags & CHEB_D_INIT)) dd.v[q] = d[g0 + q];
+      if (!(flags & CHEB_X_INIT)) xx.v[q] = x[g0 + q];
+      if (!SEM && (flags & CHEB_SUB_AD)) ad.v[q] = wsrc[g0 + q];
+    }
   }
-  if (flags & CHEB_WRITE_R) r_out[g] = rr;
-  T dd = (flags & CHEB_D_INIT) ? T(0) : a * d[g];
-  dd = dd + bc * (mode == 4 ? s * rr : rr);
-  d[g] = dd;
-  const T xx = (flags & CHEB_X_INIT) ? T(0) : x[g];
-  x[g] = xx + c * dd;
+  if (SEM && (flags & CHEB_SUB_AD)) {
+    Ijk cc = ijk_of(b, g0);
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      if (q < cnt) ad.v[q] = dss_ijk(wsrc, b, cc);
+      ijk_next(b, cc);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) {
+    T r = rr.v[q];
+    if (flags & CHEB_S_ON_R) r = s.v[q] * r;
+    if (flags & CHEB_SUB_AD) r = (mode == 1) ? r - s.v[q] * ad.v[q] : r - ad.v[q];
+    rr.v[q] = r;
+    T dn = (flags & CHEB_D_INIT) ? T(0) : a * dd.v[q];
+    dn = dn + bc * (mode == 4 ? s.v[q] * r : r);
+    dd.v[q] = dn;
+    const T xo = (flags & CHEB_X_INIT) ? T(0) : xx.v[q];
+    xx.v[q] = xo + c * dn;
+  }
+  if (full) {
+    if (flags & CHEB_WRITE_R) st<T, VEC>(r_out + g0, rr);
+    st<T, VEC>(d + g0, dd);
+    st<T, VEC>(x + g0, xx);
+  } else {
+    for (int q = 0; q < cnt; ++q) {
+      if (flags & CHEB_WRITE_R) r_out[g0 + q] = rr.v[q];
+      d[g0 + q] = dd.v[q];
+      x[g0 + q] = xx.v[q];
+    }
+  }
 }
 
 // rw = (b - DSS(wL)) / multiplicity  (or b / multiplicity when wL is null): the
 // weighted residual W_f r_f that the restriction P^T consumes.
-template <typename T>
-__global__ void resid_weight_kernel(Box b, int64_t n, const T *__restrict__ wL,
-                                    const T *__restrict__ bvec, T *__restrict__ rw) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  T r = bvec[g];
-  if (wL) r -= dss_at(wL, b, g);
-  rw[g] = r * (T)inv_mult(b, g);
+template <typename T, int VEC>
+__global__ void __launch_bounds__(256)
+resid_weight_kernel(Box b, int64_t n, const T *__restrict__ wL, const T *__restrict__ bvec,
+                    T *__restrict__ rw) {
+  const int64_t g0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  if (g0 >= n) return;
+  const bool full = g0 + VEC <= n;
+  const int cnt = full ? VEC : (int)(n - g0);
+  Pack<T, VEC> r;
+  if (full) {
+    r = ld<T, VEC>(bvec + g0);
+  } else {
+    for (int q = 0; q < cnt; ++q) r.v[q] = bvec[g0 + q];
+  }
+  Ijk cc = ijk_of(b, g0);
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) {
+    if (q < cnt) {
+      T v = r.v[q];
+      if (wL) v -= dss_ijk(wL, b, cc);
+      r.v[q] = v * (T)inv_mult_ijk(b, cc);
+    }
+    ijk_next(b, cc);
+  }
+  if (full) {
+    st<T, VEC>(rw + g0, r);
+  } else {
+    for (int q = 0; q < cnt; ++q) rw[g0 + q] = r.v[q];
+  }
 }
 
 // FD: residual r = b - Ad (plain global vectors)
@@ -331,7 +474,7 @@ restrict_kernel(Box fb, Box cb, int64_t E, const T *__restrict__ rw, const T *__
 template <typename T>
 __global__ void __launch_bounds__(256)
 prolong_kernel(Box fb, Box cb, int64_t E, const T *__restrict__ xc, const T *__restrict__ Jm,
-               T *__restrict__ xf) {
+               T *__restrict__ xf, double *__restrict__ zout) {
   const int nf = fb.N + 1, nc = cb.N + 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *sJ = reinterpret_cast<T *>(smem_raw);      // nf*nc
@@ -370,7 +513,8 @@ prolong_kernel(Box fb, Box cb, int64_t E, const T *__restrict__ xc, const T *__r
     if (g < 0) continue;
     T s = 0;
     for (int c = 0; c < nc; ++c) s += sJ[k * nc + c] * t2[(c * nf + j) * nf + i];
-    xf[g] += s;
+    if (zout) zout[g] = (double)(xf[g] + s);  // last step of a cycle: widened result only
+    else xf[g] += s;
   }
 }
 
@@ -389,18 +533,46 @@ __global__ void csr_kernel(int64_t nrows, const int64_t *__restrict__ rp, const 
   else y[r] += s;
 }
 
-// Dense row-major y = M x (sub = 0) or y = b - M x (sub = 1); one wave per row.
+// Dense row-major products of the coarse solve, one 256-thread block per row:
+//   y = M1 x1 - M2 x2 (M2 optional), then y = b - y when sub = 1.
+// Each thread issues its (up to kGemvUnroll) loads per matrix before summing, so a
+// whole row is in flight at once; rows are short (about 1e3 entries) and the
+// solve chains dozens of these products, so latency rather than bandwidth decides.
+constexpr int kGemvUnroll = 8;
 __global__ void __launch_bounds__(256)
-gemv_kernel(int64_t nrows, int64_t ncols, const double *__restrict__ M, const double *__restrict__ x,
+gemv_kernel(int64_t nrows, int64_t n1c, const double *__restrict__ M1, const double *__restrict__ x1,
+            int64_t n2c, const double *__restrict__ M2, const double *__restrict__ x2,
             const double *__restrict__ bvec, double *__restrict__ y, int sub) {
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  __shared__ double sm[4];
+  const int64_t row = blockIdx.x;
   if (row >= nrows) return;
-  const double *Mr = M + row * ncols;
-  double s = 0.0;
-  for (int64_t c = lane; c < ncols; c += 64) s += Mr[c] * x[c];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if (lane == 0) y[row] = sub ? bvec[row] - s : s;
+  double acc = 0.0;
+  for (int64_t c0 = 0; c0 < n1c; c0 += 256 * kGemvUnroll) {
+    double mv[kGemvUnroll], xv[kGemvUnroll];
+#pragma unroll
+    for (int q = 0; q < kGemvUnroll; ++q) {
+      const int64_t c = c0 + threadIdx.x + 256 * q;
+      mv[q] = c < n1c ? M1[row * n1c + c] : 0.0;
+      xv[q] = c < n1c ? x1[c] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kGemvUnroll; ++q) acc += mv[q] * xv[q];
+  }
+  if (M2) {
+    for (int64_t c0 = 0; c0 < n2c; c0 += 256 * kGemvUnroll) {
+      double mv[kGemvUnroll], xv[kGemvUnroll];
+#pragma unroll
+      for (int q = 0; q < kGemvUnroll; ++q) {
+        const int64_t c = c0 + threadIdx.x + 256 * q;
+        mv[q] = c < n2c ? M2[row * n2c + c] : 0.0;
+        xv[q] = c < n2c ? x2[c] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < kGemvUnroll; ++q) acc -= mv[q] * xv[q];
+    }
+  }
+  const double s = block_sum(acc, sm);
+  if (threadIdx.x == 0) y[row] = sub ? bvec[row] - s : s;
 }
 
 // ------------------------------------------------------------------ reductions
@@ -459,10 +631,12 @@ finalize_kernel(int nblocks, int nd, const double *__restrict__ partials, double
 }
 
 // x += alpha p; r_new = r - alpha w; partial ||r_new||^2. alpha = scal[RZ] / scal[PW].
+// r32 (optional): single-precision copy of r_new, the input of a mixed-precision cycle.
 __global__ void __launch_bounds__(256)
 update_xr_kernel(int64_t n, const double *__restrict__ scal, double *__restrict__ x,
                  const double *__restrict__ p, const double *__restrict__ r,
-                 const double *__restrict__ w, double *__restrict__ rnew, double *__restrict__ partials) {
+                 const double *__restrict__ w, double *__restrict__ rnew, double *__restrict__ partials,
+                 float *__restrict__ r32) {
   __shared__ double sm[4];
   const double alpha = scal[S_RZ] / scal[S_PW];
   double acc = 0.0;
@@ -471,6 +645,7 @@ update_xr_kernel(int64_t n, const double *__restrict__ scal, double *__restrict_
     x[g] = x[g] + alpha * p[g];
     const double rv = r[g] - alpha * w[g];
     rnew[g] = rv;
+    if (r32) r32[g] = (float)rv;
     acc += rv * rv;
   }
   const double s = block_sum(acc, sm);
@@ -574,6 +749,7 @@ adjoint_kernel(Box b, int64_t E, const double *__restrict__ lam, const double *_
 inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
 inline Box mkbox(const Level &L) { return Box{L.N, L.nex, L.ney, L.nez, L.nx, L.ny, L.nz}; }
+inline bool al16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 template <int N, typename T, typename GT>
 void launch_ax_n(const Level &L, const T *u, const GT *G, const T *D, T *wL, hipStream_t s) {
@@ -620,21 +796,41 @@ void launch_dss(const Level &L, const T *wL, T *out, hipStream_t s) {
 template void launch_dss<double>(const Level &, const double *, double *, hipStream_t);
 template void launch_dss<float>(const Level &, const float *, float *, hipStream_t);
 
-void launch_dss_dot(const Level &L, const double *wL, double *out, const double *p, double *partials,
-                    int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((dss_dot_kernel<double>), dim3(nblocks), dim3(256), 0, s, mkbox(L), L.n, wL, out, p,
-                     partials);
+int dss_dot_blocks(int64_t n) { return (int)nblk((n + 1) / 2); }
+
+int launch_dss_dot(const Level &L, const double *wL, double *out, const double *p, double *partials,
+                   hipStream_t s) {
+  const int nb = dss_dot_blocks(L.n);
+  if (al16(out) && al16(p))
+    hipLaunchKernelGGL((dss_dot_kernel<double, 2>), dim3(nb), dim3(256), 0, s, mkbox(L), L.n, wL, out, p,
+                       partials);
+  else
+    hipLaunchKernelGGL((dss_dot_kernel<double, 1>), dim3((unsigned)nblk(L.n)), dim3(256), 0, s, mkbox(L), L.n, wL,
+                       out, p, partials);
+  return al16(out) && al16(p) ? nb : (int)nblk(L.n);
+}
+
+
+template <typename T, int VEC>
+void launch_cheb_v(const Level &L, const T *wsrc, const T *b, const T *r_in, T *r_out, T *d, T *x,
+                   const T *invdiag, double a, double bc, double c, int flags, int mode, hipStream_t s) {
+  const unsigned grid = nblk((L.n + VEC - 1) / VEC);
+  if (L.type == LVL_SEM)
+    hipLaunchKernelGGL((cheb_kernel<T, true, VEC>), dim3(grid), dim3(256), 0, s, mkbox(L), L.n, wsrc, b, r_in,
+                       r_out, d, x, invdiag, (T)a, (T)bc, (T)c, flags, mode);
+  else
+    hipLaunchKernelGGL((cheb_kernel<T, false, VEC>), dim3(grid), dim3(256), 0, s, mkbox(L), L.n, wsrc, b, r_in,
+                       r_out, d, x, invdiag, (T)a, (T)bc, (T)c, flags, mode);
 }
 
 template <typename T>
 void launch_cheb(const Level &L, const T *wsrc, const T *b, const T *r_in, T *r_out, T *d, T *x,
                  const T *invdiag, double a, double bc, double c, int flags, int mode, hipStream_t s) {
-  if (L.type == LVL_SEM)
-    hipLaunchKernelGGL((cheb_kernel<T, true>), dim3(nblk(L.n)), dim3(256), 0, s, mkbox(L), L.n, wsrc, b,
-                       r_in, r_out, d, x, invdiag, (T)a, (T)bc, (T)c, flags, mode);
-  else
-    hipLaunchKernelGGL((cheb_kernel<T, false>), dim3(nblk(L.n)), dim3(256), 0, s, mkbox(L), L.n, wsrc, b,
-                       r_in, r_out, d, x, invdiag, (T)a, (T)bc, (T)c, flags, mode);
+  // 16-byte packs need every streamed vector 16-byte aligned (device allocations are)
+  const bool ok = al16(b) && al16(r_in) && al16(r_out) && al16(d) && al16(x) && al16(invdiag) &&
+                  (L.type == LVL_SEM || al16(wsrc));
+  if (ok) launch_cheb_v<T, 16 / sizeof(T)>(L, wsrc, b, r_in, r_out, d, x, invdiag, a, bc, c, flags, mode, s);
+  else launch_cheb_v<T, 1>(L, wsrc, b, r_in, r_out, d, x, invdiag, a, bc, c, flags, mode, s);
 }
 template void launch_cheb<double>(const Level &, const double *, const double *, const double *, double *,
                                   double *, double *, const double *, double, double, double, int, int,
@@ -644,8 +840,12 @@ template void launch_cheb<float>(const Level &, const float *, const float *, co
 
 template <typename T>
 void launch_resid_weight(const Level &L, const T *wL, const T *b, T *rw, hipStream_t s) {
-  if (L.type == LVL_SEM)
-    hipLaunchKernelGGL((resid_weight_kernel<T>), dim3(nblk(L.n)), dim3(256), 0, s, mkbox(L), L.n, wL, b, rw);
+  constexpr int VEC = 16 / sizeof(T);
+  if (L.type == LVL_SEM && al16(b) && al16(rw))
+    hipLaunchKernelGGL((resid_weight_kernel<T, VEC>), dim3(nblk((L.n + VEC - 1) / VEC)), dim3(256), 0, s,
+                       mkbox(L), L.n, wL, b, rw);
+  else if (L.type == LVL_SEM)
+    hipLaunchKernelGGL((resid_weight_kernel<T, 1>), dim3(nblk(L.n)), dim3(256), 0, s, mkbox(L), L.n, wL, b, rw);
   else
     hipLaunchKernelGGL((resid_plain_kernel<T>), dim3(nblk(L.n)), dim3(256), 0, s, L.n, wL, b, rw);
 }
@@ -665,16 +865,16 @@ template void launch_restrict<float>(const Level &, const Level &, const float *
                                      hipStream_t);
 
 template <typename T>
-void launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *xf, hipStream_t s) {
+void launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *xf, double *zout, hipStream_t s) {
   const int nf = F.N + 1, nc = C.N + 1;
   const size_t lds = sizeof(T) * (size_t)(nf * nc + nc * nc * nc + nc * nc * nf + nc * nf * nf);
   hipLaunchKernelGGL((prolong_kernel<T>), dim3((unsigned)F.E), dim3(128), lds, s, mkbox(F), mkbox(C), F.E, xc,
-                     J, xf);
+                     J, xf, zout);
 }
 template void launch_prolong<double>(const Level &, const Level &, const double *, const double *, double *,
-                                     hipStream_t);
+                                     double *, hipStream_t);
 template void launch_prolong<float>(const Level &, const Level &, const float *, const float *, float *,
-                                    hipStream_t);
+                                    double *, hipStream_t);
 
 template <typename T>
 void launch_csr(const DevCsr &A, const T *val, const T *x, const T *b, T *y, int mode, hipStream_t s) {
@@ -688,7 +888,14 @@ template void launch_csr<float>(const DevCsr &, const float *, const float *, co
 
 void launch_gemv(int64_t nrows, int64_t ncols, const double *M, const double *x, const double *b, double *y,
                  int sub, hipStream_t s) {
-  hipLaunchKernelGGL(gemv_kernel, dim3(nblk(nrows, 4)), dim3(256), 0, s, nrows, ncols, M, x, b, y, sub);
+  hipLaunchKernelGGL(gemv_kernel, dim3((unsigned)nrows), dim3(256), 0, s, nrows, ncols, M, x, (int64_t)0,
+                     (const double *)nullptr, (const double *)nullptr, b, y, sub);
+}
+
+void launch_gemv2(int64_t nrows, int64_t n1c, const double *M1, const double *x1, int64_t n2c, const double *M2,
+                  const double *x2, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(gemv_kernel, dim3((unsigned)nrows), dim3(256), 0, s, nrows, n1c, M1, x1, n2c, M2, x2,
+                     (const double *)nullptr, y, 0);
 }
 
 template <typename T>
@@ -706,8 +913,8 @@ void launch_finalize(int nblocks, int nd, const double *partials, double *scal, 
 }
 
 void launch_update_xr(int64_t n, const double *scal, double *x, const double *p, const double *r,
-                      const double *w, double *rnew, double *partials, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(update_xr_kernel, dim3(nblocks), dim3(256), 0, s, n, scal, x, p, r, w, rnew, partials);
+                      const double *w, double *rnew, double *partials, int nblocks, float *r32, hipStream_t s) {
+  hipLaunchKernelGGL(update_xr_kernel, dim3(nblocks), dim3(256), 0, s, n, scal, x, p, r, w, rnew, partials, r32);
 }
 
 void launch_update_p(int64_t n, const double *scal, const double *z, double *p, hipStream_t s) {

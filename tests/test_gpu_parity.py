@@ -1,6 +1,7 @@
 """GPU parity of the HIP path against the FP64 oracle, through the C ABI.
 
-Tolerances (FP64): operator and transfers 1e-13 relative (max norm), V-cycle
+Tolerances (FP64): operator 1e-14 (N+1)^2 relative in the max norm (its rounding
+grows with the size of the GLL derivative entries, ~N^2/4), V-cycle
 1e-12 relative (2-norm), PCG/FCG solves: identical iteration counts, every
 residual norm within 1e-12 ||b||, solution within 1e-12 relative. lambda_max
 is estimated by the oracle and handed to both sides, so the solve comparison
@@ -44,7 +45,7 @@ def test_apply_A_parity(m, N):
         pytest.skip("order 1 alone has no smoothed level")
     u = wl.uniform_noise(box.n, 11)
     w = host(s.apply_A(dev(u)))
-    assert relmax(w, box.apply(u)) < 1e-13
+    assert relmax(w, box.apply(u)) < 1e-14 * (N + 1) ** 2
 
 
 def test_apply_A_order1_and_deterministic():
@@ -126,7 +127,7 @@ def test_cfg2_rhs_parity(cfg2):
     s = SemSolver(V, N=7, lambda_max=lmax)
     f = wl.manufactured_load(host(s.coords()))
     bg = host(s.mass_apply(dev(f)))
-    assert relmax(bg, box.mass() * wl.manufactured_load(box.coords())) < 1e-14
+    assert relmax(bg, box.mass() * wl.manufactured_load(box.coords())) < 1e-13
 
 
 def test_cfg2_solve_parity(cfg2):
@@ -230,9 +231,9 @@ def test_adjoint_contract_parity():
     dG, df = s.adjoint_contract(dev(lam), dev(u))
     ref = adjoint.contract(box, lam, u)
     assert relmax(host(dG), ref) < 1e-13
-    assert relmax(host(df), box.mass() * lam) < 1e-15
+    assert relmax(host(df), box.mass() * lam) < 1e-14
     G = s.factors()
-    assert relmax(host(G), box.G) < 1e-14
+    assert relmax(host(G), box.G) < 1e-13
 
 
 @pytest.mark.parametrize("planes", [1, 2])
