@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--m", type=int, default=32, help="elements per direction")
     ap.add_argument("--order", type=int, default=7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batched measurement")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--kernel-only", action="store_true",
                     help="set up the FP64 and mixed contexts with fixed lambda_max and only launch the "
@@ -106,6 +107,61 @@ def time_kernel(fn, reps):
     e.record()
     e.synchronize()
     return s.elapsed_time(e) / reps * 1e-3
+
+
+def bench_batched(steps, nsys=64):
+    """64 independent systems (m ~ U{4..16}, N ~ U{5,7,9}, per-system random deformation and
+    rhs): one batched mixed-precision solve of all systems versus the plain FP64 form (every
+    system solved on its own, one after the other) on the same GPU."""
+    import torch
+
+    import workload as wl
+    from paper_2210_03179_amd.solver import BatchedSolver, SemSolver
+    specs = wl.batched_specs(nsys, 1000)
+    verts = [wl.batched_box(sp.m, sp.mesh_seed) for sp in specs]
+    t0 = time.perf_counter()
+    singles = [SemSolver(V, N=sp.N, smoother="cheb4opt", pre=4, post=0, precision="fp64", krylov="fcg")
+               for V, sp in zip(verts, specs)]
+    t_setup64 = time.perf_counter() - t0
+    rhs = []
+    for s, sp in zip(singles, specs):
+        f = wl.manufactured_load(s.coords().cpu().numpy())
+        b0 = s.mass_apply(torch.from_numpy(f).cuda()).cpu().numpy()
+        rhs.append(b0 + 1e-3 * np.max(np.abs(b0)) * wl.uniform_noise(s.n, sp.rhs_seed))
+    t0 = time.perf_counter()
+    bs = BatchedSolver(verts, [sp.N for sp in specs], smoother="cheb4opt", pre=4, post=0, krylov="fcg")
+    t_setupb = time.perf_counter() - t0
+    b = torch.from_numpy(np.concatenate(rhs)).cuda()
+    bs.solve(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u, st, its, rel = bs.solve(b)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    bdev = [torch.from_numpy(r).cuda() for r in rhs]
+    for s, bq in zip(singles, bdev):
+        s.solve(bq)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its64 = []
+    for s, bq in zip(singles, bdev):
+        _, info = s.solve(bq)
+        its64.append(info.iterations)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    # true FP64 residual of every batched solution with each system's FP64 operator
+    worst = 0.0
+    for q, (s, bq) in enumerate(zip(singles, bdev)):
+        uq = u[bs.offsets[q]:bs.offsets[q + 1]].contiguous()
+        worst = max(worst, float(torch.linalg.vector_norm(bq - s.apply_A(uq)) / torch.linalg.vector_norm(bq)))
+    ns = [bs.offsets[q + 1] - bs.offsets[q] for q in range(nsys)]
+    return {"systems": nsys, "unknowns": bs.n, "ms_per_batch_solve": round(t_batch * 1e3, 3),
+            "ms_fp64_one_by_one": round(t_seq * 1e3, 3), "speedup_vs_fp64": round(t_seq / t_batch, 3),
+            "gdof_iter_per_s": round(sum(n * i for n, i in zip(ns, its)) / t_batch / 1e9, 4),
+            "iterations_min_max": [min(its), max(its)], "fp64_iterations_min_max": [min(its64), max(its64)],
+            "worst_true_relres": worst, "status": st,
+            "setup_s": {"fp64_systems": round(t_setup64, 1), "batched": round(t_setupb, 1)}}
 
 
 def cpu_baseline(m, N, n_global):
@@ -219,6 +275,10 @@ def main():
                      "mixed_kernel": {"kernel": "ax_local_kernel<7,float,bf16>", "kernel_us": round(t_axmx * 1e6, 2),
                                       "achieved": round(bytesmx / t_axmx / 1e9, 1)}},
     }
+    if not args.no_batched:
+        log("batched systems ...")
+        out["batched"] = bench_batched(max(1, args.steps // 2))
+        log(f"batched: {out['batched']}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(m, N, n)

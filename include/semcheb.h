@@ -191,6 +191,28 @@ sem_status sem_reset_counts(sem_ctx *ctx);
 sem_status sem_host_array(const sem_ctx *ctx, const char *what, int32_t level, double *out,
                           int64_t n, int64_t *needed);
 
+/* Batched problems: nsys (1..64) independent SEM systems on box meshes with their
+ * own orders (orders[s] in 4..12, schedule N, floor(N/2), 1), all with the smoother,
+ * cycle and Krylov settings of *opt and a mixed-precision cycle (FP32 arithmetic,
+ * BF16 geometric factors, FP64 Krylov and coarse solve). lambda_max is estimated per
+ * system and level. meshes, orders: host arrays of nsys entries. Same errors as
+ * sem_setup_box, plus SEM_EINVAL for pre_order < 1 or a given lambda_max/schedule. */
+sem_status sem_setup_batched(int32_t nsys, const sem_box_mesh *meshes, const int32_t *orders,
+                             const sem_options *opt, void *stream, sem_ctx **out);
+
+/* Number of systems and the offsets (host, nsys+1 entries) of every system's
+ * unknowns in the concatenated vectors of sem_solve_batched. */
+sem_status sem_batch_info(const sem_ctx *ctx, int32_t *nsys, int64_t *offsets);
+
+/* Solve all systems of a batched context from a zero initial guess, each to
+ * ||r||_2 <= rtol ||b||_2 (or maxit iterations), advancing the unconverged systems
+ * together: every kernel launch covers all of them. b, u: device, concatenated
+ * per sem_batch_info (u is overwritten). iters, relres: host arrays of nsys entries
+ * (may be NULL). Returns SEM_ENOTCONV if some system reached maxit, SEM_EBREAKDOWN /
+ * SEM_ENAN if some system broke down; the other systems are still solved. */
+sem_status sem_solve_batched(sem_ctx *ctx, const double *b, double *u, double rtol, int32_t maxit,
+                             int32_t *iters, double *relres, void *stream);
+
 /* beta_i^{(k)}, i = 1..k, of Table beta_coef into out[0..k-1]; k in 1..16. */
 sem_status sem_beta_table(int32_t k, double *out);
 

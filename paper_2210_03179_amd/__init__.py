@@ -6,4 +6,4 @@ the C ABI of include/semcheb.h (libsemcheb.so). This package is the thin Python
 binding over that library.
 """
 from ._lib import SemError, load, LIB_PATH  # noqa: F401
-from .solver import SemSolver, FdSolver, SolveInfo, beta_table  # noqa: F401
+from .solver import SemSolver, FdSolver, BatchedSolver, SolveInfo, beta_table  # noqa: F401

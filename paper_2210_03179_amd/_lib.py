@@ -26,6 +26,7 @@ EXPORTS = (
     "sem_apply_A", "sem_apply_local", "sem_vcycle", "sem_solve", "sem_coords", "sem_mass_apply", "sem_get_factors",
     "sem_set_factors", "sem_adjoint_contract", "sem_apply_counts", "sem_reset_counts",
     "sem_host_array", "sem_beta_table", "sem_destroy", "sem_last_error", "sem_global_error",
+    "sem_setup_batched", "sem_batch_info", "sem_solve_batched",
 )
 
 
@@ -81,6 +82,9 @@ def load() -> C.CDLL:
         "sem_reset_counts": (i32, [vp]),
         "sem_host_array": (i32, [vp, C.c_char_p, i32, P(dbl), i64, P(i64)]),
         "sem_beta_table": (i32, [i32, P(dbl)]),
+        "sem_setup_batched": (i32, [i32, P(SemBoxMesh), P(i32), P(SemOptions), vp, P(vp)]),
+        "sem_batch_info": (i32, [vp, P(i32), P(i64)]),
+        "sem_solve_batched": (i32, [vp, vp, vp, dbl, i32, P(i32), P(dbl), vp]),
         "sem_destroy": (i32, [vp]),
         "sem_last_error": (C.c_char_p, [vp]),
         "sem_global_error": (C.c_char_p, []),

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsemcheb.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "api.cpp", "host_setup.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "host_setup.cpp", "batched.cpp"]
 ARCH = os.environ.get("SEMCHEB_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <utility>
@@ -410,6 +411,57 @@ sem_status alloc_krylov(sem_ctx *c, int64_t n) {
   return SEM_OK;
 }
 
+// Autotuner: time every operator-kernel variant on the level's own data (events on the
+// setup stream) and keep the fastest per precision. Variants differ only in load
+// scheduling and register allocation, not in arithmetic, so results are identical.
+sem_status autotune_operator(sem_ctx *c, hipStream_t s) {
+  const char *env = std::getenv("SEMCHEB_AUTOTUNE");
+  if (env && env[0] == '0') return SEM_OK;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  const bool mixed = c->opt.precision == SEM_MIXED;
+  HIPCHK(c, hipMemsetAsync(c->kr, 0, c->levels[0].n * sizeof(double), s));
+  const int reps = 4;
+  sem_status st = SEM_OK;
+  for (size_t j = 0; j + 1 < c->levels.size() && st == SEM_OK; ++j) {
+    Level &L = c->levels[j];
+    for (int prec = 0; prec < 2; ++prec) {
+      const bool fp64 = prec == 0;
+      if (!fp64 && !(mixed && L.Gbf && L.w32)) continue;
+      if (fp64 && !L.w64) continue;
+      float best = 1e30f;
+      for (int v = 0; v < kAxVariants; ++v) {
+        int &var = fp64 ? L.ax_variant64 : L.ax_variant32;
+        var = v;
+        auto run = [&]() {
+          if (fp64) launch_ax(L, (const double *)c->kr, L.w64, s);
+          else launch_ax(L, (const float *)c->kr, L.w32, s);
+        };
+        run();
+        hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) run();
+        hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) { st = SEM_EHIP; break; }
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        const float us = ms * 1000.0f / reps;
+        (fp64 ? L.ax_time64_us : L.ax_time32_us)[v] = us;
+        if (us < best) best = us;
+      }
+      const float *tt = fp64 ? L.ax_time64_us : L.ax_time32_us;
+      int bv = 0;
+      for (int v = 1; v < kAxVariants; ++v)
+        if (tt[v] < tt[bv]) bv = v;
+      (fp64 ? L.ax_variant64 : L.ax_variant32) = bv;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != SEM_OK) c->err = "autotuning the operator failed";
+  return st;
+}
+
 sem_status estimate_lambdas(sem_ctx *c, hipStream_t s) {
   const int ns = (int)c->levels.size() - 1;  // smoothed levels
   for (int j = 0; j < ns; ++j) {
@@ -578,6 +630,7 @@ sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipS
   }
   TRY(alloc_krylov(c, c->levels[0].n));
   HIPCHK(c, hipStreamSynchronize(s));
+  TRY(autotune_operator(c, s));
   TRY(estimate_lambdas(c, s));
   for (auto &L : c->levels) L.applies = 0;
   return SEM_OK;
@@ -666,6 +719,10 @@ sem_status setup_fd_impl(int n, double Lx, double Ly, int factor, int coarsest_n
 
 sem_status need_device(sem_ctx *c) {
   if (!c) return SEM_EINVAL;
+  if (c->batch) {
+    c->err = "batched context: use sem_solve_batched";
+    return SEM_EINVAL;
+  }
   if (c->host_only) {
     c->err = "host-only context: no device data";
     return SEM_ENODEV;
@@ -679,6 +736,12 @@ sem_status need_device(sem_ctx *c) {
 
 void release(sem_ctx *c) {
   if (!c) return;
+  if (c->batch) {
+    for (sem_ctx *sub : c->batch->sys) release(sub);
+    if (c->batch->pinned) hipHostFree(c->batch->pinned);
+    delete c->batch;
+    c->batch = nullptr;
+  }
   if (!c->host_only) {
     hipSetDevice(c->device);
     hipDeviceSynchronize();
@@ -690,6 +753,10 @@ void release(sem_ctx *c) {
 }
 
 }  // namespace
+
+namespace semcheb {
+void set_global_error(const std::string &msg) { g_err = msg; }
+}  // namespace semcheb
 
 // ====================================================================== C ABI
 extern "C" {
@@ -936,7 +1003,16 @@ sem_status sem_host_array(const sem_ctx *c, const char *what, int32_t j, double 
   const std::vector<double> *src = nullptr;
   const std::string w(what);
   const bool sem = c->kind == LVL_SEM;
-  if (w == "lambda_max") {
+  if (w == "ax_tuning") {
+    // per level: variant64, 3 timings (us), variant32, 3 timings (us)
+    for (auto &L : c->levels) {
+      tmp.push_back(L.ax_variant64);
+      for (int v = 0; v < kAxVariants; ++v) tmp.push_back(L.ax_time64_us[v]);
+      tmp.push_back(L.ax_variant32);
+      for (int v = 0; v < kAxVariants; ++v) tmp.push_back(L.ax_time32_us[v]);
+    }
+    src = &tmp;
+  } else if (w == "lambda_max") {
     for (auto &L : c->levels) tmp.push_back(L.lmax);
     src = &tmp;
   } else if (w == "coarse_matrix") {

@@ -68,6 +68,9 @@ struct FdLevelHost {
 void build_fd_hierarchy(int n, double Lx, double Ly, int factor, int coarsest_n,
                         std::vector<FdLevelHost> &out);
 
+// message returned by sem_global_error()
+void set_global_error(const std::string &msg);
+
 // Largest eigenvalue of a symmetric tridiagonal matrix (diag a[0..m-1], offdiag b[0..m-2]).
 double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &b);
 
@@ -106,7 +109,11 @@ struct Level {
   double *b64 = nullptr, *x64 = nullptr, *r64 = nullptr, *d64 = nullptr, *w64 = nullptr;
   float *b32 = nullptr, *x32 = nullptr, *r32 = nullptr, *d32 = nullptr, *w32 = nullptr;
   int64_t applies = 0;
+  // operator kernel variant per precision, chosen at setup by timing (kAxVariants)
+  int ax_variant64 = 0, ax_variant32 = 0;
+  float ax_time64_us[3] = {0, 0, 0}, ax_time32_us[3] = {0, 0, 0};
 };
+constexpr int kAxVariants = 3;
 
 struct CoarseSolver {
   bool dense = true;
@@ -120,7 +127,45 @@ struct CoarseSolver {
   std::vector<double> host_dense;  // small problems: assembled matrix for inspection
 };
 
+// ---------------------------------------------------------------- batched solves
+constexpr int kMaxBatch = 64;      // systems per batched context
+constexpr int kBatchLevels = 3;    // schedule N, floor(N/2), 1 for every system
+constexpr int kMaxChebSteps = 17;  // Chebyshev steps per smoothing (order <= 16, plus the first)
+
+// One level of one system as the batched kernels see it (device memory).
+struct BatchLevelDev {
+  int N, nex, ney, nez, nx, ny, nz;
+  int64_t n, E;
+  float *b, *x, *r, *d, *w;        // single-precision cycle vectors (w: element-local)
+  const float *inv, *J, *D;        // diag^{-1}, interpolation from the next level, derivative
+  const uint16_t *G;               // BF16 geometric factors
+  const double *G64, *D64;         // FP64 factors and derivative (finest level: Krylov apply)
+  double *w64;                     // FP64 element-local result (finest level)
+  double coef[2][kMaxChebSteps][3];  // Chebyshev (a, bc, c) per [pre/post][step]
+};
+
+// One system of a batch (device memory).
+struct BatchSysDev {
+  BatchLevelDev lev[kBatchLevels];
+  double *u, *b;                   // caller's solution and right-hand side
+  double *r[2], *z, *p, *w;        // Krylov vectors (r[0], r[1] alternate)
+  double *scal;                    // this system's Krylov scalars
+  double *cb, *cx;                 // coarse right-hand side and solution (FP64)
+  const double *Minv;              // dense inverse of the coarse operator
+  int64_t nc;
+};
+
+// Kernel-argument table mapping the blocks of one batched launch to systems:
+// blocks [begin[k], begin[k+1]) belong to system sys[k].
+struct LaunchTable {
+  int count;
+  int sys[kMaxBatch];
+  int begin[kMaxBatch + 1];
+};
+
 }  // namespace semcheb
+
+struct sem_batch;
 
 struct sem_ctx {
   int kind = 0;  // semcheb::LVL_SEM or LVL_FD
@@ -141,4 +186,18 @@ struct sem_ctx {
   double *zout = nullptr;      // set during a mixed one-sided cycle: widened output target
   std::string err;
   std::vector<void *> allocations;
+  sem_batch *batch = nullptr;  // set for batched contexts (kind == 2)
+};
+
+// Batched context data: independent systems solved in lock-step, every kernel
+// launch covering all systems that have not converged.
+struct sem_batch {
+  std::vector<sem_ctx *> sys;                   // per-system hierarchies (mixed precision)
+  std::vector<semcheb::BatchSysDev> host;       // host image of the descriptors
+  semcheb::BatchSysDev *dev = nullptr;          // device descriptors
+  std::vector<int64_t> offsets;                 // offsets of the systems in concatenated vectors
+  double *scal = nullptr;                       // nsys * S_COUNT device scalars
+  double *pinned = nullptr;                     // host mirror of scal
+  double *partials = nullptr;                   // reduction partials of a batched launch
+  int64_t partials_cap = 0;
 };

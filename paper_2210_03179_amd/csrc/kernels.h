@@ -64,3 +64,25 @@ void launch_mul(int64_t n, const double *a, const double *b, double *out, hipStr
 bool launch_adjoint(const Level &L, const double *lam, const double *u, double *dG, hipStream_t s);
 
 }  // namespace semcheb
+
+namespace semcheb {
+// ---------------------------------------------------------------- batched launchers
+// The grid of every batched launch is t.begin[t.count] blocks (finalize: t.count).
+int batch_ax_elements_per_block(int N);
+bool launch_b_ax32(int N, const LaunchTable &t, const BatchSysDev *sys, int level, int src, hipStream_t s);
+bool launch_b_ax64(int N, const LaunchTable &t, const BatchSysDev *sys, hipStream_t s);
+void launch_b_cheb(const LaunchTable &t, const BatchSysDev *sys, int level, int pp, int step, int flags, int mode,
+                   hipStream_t s);
+void launch_b_resid(const LaunchTable &t, const BatchSysDev *sys, int level, int has_w, hipStream_t s);
+void launch_b_restrict(const LaunchTable &t, const BatchSysDev *sys, int level, size_t lds, hipStream_t s);
+void launch_b_dss(const LaunchTable &t, const BatchSysDev *sys, int level, hipStream_t s);
+void launch_b_prolong(const LaunchTable &t, const BatchSysDev *sys, int level, int to_z, size_t lds, hipStream_t s);
+void launch_b_convert(const LaunchTable &t, const BatchSysDev *sys, int op, int par, hipStream_t s);
+void launch_b_coarse(const LaunchTable &t, const BatchSysDev *sys, hipStream_t s);
+void launch_b_dssdot(const LaunchTable &t, const BatchSysDev *sys, double *partials, hipStream_t s);
+void launch_b_finalize(const LaunchTable &t, const BatchSysDev *sys, const double *partials, int nd, int slot, int op,
+                       hipStream_t s);
+void launch_b_update_xr(const LaunchTable &t, const BatchSysDev *sys, int par, double *partials, hipStream_t s);
+void launch_b_dots(const LaunchTable &t, const BatchSysDev *sys, int par, int what, double *partials, hipStream_t s);
+void launch_b_vec(const LaunchTable &t, const BatchSysDev *sys, int op, hipStream_t s);
+}  // namespace semcheb

@@ -12,253 +12,19 @@
 
 #include <cstdint>
 
-#include "kernels.h"
+#include "device_ops.h"
 
 namespace semcheb {
 namespace {
+using namespace dev;
 
-__device__ __forceinline__ float bf16_to_float(uint16_t h) {
-  return __uint_as_float(((uint32_t)h) << 16);
-}
-template <typename GT, typename T>
-__device__ __forceinline__ T load_factor(const GT *p);
-template <>
-__device__ __forceinline__ double load_factor<double, double>(const double *p) { return *p; }
-template <>
-__device__ __forceinline__ float load_factor<uint16_t, float>(const uint16_t *p) { return bf16_to_float(*p); }
-template <>
-__device__ __forceinline__ float load_factor<float, float>(const float *p) { return *p; }
-
-// ------------------------------------------------------------------ box geometry helpers
-struct Box {
-  int N, nex, ney, nez, nx, ny, nz;
-};
-
-// Element copies of lattice coordinate I (1 <= I <= nex*N-1) along one axis.
-__device__ __forceinline__ int copies_1d(int I, int N, int *el, int *loc) {
-  const int q = I / N, r = I - q * N;
-  if (r == 0) {
-    el[0] = q - 1; loc[0] = N;
-    el[1] = q;     loc[1] = 0;
-    return 2;
-  }
-  el[0] = q; loc[0] = r;
-  return 1;
-}
-
-// Lattice coordinates (1-based) of unknown g; 32-bit arithmetic (n < 2^31 is checked at setup).
-struct Ijk {
-  int I, J, K;
-};
-__device__ __forceinline__ Ijk ijk_of(const Box &b, int64_t g) {
-  const unsigned gg = (unsigned)g, nx = (unsigned)b.nx, ny = (unsigned)b.ny;
-  const unsigned q = gg / nx;
-  return Ijk{(int)(gg - q * nx) + 1, (int)(q % ny) + 1, (int)(q / ny) + 1};
-}
-__device__ __forceinline__ void ijk_next(const Box &b, Ijk &c) {
-  if (++c.I > b.nx) {
-    c.I = 1;
-    if (++c.J > b.ny) {
-      c.J = 1;
-      ++c.K;
-    }
-  }
-}
-
-// Sum of the element-local copies of the unknown at lattice point c (direct stiffness summation).
-template <typename T>
-__device__ __forceinline__ T dss_ijk(const T *__restrict__ wL, const Box &b, const Ijk &c) {
-  const int I = c.I, J = c.J, K = c.K;
-  int exs[2], is[2], eys[2], js[2], ezs[2], ks[2];
-  const int cx = copies_1d(I, b.N, exs, is);
-  const int cy = copies_1d(J, b.N, eys, js);
-  const int cz = copies_1d(K, b.N, ezs, ks);
-  const int n1 = b.N + 1;
-  const int64_t n3 = (int64_t)n1 * n1 * n1;
-  T s = 0;
-  for (int c = 0; c < cz; ++c)
-    for (int bq = 0; bq < cy; ++bq)
-      for (int a = 0; a < cx; ++a) {
-        const int64_t e = exs[a] + (int64_t)b.nex * (eys[bq] + (int64_t)b.ney * ezs[c]);
-        s += wL[e * n3 + (ks[c] * n1 + js[bq]) * n1 + is[a]];
-      }
-  return s;
-}
-
-template <typename T>
-__device__ __forceinline__ T dss_at(const T *__restrict__ wL, const Box &b, int64_t g) {
-  return dss_ijk(wL, b, ijk_of(b, g));
-}
-
-// 1 / (number of element copies) of an unknown: a power of two, so exact.
-__device__ __forceinline__ double inv_mult_ijk(const Box &b, const Ijk &c) {
-  int m = 1;
-  if (c.I % b.N == 0) m *= 2;
-  if (c.J % b.N == 0) m *= 2;
-  if (c.K % b.N == 0) m *= 2;
-  return 1.0 / m;
-}
-__device__ __forceinline__ double inv_mult(const Box &b, int64_t g) { return inv_mult_ijk(b, ijk_of(b, g)); }
-
-// VEC consecutive elements of a vector as one 16-byte access.
-template <typename T, int VEC>
-struct Pack {
-  T v[VEC];
-};
-template <typename T, int VEC>
-__device__ __forceinline__ Pack<T, VEC> ld(const T *__restrict__ p) {
-  typedef T vt __attribute__((ext_vector_type(VEC)));
-  const vt x = *reinterpret_cast<const vt *>(p);
-  Pack<T, VEC> r;
-#pragma unroll
-  for (int q = 0; q < VEC; ++q) r.v[q] = x[q];
-  return r;
-}
-template <typename T, int VEC>
-__device__ __forceinline__ void st(T *__restrict__ p, const Pack<T, VEC> &r) {
-  typedef T vt __attribute__((ext_vector_type(VEC)));
-  vt x;
-#pragma unroll
-  for (int q = 0; q < VEC; ++q) x[q] = r.v[q];
-  *reinterpret_cast<vt *>(p) = x;
-}
-
-__device__ __forceinline__ int64_t lattice_index(const Box &b, int I, int J, int K) {
-  if (I < 1 || I > b.nx || J < 1 || J > b.ny || K < 1 || K > b.nz) return -1;
-  return (I - 1) + (int64_t)b.nx * ((J - 1) + (int64_t)b.ny * (K - 1));
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on XCD
-// b mod 8). Remap so that XCD x processes the contiguous chunk x of the logical
-// block range: neighbouring elements, which share face values of the input,
-// then meet in the same L2. The tail beyond a multiple of 8 keeps identity order.
-__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
-  constexpr unsigned kXcd = 8;
-  const unsigned full = nb - nb % kXcd;
-  if (b >= full) return b;
-  return (b % kXcd) * (full / kXcd) + b / kXcd;
-}
-
-// ------------------------------------------------------------------ operator (element-local)
-// One (N+1)^2 thread slab per element, looping over the k planes:
-//   u column (i,j,:) held in registers, plane k of u staged in LDS for the r and s
-//   derivatives; the t derivative and its transpose stay in registers.
-template <int N>
-struct AxShape {
-  static constexpr int n1 = N + 1;
-  static constexpr int tpe = n1 * n1;
-  static constexpr int block = tpe <= 64 ? 64 : ((tpe + 63) / 64) * 64;
-  static constexpr int epb = tpe <= 64 ? 64 / tpe : 1;
-};
-
-template <int N, typename T, typename GT>
-__global__ void __launch_bounds__(AxShape<N>::block)
+// Variants of the operator kernel chosen per level by the setup-time autotuner:
+// PF (factor prefetch) and OCC (waves per SIMD requested from the register allocator).
+template <int N, typename T, typename GT, int PF, int OCC>
+__global__ void __launch_bounds__(AxShape<N>::block, OCC)
 ax_local_kernel(Box b, int64_t E, const T *__restrict__ u, const GT *__restrict__ G,
                 const T *__restrict__ Dm, T *__restrict__ wL) {
-  using S = AxShape<N>;
-  constexpr int n1 = S::n1, n3 = n1 * n1 * n1;
-  __shared__ T sD[n1 * n1];
-  __shared__ T su[S::epb][n1][n1];
-  __shared__ T sr[S::epb][n1][n1];
-  __shared__ T ss[S::epb][n1][n1];
-  const int t = threadIdx.x;
-  const int le = t / S::tpe;
-  const int ij = t - le * S::tpe;
-  const int i = ij % n1, j = ij / n1;
-  const int64_t e = (int64_t)xcd_block(blockIdx.x, gridDim.x) * S::epb + le;
-  const bool active = (le < S::epb) && (e < E);
-  for (int q = t; q < n1 * n1; q += S::block) sD[q] = Dm[q];
-
-  T ureg[n1], wreg[n1];
-  T Di[n1], Dj[n1];
-  [[maybe_unused]] T DTi[n1], DTj[n1];
-  int ex = 0, ey = 0, ez = 0;
-  if (active) {
-    ex = (int)(e % b.nex);
-    ey = (int)((e / b.nex) % b.ney);
-    ez = (int)(e / ((int64_t)b.nex * b.ney));
-  }
-  const int I = ex * N + i, J = ey * N + j;
-  const bool inIJ = active && I >= 1 && I <= b.nx && J >= 1 && J <= b.ny;
-  const int64_t gIJ = (int64_t)(I - 1) + (int64_t)b.nx * (J - 1);
-  const int64_t plane = (int64_t)b.nx * b.ny;
-#pragma unroll
-  for (int k = 0; k < n1; ++k) {
-    const int K = ez * N + k;
-    ureg[k] = (inIJ && K >= 1 && K <= b.nz) ? u[gIJ + plane * (K - 1)] : T(0);
-    wreg[k] = T(0);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int l = 0; l < n1; ++l) {
-    Di[l] = sD[i * n1 + l];
-    Dj[l] = sD[j * n1 + l];
-    if constexpr (sizeof(T) == 4) {
-      DTi[l] = sD[l * n1 + i];
-      DTj[l] = sD[l * n1 + j];
-    }
-  }
-  const GT *Ge = G + (active ? e : 0) * 6 * n3 + j * n1 + i;
-  const int lec = active ? le : 0;
-  // factors of plane 0; the loop prefetches plane k+1 while computing plane k
-  T g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0;
-  if (active) {
-    g0 = load_factor<GT, T>(Ge + 0 * n3);
-    g1 = load_factor<GT, T>(Ge + 1 * n3);
-    g2 = load_factor<GT, T>(Ge + 2 * n3);
-    g3 = load_factor<GT, T>(Ge + 3 * n3);
-    g4 = load_factor<GT, T>(Ge + 4 * n3);
-    g5 = load_factor<GT, T>(Ge + 5 * n3);
-  }
-#pragma unroll 1
-  for (int k = 0; k < n1; ++k) {
-    // register arrays are only indexed with compile-time indices (selects on k)
-    T uk = ureg[0];
-#pragma unroll
-    for (int l = 1; l < n1; ++l) uk = (l == k) ? ureg[l] : uk;
-    if (active) su[lec][j][i] = uk;
-    T h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0, h5 = 0;
-    if (active && k + 1 < n1) {
-      const int qn = (k + 1) * n1 * n1;
-      h0 = load_factor<GT, T>(Ge + 0 * n3 + qn);
-      h1 = load_factor<GT, T>(Ge + 1 * n3 + qn);
-      h2 = load_factor<GT, T>(Ge + 2 * n3 + qn);
-      h3 = load_factor<GT, T>(Ge + 3 * n3 + qn);
-      h4 = load_factor<GT, T>(Ge + 4 * n3 + qn);
-      h5 = load_factor<GT, T>(Ge + 5 * n3 + qn);
-    }
-    __syncthreads();
-    T ur = 0, us = 0, ut = 0;
-#pragma unroll
-    for (int l = 0; l < n1; ++l) {
-      ur += Di[l] * su[lec][j][l];
-      us += Dj[l] * su[lec][l][i];
-      ut += Dm[k * n1 + l] * ureg[l];  // wave-uniform: scalar loads
-    }
-    const T wr = g0 * ur + g1 * us + g2 * ut;
-    const T ws = g1 * ur + g3 * us + g4 * ut;
-    const T wt = g2 * ur + g4 * us + g5 * ut;
-    if (active) {
-      sr[lec][j][i] = wr;
-      ss[lec][j][i] = ws;
-    }
-    __syncthreads();
-    T acc = 0;
-#pragma unroll
-    for (int l = 0; l < n1; ++l) {
-      if constexpr (sizeof(T) == 4) acc += DTi[l] * sr[lec][j][l] + DTj[l] * ss[lec][l][i];
-      else acc += sD[l * n1 + i] * sr[lec][j][l] + sD[l * n1 + j] * ss[lec][l][i];
-    }
-#pragma unroll
-    for (int l = 0; l < n1; ++l) wreg[l] += ((l == k) ? acc : T(0)) + Dm[k * n1 + l] * wt;
-    g0 = h0; g1 = h1; g2 = h2; g3 = h3; g4 = h4; g5 = h5;
-    __syncthreads();
-  }
-  if (active) {
-    T *we = wL + e * n3;
-#pragma unroll
-    for (int k = 0; k < n1; ++k) we[(k * n1 + j) * n1 + i] = wreg[k];
-  }
+  ax_body<N, T, GT, PF>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
 }
 
 // ------------------------------------------------------------------ summation / vector kernels
@@ -284,12 +50,12 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
 // One thread per VEC consecutive unknowns (no grid-stride loop: every load of a
 // thread is independent of the others), one partial per block.
 template <typename T, int VEC>
-__global__ void __launch_bounds__(256)
-dss_dot_kernel(Box b, int64_t n, const T *__restrict__ wL, T *__restrict__ out,
-               const T *__restrict__ p, double *__restrict__ partials) {
+__device__ __forceinline__ void dss_dot_body(unsigned blk, const Box &b, int64_t n, const T *__restrict__ wL,
+                                             T *__restrict__ out, const T *__restrict__ p,
+                                             double *__restrict__ partial) {
   __shared__ double sm[4];
   double acc = 0.0;
-  const int64_t g0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  const int64_t g0 = ((int64_t)blk * blockDim.x + threadIdx.x) * VEC;
   if (g0 < n) {
     const bool full = g0 + VEC <= n;
     Pack<T, VEC> pv, ov;
@@ -309,7 +75,14 @@ dss_dot_kernel(Box b, int64_t n, const T *__restrict__ wL, T *__restrict__ out,
         if (g0 + q < n) out[g0 + q] = ov.v[q];
   }
   const double s = block_sum(acc, sm);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) *partial = s;
+}
+
+template <typename T, int VEC>
+__global__ void __launch_bounds__(256)
+dss_dot_kernel(Box b, int64_t n, const T *__restrict__ wL, T *__restrict__ out,
+               const T *__restrict__ p, double *__restrict__ partials) {
+  dss_dot_body<T, VEC>(blockIdx.x, b, n, wL, out, p, partials + blockIdx.x);
 }
 
 // Chebyshev step (Algorithms 1 and 2) fused with the summation of A d:
@@ -320,12 +93,11 @@ dss_dot_kernel(Box b, int64_t n, const T *__restrict__ wL, T *__restrict__ out,
 // One thread updates VEC consecutive unknowns (16-byte accesses of the plain
 // vectors); the last thread handles a partial pack element by element.
 template <typename T, bool SEM, int VEC>
-__global__ void __launch_bounds__(256)
-cheb_kernel(Box b, int64_t n, const T *__restrict__ wsrc, const T *__restrict__ bvec,
-            const T *__restrict__ r_in, T *__restrict__ r_out, T *__restrict__ d,
-            T *__restrict__ x, const T *__restrict__ invdiag, T a, T bc, T c, int flags,
-            int mode) {
-  const int64_t g0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+__device__ __forceinline__ void cheb_body(unsigned blk, const Box &b, int64_t n, const T *__restrict__ wsrc,
+                                          const T *__restrict__ bvec, const T *__restrict__ r_in,
+                                          T *__restrict__ r_out, T *__restrict__ d, T *__restrict__ x,
+                                          const T *__restrict__ invdiag, T a, T bc, T c, int flags, int mode) {
+  const int64_t g0 = ((int64_t)blk * blockDim.x + threadIdx.x) * VEC;
   if (g0 >= n) return;
   const bool full = g0 + VEC <= n;
   const int cnt = full ? VEC : (int)(n - g0);
@@ -379,13 +151,21 @@ cheb_kernel(Box b, int64_t n, const T *__restrict__ wsrc, const T *__restrict__ 
   }
 }
 
+template <typename T, bool SEM, int VEC>
+__global__ void __launch_bounds__(256)
+cheb_kernel(Box b, int64_t n, const T *__restrict__ wsrc, const T *__restrict__ bvec,
+            const T *__restrict__ r_in, T *__restrict__ r_out, T *__restrict__ d,
+            T *__restrict__ x, const T *__restrict__ invdiag, T a, T bc, T c, int flags,
+            int mode) {
+  cheb_body<T, SEM, VEC>(blockIdx.x, b, n, wsrc, bvec, r_in, r_out, d, x, invdiag, a, bc, c, flags, mode);
+}
+
 // rw = (b - DSS(wL)) / multiplicity  (or b / multiplicity when wL is null): the
 // weighted residual W_f r_f that the restriction P^T consumes.
 template <typename T, int VEC>
-__global__ void __launch_bounds__(256)
-resid_weight_kernel(Box b, int64_t n, const T *__restrict__ wL, const T *__restrict__ bvec,
-                    T *__restrict__ rw) {
-  const int64_t g0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+__device__ __forceinline__ void resid_weight_body(unsigned blk, const Box &b, int64_t n, const T *__restrict__ wL,
+                                                  const T *__restrict__ bvec, T *__restrict__ rw) {
+  const int64_t g0 = ((int64_t)blk * blockDim.x + threadIdx.x) * VEC;
   if (g0 >= n) return;
   const bool full = g0 + VEC <= n;
   const int cnt = full ? VEC : (int)(n - g0);
@@ -412,6 +192,13 @@ resid_weight_kernel(Box b, int64_t n, const T *__restrict__ wL, const T *__restr
   }
 }
 
+template <typename T, int VEC>
+__global__ void __launch_bounds__(256)
+resid_weight_kernel(Box b, int64_t n, const T *__restrict__ wL, const T *__restrict__ bvec,
+                    T *__restrict__ rw) {
+  resid_weight_body<T, VEC>(blockIdx.x, b, n, wL, bvec, rw);
+}
+
 // FD: residual r = b - Ad (plain global vectors)
 template <typename T>
 __global__ void resid_plain_kernel(int64_t n, const T *__restrict__ ad, const T *__restrict__ bvec,
@@ -425,15 +212,13 @@ __global__ void resid_plain_kernel(int64_t n, const T *__restrict__ ad, const T 
 // Restriction P^T: for every coarse element, gather the weighted fine residual,
 // contract with J^T along i, j, k and write coarse element-local values.
 template <typename T>
-__global__ void __launch_bounds__(256)
-restrict_kernel(Box fb, Box cb, int64_t E, const T *__restrict__ rw, const T *__restrict__ Jm,
-                T *__restrict__ rcL) {
+__device__ __forceinline__ void restrict_body(int64_t e, const Box &fb, const Box &cb, int64_t E,
+                                              const T *__restrict__ rw, const T *__restrict__ Jm,
+                                              T *__restrict__ rcL, T *smem) {
   const int nf = fb.N + 1, nc = cb.N + 1;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *sJ = reinterpret_cast<T *>(smem_raw);      // nf*nc
+  T *sJ = smem;                                 // nf*nc
   T *sf = sJ + nf * nc;                         // nf^3 (later nf*nc*nc)
   T *t1 = sf + nf * nf * nf;                    // nf*nf*nc
-  const int64_t e = blockIdx.x;
   if (e >= E) return;
   const int ex = (int)(e % fb.nex), ey = (int)((e / fb.nex) % fb.ney), ez = (int)(e / ((int64_t)fb.nex * fb.ney));
   for (int q = threadIdx.x; q < nf * nc; q += blockDim.x) sJ[q] = Jm[q];
@@ -469,19 +254,25 @@ restrict_kernel(Box fb, Box cb, int64_t E, const T *__restrict__ rw, const T *__
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256)
+restrict_kernel(Box fb, Box cb, int64_t E, const T *__restrict__ rw, const T *__restrict__ Jm,
+                T *__restrict__ rcL) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  restrict_body<T>(blockIdx.x, fb, cb, E, rw, Jm, rcL, reinterpret_cast<T *>(smem_raw));
+}
+
 // Prolongation x_f += P x_c: every fine element interpolates the coarse element
 // values and updates the fine unknowns it owns (local i, j, k < N_f).
 template <typename T>
-__global__ void __launch_bounds__(256)
-prolong_kernel(Box fb, Box cb, int64_t E, const T *__restrict__ xc, const T *__restrict__ Jm,
-               T *__restrict__ xf, double *__restrict__ zout) {
+__device__ __forceinline__ void prolong_body(int64_t e, const Box &fb, const Box &cb, int64_t E,
+                                             const T *__restrict__ xc, const T *__restrict__ Jm,
+                                             T *__restrict__ xf, double *__restrict__ zout, T *smem) {
   const int nf = fb.N + 1, nc = cb.N + 1;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *sJ = reinterpret_cast<T *>(smem_raw);      // nf*nc
+  T *sJ = smem;                                 // nf*nc
   T *sc = sJ + nf * nc;                         // nc^3
   T *t1 = sc + nc * nc * nc;                    // nc*nc*nf
   T *t2 = t1 + nc * nc * nf;                    // nc*nf*nf
-  const int64_t e = blockIdx.x;
   if (e >= E) return;
   const int ex = (int)(e % fb.nex), ey = (int)((e / fb.nex) % fb.ney), ez = (int)(e / ((int64_t)fb.nex * fb.ney));
   for (int q = threadIdx.x; q < nf * nc; q += blockDim.x) sJ[q] = Jm[q];
@@ -518,6 +309,14 @@ prolong_kernel(Box fb, Box cb, int64_t E, const T *__restrict__ xc, const T *__r
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256)
+prolong_kernel(Box fb, Box cb, int64_t E, const T *__restrict__ xc, const T *__restrict__ Jm,
+               T *__restrict__ xf, double *__restrict__ zout) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  prolong_body<T>(blockIdx.x, fb, cb, E, xc, Jm, xf, zout, reinterpret_cast<T *>(smem_raw));
+}
+
 // ------------------------------------------------------------------ sparse / dense
 // y = A x (mode 0), y = b - A x (mode 1), y += A x (mode 2); one thread per row.
 template <typename T>
@@ -539,12 +338,11 @@ __global__ void csr_kernel(int64_t nrows, const int64_t *__restrict__ rp, const 
 // whole row is in flight at once; rows are short (about 1e3 entries) and the
 // solve chains dozens of these products, so latency rather than bandwidth decides.
 constexpr int kGemvUnroll = 8;
-__global__ void __launch_bounds__(256)
-gemv_kernel(int64_t nrows, int64_t n1c, const double *__restrict__ M1, const double *__restrict__ x1,
-            int64_t n2c, const double *__restrict__ M2, const double *__restrict__ x2,
-            const double *__restrict__ bvec, double *__restrict__ y, int sub) {
+__device__ __forceinline__ void gemv_row(int64_t row, int64_t nrows, int64_t n1c, const double *__restrict__ M1,
+                                         const double *__restrict__ x1, int64_t n2c,
+                                         const double *__restrict__ M2, const double *__restrict__ x2,
+                                         const double *__restrict__ bvec, double *__restrict__ y, int sub) {
   __shared__ double sm[4];
-  const int64_t row = blockIdx.x;
   if (row >= nrows) return;
   double acc = 0.0;
   for (int64_t c0 = 0; c0 < n1c; c0 += 256 * kGemvUnroll) {
@@ -573,6 +371,13 @@ gemv_kernel(int64_t nrows, int64_t n1c, const double *__restrict__ M1, const dou
   }
   const double s = block_sum(acc, sm);
   if (threadIdx.x == 0) y[row] = sub ? bvec[row] - s : s;
+}
+
+__global__ void __launch_bounds__(256)
+gemv_kernel(int64_t nrows, int64_t n1c, const double *__restrict__ M1, const double *__restrict__ x1,
+            int64_t n2c, const double *__restrict__ M2, const double *__restrict__ x2,
+            const double *__restrict__ bvec, double *__restrict__ y, int sub) {
+  gemv_row(blockIdx.x, nrows, n1c, M1, x1, n2c, M2, x2, bvec, y, sub);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -746,24 +551,236 @@ adjoint_kernel(Box b, int64_t E, const double *__restrict__ lam, const double *_
   }
 }
 
+// ------------------------------------------------------------------ batched kernels
+// A batched launch covers the active systems of a batch: blocks [begin[k],
+// begin[k+1]) of the grid belong to system sys[k] of the launch table, and run the
+// same bodies as the single-system kernels on that system's level data.
+__device__ __forceinline__ int table_slot(const LaunchTable &t, unsigned b) {
+  int lo = 0, hi = t.count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((unsigned)t.begin[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+__device__ __forceinline__ Box lbox(const BatchLevelDev &L) {
+  return Box{L.N, L.nex, L.ney, L.nez, L.nx, L.ny, L.nz};
+}
+#define SEMCHEB_BATCH_SYS                                  \
+  const int slot_ = table_slot(tab, blockIdx.x);           \
+  const BatchSysDev &S = sys[tab.sys[slot_]];              \
+  const unsigned blk = blockIdx.x - (unsigned)tab.begin[slot_];
+
+// single-precision operator of a cycle level: src 0 applies to d, 1 to x
+template <int N>
+__global__ void __launch_bounds__(AxShape<N>::block)
+b_ax32_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, int level, int src) {
+  SEMCHEB_BATCH_SYS
+  const BatchLevelDev &L = S.lev[level];
+  ax_body<N, float, uint16_t>(blk, lbox(L), L.E, src == 0 ? L.d : L.x, L.G, L.D, L.w);
+}
+
+// FP64 operator on the finest level applied to the Krylov direction p
+template <int N>
+__global__ void __launch_bounds__(AxShape<N>::block)
+b_ax64_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys) {
+  SEMCHEB_BATCH_SYS
+  const BatchLevelDev &L = S.lev[0];
+  ax_body<N, double, double>(blk, lbox(L), L.E, S.p, L.G64, L.D64, L.w64);
+}
+
+__global__ void __launch_bounds__(256)
+b_cheb_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, int level, int pp, int step, int flags,
+              int mode) {
+  SEMCHEB_BATCH_SYS
+  const BatchLevelDev &L = S.lev[level];
+  const double *cf = L.coef[pp][step];
+  cheb_body<float, true, 4>(blk, lbox(L), L.n, L.w, L.b, L.r, L.r, L.d, L.x, L.inv, (float)cf[0], (float)cf[1],
+                            (float)cf[2], flags, mode);
+}
+
+__global__ void __launch_bounds__(256)
+b_resid_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, int level, int has_w) {
+  SEMCHEB_BATCH_SYS
+  const BatchLevelDev &L = S.lev[level];
+  resid_weight_body<float, 4>(blk, lbox(L), L.n, has_w ? L.w : nullptr, L.b, L.r);
+}
+
+__global__ void __launch_bounds__(256)
+b_restrict_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, int level) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  SEMCHEB_BATCH_SYS
+  const BatchLevelDev &F = S.lev[level], &C = S.lev[level + 1];
+  restrict_body<float>(blk, lbox(F), lbox(C), F.E, F.r, F.J, C.w, reinterpret_cast<float *>(smem_raw));
+}
+
+// coarse right-hand side: b = DSS of the restricted element-local values
+__global__ void __launch_bounds__(256)
+b_dss_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, int level) {
+  SEMCHEB_BATCH_SYS
+  const BatchLevelDev &L = S.lev[level];
+  const int64_t g = (int64_t)blk * blockDim.x + threadIdx.x;
+  if (g < L.n) L.b[g] = dss_at(L.w, lbox(L), g);
+}
+
+__global__ void __launch_bounds__(256)
+b_prolong_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, int level, int to_z) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  SEMCHEB_BATCH_SYS
+  const BatchLevelDev &F = S.lev[level], &C = S.lev[level + 1];
+  prolong_body<float>(blk, lbox(F), lbox(C), F.E, C.x, F.J, F.x, to_z ? S.z : nullptr,
+                      reinterpret_cast<float *>(smem_raw));
+}
+
+// conversions: 0 coarse b (FP32 -> FP64), 1 coarse x (FP64 -> FP32),
+// 2 Krylov r[par] -> finest cycle b, 3 finest cycle x -> z
+__global__ void __launch_bounds__(256)
+b_convert_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, int op, int par) {
+  SEMCHEB_BATCH_SYS
+  const int64_t g = (int64_t)blk * blockDim.x + threadIdx.x;
+  const BatchLevelDev &C = S.lev[kBatchLevels - 1], &F = S.lev[0];
+  if (op == 0) { if (g < S.nc) S.cb[g] = (double)C.b[g]; }
+  else if (op == 1) { if (g < S.nc) C.x[g] = (float)S.cx[g]; }
+  else if (op == 2) { if (g < F.n) F.b[g] = (float)S.r[par][g]; }
+  else { if (g < F.n) S.z[g] = (double)F.x[g]; }
+}
+
+// exact coarse solve, one block per row of the dense inverse
+__global__ void __launch_bounds__(256)
+b_coarse_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys) {
+  SEMCHEB_BATCH_SYS
+  gemv_row(blk, S.nc, S.nc, S.Minv, S.cb, 0, nullptr, nullptr, nullptr, S.cx, 0);
+}
+
+// Krylov apply: w = DSS(w64) with partials of p . w
+__global__ void __launch_bounds__(256)
+b_dssdot_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, double *__restrict__ partials) {
+  SEMCHEB_BATCH_SYS
+  const BatchLevelDev &L = S.lev[0];
+  dss_dot_body<double, 2>(blk, lbox(L), L.n, L.w64, S.w, S.p, partials + blockIdx.x);
+}
+
+// per-system reduction of the partials written by a launch with the same table
+__global__ void __launch_bounds__(256)
+b_finalize_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, const double *__restrict__ partials,
+                  int nd, int slot, int op) {
+  __shared__ double sm[4];
+  __shared__ double res[3];
+  const int k = blockIdx.x;
+  double *scal = sys[tab.sys[k]].scal;
+  const int b0 = tab.begin[k], b1 = tab.begin[k + 1];
+  for (int q = 0; q < nd; ++q) {
+    double a = 0.0;
+    for (int bq = b0 + (int)threadIdx.x; bq < b1; bq += blockDim.x) a += partials[(int64_t)bq * nd + q];
+    const double s = block_sum(a, sm);
+    if (threadIdx.x == 0) res[q] = s;
+  }
+  if (threadIdx.x != 0) return;
+  for (int q = 0; q < nd; ++q) scal[slot + q] = res[q];
+  if (op == FIN_INIT_RZ) {
+    scal[S_RZ] = res[0];
+    scal[S_BETA] = 0.0;
+  } else if (op == FIN_BETA_PCG || op == FIN_BETA_FCG) {
+    const double rz_old = scal[S_RZ];
+    const double num = (op == FIN_BETA_FCG) ? res[0] - res[1] : res[0];
+    scal[S_BETA] = num / rz_old;
+    scal[S_RZ] = res[0];
+  }
+}
+
+// u += alpha p; r[par^1] = r[par] - alpha w (also in FP32 into the cycle input); partial ||r||^2
+__global__ void __launch_bounds__(256)
+b_update_xr_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, int par, double *__restrict__ partials) {
+  __shared__ double sm[4];
+  SEMCHEB_BATCH_SYS
+  const int64_t n = S.lev[0].n;
+  const int64_t g = (int64_t)blk * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (g < n) {
+    const double alpha = S.scal[S_RZ] / S.scal[S_PW];
+    S.u[g] = S.u[g] + alpha * S.p[g];
+    const double rv = S.r[par][g] - alpha * S.w[g];
+    S.r[par ^ 1][g] = rv;
+    S.lev[0].b[g] = (float)rv;
+    acc = rv * rv;
+  }
+  const double s = block_sum(acc, sm);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// dot products: what 0 -> (z.r[par], z.r[par^1]); 1 -> b.b; 2 -> r[par].z
+__global__ void __launch_bounds__(256)
+b_dots_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, int par, int what,
+              double *__restrict__ partials) {
+  __shared__ double sm[4];
+  SEMCHEB_BATCH_SYS
+  const int64_t n = S.lev[0].n;
+  const int64_t g = (int64_t)blk * blockDim.x + threadIdx.x;
+  double a0 = 0.0, a1 = 0.0;
+  if (g < n) {
+    if (what == 0) {
+      a0 = S.z[g] * S.r[par][g];
+      a1 = S.z[g] * S.r[par ^ 1][g];
+    } else if (what == 1) {
+      a0 = S.b[g] * S.b[g];
+    } else {
+      a0 = S.r[par][g] * S.z[g];
+    }
+  }
+  const int nd = what == 0 ? 2 : 1;
+  double s = block_sum(a0, sm);
+  if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * nd] = s;
+  if (nd > 1) {
+    s = block_sum(a1, sm);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * nd + 1] = s;
+  }
+}
+
+// op 0: p = z + beta p; op 1: p = z; op 2: start (r[0] = b, u = 0, cycle input = b in FP32)
+__global__ void __launch_bounds__(256)
+b_vec_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, int op) {
+  SEMCHEB_BATCH_SYS
+  const int64_t n = S.lev[0].n;
+  const int64_t g = (int64_t)blk * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  if (op == 0) S.p[g] = S.z[g] + S.scal[S_BETA] * S.p[g];
+  else if (op == 1) S.p[g] = S.z[g];
+  else {
+    S.r[0][g] = S.b[g];
+    S.u[g] = 0.0;
+    S.lev[0].b[g] = (float)S.b[g];
+  }
+}
+
 inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
 inline Box mkbox(const Level &L) { return Box{L.N, L.nex, L.ney, L.nez, L.nx, L.ny, L.nz}; }
 inline bool al16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+// variant 0: prefetch, compiler's register choice; 1: no prefetch, AxShape::min_waves;
+// 2: prefetch, AxShape::min_waves
 template <int N, typename T, typename GT>
-void launch_ax_n(const Level &L, const T *u, const GT *G, const T *D, T *wL, hipStream_t s) {
+void launch_ax_n(const Level &L, const T *u, const GT *G, const T *D, T *wL, int variant, hipStream_t s) {
   using S = AxShape<N>;
   const unsigned grid = (unsigned)((L.E + S::epb - 1) / S::epb);
-  hipLaunchKernelGGL((ax_local_kernel<N, T, GT>), dim3(grid), dim3(S::block), 0, s, mkbox(L), L.E, u,
-                     G, D, wL);
+  if (variant == 1)
+    hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, S::min_waves>), dim3(grid), dim3(S::block), 0, s, mkbox(L),
+                       L.E, u, G, D, wL);
+  else if (variant == 2)
+    hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 1, S::min_waves>), dim3(grid), dim3(S::block), 0, s, mkbox(L),
+                       L.E, u, G, D, wL);
+  else
+    hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 1, 1>), dim3(grid), dim3(S::block), 0, s, mkbox(L), L.E, u, G,
+                       D, wL);
 }
 
 template <typename T, typename GT>
 bool launch_ax_t(const Level &L, const T *u, const GT *G, const T *D, T *wL, hipStream_t s) {
+  const int variant = sizeof(T) == 8 ? L.ax_variant64 : L.ax_variant32;
   switch (L.N) {
 #define SEMCHEB_AX_CASE(n) \
-  case n: launch_ax_n<n, T, GT>(L, u, G, D, wL, s); return true;
+  case n: launch_ax_n<n, T, GT>(L, u, G, D, wL, variant, s); return true;
     SEMCHEB_AX_CASE(1) SEMCHEB_AX_CASE(2) SEMCHEB_AX_CASE(3) SEMCHEB_AX_CASE(4)
     SEMCHEB_AX_CASE(5) SEMCHEB_AX_CASE(6) SEMCHEB_AX_CASE(7) SEMCHEB_AX_CASE(8)
     SEMCHEB_AX_CASE(9) SEMCHEB_AX_CASE(10) SEMCHEB_AX_CASE(11) SEMCHEB_AX_CASE(12)
@@ -948,4 +965,88 @@ bool launch_adjoint(const Level &L, const double *lam, const double *u, double *
   }
 }
 
+}  // namespace semcheb
+
+// ------------------------------------------------------------------ batched launchers
+namespace semcheb {
+namespace {
+inline unsigned tgrid(const LaunchTable &t) { return (unsigned)t.begin[t.count]; }
+template <int N>
+void b_ax32_n(const LaunchTable &t, const BatchSysDev *sys, int level, int src, hipStream_t s) {
+  hipLaunchKernelGGL((b_ax32_kernel<N>), dim3(tgrid(t)), dim3(AxShape<N>::block), 0, s, t, sys, level, src);
+}
+template <int N>
+void b_ax64_n(const LaunchTable &t, const BatchSysDev *sys, hipStream_t s) {
+  hipLaunchKernelGGL((b_ax64_kernel<N>), dim3(tgrid(t)), dim3(AxShape<N>::block), 0, s, t, sys);
+}
+}  // namespace
+
+int batch_ax_elements_per_block(int N) {
+  const int tpe = (N + 1) * (N + 1);
+  return tpe <= 64 ? 64 / tpe : 1;
+}
+
+bool launch_b_ax32(int N, const LaunchTable &t, const BatchSysDev *sys, int level, int src, hipStream_t s) {
+  if (t.count == 0) return true;
+  switch (N) {
+#define SEMCHEB_BAX(n) \
+  case n: b_ax32_n<n>(t, sys, level, src, s); return true;
+    SEMCHEB_BAX(1) SEMCHEB_BAX(2) SEMCHEB_BAX(3) SEMCHEB_BAX(4) SEMCHEB_BAX(5) SEMCHEB_BAX(6)
+    SEMCHEB_BAX(7) SEMCHEB_BAX(8) SEMCHEB_BAX(9) SEMCHEB_BAX(10) SEMCHEB_BAX(11) SEMCHEB_BAX(12)
+#undef SEMCHEB_BAX
+    default: return false;
+  }
+}
+
+bool launch_b_ax64(int N, const LaunchTable &t, const BatchSysDev *sys, hipStream_t s) {
+  if (t.count == 0) return true;
+  switch (N) {
+#define SEMCHEB_BAX(n) \
+  case n: b_ax64_n<n>(t, sys, s); return true;
+    SEMCHEB_BAX(1) SEMCHEB_BAX(2) SEMCHEB_BAX(3) SEMCHEB_BAX(4) SEMCHEB_BAX(5) SEMCHEB_BAX(6)
+    SEMCHEB_BAX(7) SEMCHEB_BAX(8) SEMCHEB_BAX(9) SEMCHEB_BAX(10) SEMCHEB_BAX(11) SEMCHEB_BAX(12)
+#undef SEMCHEB_BAX
+    default: return false;
+  }
+}
+
+void launch_b_cheb(const LaunchTable &t, const BatchSysDev *sys, int level, int pp, int step, int flags, int mode,
+                   hipStream_t s) {
+  if (t.count) hipLaunchKernelGGL(b_cheb_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, level, pp, step, flags, mode);
+}
+void launch_b_resid(const LaunchTable &t, const BatchSysDev *sys, int level, int has_w, hipStream_t s) {
+  if (t.count) hipLaunchKernelGGL(b_resid_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, level, has_w);
+}
+void launch_b_restrict(const LaunchTable &t, const BatchSysDev *sys, int level, size_t lds, hipStream_t s) {
+  if (t.count) hipLaunchKernelGGL(b_restrict_kernel, dim3(tgrid(t)), dim3(128), lds, s, t, sys, level);
+}
+void launch_b_dss(const LaunchTable &t, const BatchSysDev *sys, int level, hipStream_t s) {
+  if (t.count) hipLaunchKernelGGL(b_dss_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, level);
+}
+void launch_b_prolong(const LaunchTable &t, const BatchSysDev *sys, int level, int to_z, size_t lds, hipStream_t s) {
+  if (t.count) hipLaunchKernelGGL(b_prolong_kernel, dim3(tgrid(t)), dim3(128), lds, s, t, sys, level, to_z);
+}
+void launch_b_convert(const LaunchTable &t, const BatchSysDev *sys, int op, int par, hipStream_t s) {
+  if (t.count) hipLaunchKernelGGL(b_convert_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, op, par);
+}
+void launch_b_coarse(const LaunchTable &t, const BatchSysDev *sys, hipStream_t s) {
+  if (t.count) hipLaunchKernelGGL(b_coarse_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys);
+}
+void launch_b_dssdot(const LaunchTable &t, const BatchSysDev *sys, double *partials, hipStream_t s) {
+  if (t.count) hipLaunchKernelGGL(b_dssdot_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, partials);
+}
+void launch_b_finalize(const LaunchTable &t, const BatchSysDev *sys, const double *partials, int nd, int slot, int op,
+                       hipStream_t s) {
+  if (t.count)
+    hipLaunchKernelGGL(b_finalize_kernel, dim3((unsigned)t.count), dim3(256), 0, s, t, sys, partials, nd, slot, op);
+}
+void launch_b_update_xr(const LaunchTable &t, const BatchSysDev *sys, int par, double *partials, hipStream_t s) {
+  if (t.count) hipLaunchKernelGGL(b_update_xr_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, par, partials);
+}
+void launch_b_dots(const LaunchTable &t, const BatchSysDev *sys, int par, int what, double *partials, hipStream_t s) {
+  if (t.count) hipLaunchKernelGGL(b_dots_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, par, what, partials);
+}
+void launch_b_vec(const LaunchTable &t, const BatchSysDev *sys, int op, hipStream_t s) {
+  if (t.count) hipLaunchKernelGGL(b_vec_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, op);
+}
 }  // namespace semcheb

@@ -218,6 +218,51 @@ class FdSolver(_Base):
         self._ctx = ctx
 
 
+class BatchedSolver(_Base):
+    """Many independent SEM systems (own meshes and orders) solved together: every
+    kernel launch of a solve covers all systems that have not converged.
+
+    verts_list: list of (nez+1, ney+1, nex+1, 3) vertex arrays; orders: list of N.
+    Vectors are concatenated over the systems (see `offsets`).
+    """
+
+    def __init__(self, verts_list, orders, smoother="cheb4opt", pre=4, post=0, krylov="fcg",
+                 lambda_scale=1.0, device=0):
+        super().__init__()
+        nsys = len(verts_list)
+        self._verts = [np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for v in verts_list]
+        meshes = (L.SemBoxMesh * nsys)()
+        for q, v in enumerate(self._verts):
+            meshes[q] = L.SemBoxMesh(v.shape[2] - 1, v.shape[1] - 1, v.shape[0] - 1,
+                                     v.ctypes.data_as(C.POINTER(C.c_double)))
+        ords = (C.c_int32 * nsys)(*[int(o) for o in orders])
+        opt = L.make_options(int(orders[0]), smoother, pre, post, "mixed", krylov, None, None,
+                             lambda_scale, device)
+        ctx = C.c_void_p()
+        L.check(self._lib.sem_setup_batched(nsys, meshes, ords, C.byref(opt), _stream(), C.byref(ctx)))
+        self._ctx = ctx
+        self.nsys = nsys
+        offs = (C.c_int64 * (nsys + 1))()
+        L.check(self._lib.sem_batch_info(self._ctx, None, offs), self._ctx)
+        self.offsets = list(offs)
+
+    @property
+    def n(self) -> int:
+        return self.offsets[-1]
+
+    def solve(self, b, rtol: float = 1e-8, maxit: int = 500):
+        """Returns (u, status, iterations per system, relative residual per system)."""
+        torch = _torch()
+        u = torch.empty_like(b)
+        its = (C.c_int32 * self.nsys)()
+        rel = (C.c_double * self.nsys)()
+        st = self._lib.sem_solve_batched(self._ctx, _ptr(b), _ptr(u), float(rtol), int(maxit), its, rel,
+                                         _stream())
+        if st not in (L.SEM_OK, L.SEM_ENOTCONV):
+            L.check(st, self._ctx)
+        return u, st, list(its), list(rel)
+
+
 def beta_table(k: int) -> list:
     lib = L.load()
     out = (C.c_double * k)()
