@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -80,19 +81,50 @@ def log(msg):
 
 
 def time_solves(solver, b, steps, warmup):
+    """Mean time per solve over `steps` back-to-back solves, plus each solve's own wall time
+    (a solve ends with a stream synchronisation, so the per-solve times are exact)."""
     import torch
     info = None
     for _ in range(warmup):
         _, info = solver.solve(b, rtol=1e-8, maxit=500)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    its = []
+    its, each = [], []
     for _ in range(steps):
+        t1 = time.perf_counter()
         u, info = solver.solve(b, rtol=1e-8, maxit=500)
+        each.append(time.perf_counter() - t1)
         its.append(info.iterations)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    return u, info, dt, its
+    return u, info, dt, its, each
+
+
+# operator variant index -> (prefetch, occupancy, tile) template arguments; N <= 7 asks for 4 waves
+def _variant_args(variant, N):
+    mw = 4 if N <= 7 else 2
+    return {0: (1, 1, 0), 1: (0, mw, 0), 2: (1, mw, 0), 3: (1, 1, 1), 4: (0, mw, 1), 5: (0, mw, 2)}[variant]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE in KiB per dispatch, scaled by the factors a 1 GiB copy gives); None when the
+    summary does not cover this kernel."""
+    path = os.path.join(ROOT, "profiles", "ax_n7_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    sf = sw = None
+    row = None
+    for line in open(path):
+        if line.startswith("Calibration:"):
+            mt = re.search(r"FETCH_SIZE is scaled by ([0-9.]+) and WRITE_SIZE by ([0-9.]+?)\.?\s*$", line)
+            if mt:
+                sf, sw = float(mt.group(1)), float(mt.group(2))
+        if row is None and line.startswith(f"| `{kernel}`"):  # first table: FETCH / WRITE KiB
+            row = [c.strip() for c in line.strip().strip("|").split("|")]
+    if sf is None or row is None:
+        return None
+    return float(row[1]) * 1024 * sf + float(row[2]) * 1024 * sw
 
 
 def time_kernel(fn, reps):
@@ -216,9 +248,9 @@ def main():
     bh = b0 + 1e-3 * np.max(np.abs(b0)) * wl.uniform_noise(n, 0)
     b = torch.from_numpy(bh).cuda()
 
-    u64, info64, dt64, its64 = time_solves(s64, b, args.steps, args.warmup)
+    u64, info64, dt64, its64, each64 = time_solves(s64, b, args.steps, args.warmup)
     log(f"fp64: {info64.iterations} its, {dt64 * 1e3:.2f} ms/solve")
-    umx, infomx, dtmx, itsmx = time_solves(smx, b, args.steps, args.warmup)
+    umx, infomx, dtmx, itsmx, eachmx = time_solves(smx, b, args.steps, args.warmup)
     log(f"mixed: {infomx.iterations} its, {dtmx * 1e3:.2f} ms/solve")
 
     def true_rel(u):
@@ -245,6 +277,14 @@ def main():
     gdof_mx = n * infomx.iterations / dtmx / 1e9
     gdof_64 = n * info64.iterations / dt64 / 1e9
     ach = bytes64 / t_ax64 / 1e9
+    tune64 = s64.host_array("ax_tuning", 0)
+    tunemx = smx.host_array("ax_tuning", 0)
+    nvar = (len(tune64) // s64.num_levels - 2) // 2  # per level: variant, times (FP64), variant, times
+    v64, vmx = int(tune64[0]), int(tunemx[1 + nvar])
+    k64 = "ax_local_kernel<%d, double, double, %d, %d, %d>" % ((N,) + _variant_args(v64, N))
+    kmx = "ax_local_kernel<%d, float, bf16, %d, %d, %d>" % ((N,) + _variant_args(vmx, N))
+    tr64 = measured_traffic(k64) if N == 7 and m == 32 else None
+    trmx = measured_traffic(kmx) if N == 7 and m == 32 else None
     out = {
         "metric": "PCG-to-1e-8 solve time & GDOF-iter/s; mixed/batched vs plain FP64 same GPU",
         "value": round(gdof_mx, 4),
@@ -264,16 +304,24 @@ def main():
         "iterations": infomx.iterations,
         "true_relres": relmx,
         "rel_diff_to_fp64_solution": err_mx,
-        "fp64": {"ms_per_solve": round(dt64 * 1e3, 4), "iterations": info64.iterations,
+        "ms_min": round(min(eachmx) * 1e3, 4),
+        "ms_median": round(float(np.median(eachmx)) * 1e3, 4),
+        "fp64": {"ms_per_solve": round(dt64 * 1e3, 4), "ms_min": round(min(each64) * 1e3, 4),
+                 "ms_median": round(float(np.median(each64)) * 1e3, 4), "iterations": info64.iterations,
                  "gdof_iter_per_s": round(gdof_64, 4), "true_relres": rel64},
         "speedup_mixed_vs_fp64": round(dt64 / dtmx, 4),
         "setup_s": {"fp64": round(t_setup64, 2), "mixed": round(t_setupmx, 2)},
+        # traffic: measured HBM bytes per launch (profiler counters, committed summary) over the
+        # same launch time as `achieved`, in GB/s; null when the summary does not cover the kernel
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "ax_local_kernel<7,double,double>", "kernel_us": round(t_ax64 * 1e6, 2),
-                     "bytes_per_launch": bytes64,
-                     "mixed_kernel": {"kernel": "ax_local_kernel<7,float,bf16>", "kernel_us": round(t_axmx * 1e6, 2),
-                                      "achieved": round(bytesmx / t_axmx / 1e9, 1)}},
+                     "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": round(tr64 / t_ax64 / 1e9, 1) if tr64 else None,
+                     "kernel": k64, "kernel_us": round(t_ax64 * 1e6, 2),
+                     "bytes_per_launch": bytes64, "traffic_bytes_per_launch": tr64,
+                     "mixed_kernel": {"kernel": kmx, "kernel_us": round(t_axmx * 1e6, 2),
+                                      "achieved": round(bytesmx / t_axmx / 1e9, 1),
+                                      "bytes_per_launch": bytesmx,
+                                      "traffic": round(trmx / t_axmx / 1e9, 1) if trmx else None}},
     }
     if not args.no_batched:
         log("batched systems ...")

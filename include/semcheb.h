@@ -73,7 +73,9 @@ enum {
   SEM_CHEB4_OPT = 5  /* optimised 4th kind, beta from Table beta_coef (order <= 16) */
 };
 enum { SEM_FP64 = 0, SEM_MIXED = 1 }; /* precision of the V-cycle */
-enum { SEM_PCG = 0, SEM_FCG = 1 };    /* Krylov method */
+/* Krylov method: PCG, flexible CG (Polak-Ribiere beta), or restarted flexible
+ * GMRES(m) with classical Gram-Schmidt (Sec. 6.1: two reductions per iteration) */
+enum { SEM_PCG = 0, SEM_FCG = 1, SEM_GMRES = 2 };
 
 #define SEM_MAX_LEVELS 8
 
@@ -85,12 +87,13 @@ typedef struct {
   int32_t pre_order;                /* m: order of pre-smoothing (0..32) */
   int32_t post_order;               /* n: order of post-smoothing, 0 = one-sided */
   int32_t precision;                /* SEM_FP64 or SEM_MIXED */
-  int32_t krylov;                   /* SEM_PCG or SEM_FCG */
+  int32_t krylov;                   /* SEM_PCG, SEM_FCG or SEM_GMRES */
   int32_t num_lambda_max;           /* 0: estimate every smoothed level at setup */
   double lambda_max[SEM_MAX_LEVELS];/* lambda_max(S_j A_j) per smoothed level */
   double lambda_scale;              /* factor applied to estimated values (0 -> 1) */
   int32_t device;                   /* HIP device ordinal; -1: host-only context */
   int32_t coarse_planes;            /* planes per block of the coarse solve, 0 = auto */
+  int32_t gmres_restart;            /* m of GMRES(m), 1..32; 0 = 30 */
 } sem_options;
 
 /* Structured hexahedral box mesh: (nex+1)(ney+1)(nez+1) vertices, x fastest.
@@ -102,13 +105,16 @@ typedef struct {
 } sem_box_mesh;
 
 /* Fills *opt with: N = 7, default schedule, SEM_CHEB4_OPT, (4,0), FP64,
- * SEM_FCG, estimated lambda_max, lambda_scale 1, device 0. */
+ * SEM_FCG, estimated lambda_max, lambda_scale 1, device 0, GMRES restart 30. */
 void sem_options_default(sem_options *opt);
 
 /* Set up the SEM hierarchy on a box mesh: GLL data, geometric factors, Jacobi
  * diagonals, transfers, lambda_max (Lanczos unless given), and the factored
- * coarse (order 1) operator. Errors: SEM_EINVAL (orders, sizes, opt-4th order
- * > 16), SEM_EMESH (det J <= 0), SEM_ENOMEM, SEM_EHIP, SEM_ENODEV. */
+ * coarse (order 1) operator. Setup also times the element-operator kernel
+ * variants on every smoothed level and keeps the fastest per precision
+ * (environment: SEMCHEB_AUTOTUNE=0 keeps variant 0, SEMCHEB_AX_VARIANT=v fixes
+ * variant v). Errors: SEM_EINVAL (orders, sizes, opt-4th order > 16, variant
+ * out of range), SEM_EMESH (det J <= 0), SEM_ENOMEM, SEM_EHIP, SEM_ENODEV. */
 sem_status sem_setup_box(const sem_box_mesh *mesh, const sem_options *opt, void *stream,
                          sem_ctx **out);
 
@@ -152,7 +158,17 @@ sem_status sem_vcycle(sem_ctx *ctx, const double *r, double *z, void *stream);
  * iterate. iters, relres: host outputs (may be NULL). history: host array
  * of maxit+1 doubles receiving ||r_k||_2, k = 0..iters (may be NULL).
  * Returns SEM_ENOTCONV when maxit is reached, SEM_EBREAKDOWN when r.z <= 0
- * or p.Ap <= 0, SEM_ENAN on a non-finite residual. */
+ * or p.Ap <= 0, SEM_ENAN on a non-finite residual.
+ * With SEM_GMRES the method is right-preconditioned flexible GMRES(m): per
+ * iteration z_j = M v_j (one V-cycle), w = A z_j, the classical Gram-Schmidt
+ * projections h_ij = v_i . w (one reduction), w -= sum h_ij v_i and
+ * h_{j+1,j} = ||w|| (second reduction), Givens rotations on the host; the
+ * residual used for stopping and in `history` is the rotated recurrence
+ * |g_{j+1}|, the true residual norm of the current iterate in exact
+ * arithmetic. Each restart recomputes r = b - A x. The V-cycles of the solve
+ * are captured once per context as HIP graphs (on a private stream) and
+ * replayed on `stream`; SEMCHEB_GRAPHS=0 in the environment at setup launches
+ * them kernel by kernel instead (same kernels, bitwise identical results). */
 sem_status sem_solve(sem_ctx *ctx, const double *b, double *u, double rtol, int32_t maxit,
                      int32_t *iters, double *relres, double *history, void *stream);
 
@@ -186,8 +202,11 @@ sem_status sem_reset_counts(sem_ctx *ctx);
 /* Host copies of setup arrays, for inspection and testing. `what` is one of
  * "gll_nodes", "gll_weights", "deriv", "interp" (to level+1), "factors",
  * "diag", "mass", "coords", "lambda_max", "coarse_matrix" (dense, small
- * problems only). Returns SEM_EINVAL if `n` does not equal the array size,
- * with the size written to *needed when it is not NULL. */
+ * problems only), "ax_tuning" (all levels, `level` ignored: per level the
+ * chosen FP64 operator variant, the measured time in microseconds of each of
+ * the 6 variants (-1 where not timed), then the same for single precision).
+ * Returns SEM_EINVAL if `n` does not equal the array size, with the size
+ * written to *needed when it is not NULL. */
 sem_status sem_host_array(const sem_ctx *ctx, const char *what, int32_t level, double *out,
                           int64_t n, int64_t *needed);
 

@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "SEM_OK", -1: "SEM_EINVAL", -2: "SEM_ENOMEM", -3: "SEM_EHIP",
                 -5: "SEM_ENOTCONV", -6: "SEM_EBREAKDOWN", -7: "SEM_ENAN", -8: "SEM_ENODEV"}
 SMOOTHERS = {"cheb1": 1, "cheb1opt": 2, "cheb4": 4, "cheb4opt": 5}
 PRECISIONS = {"fp64": 0, "mixed": 1}
-KRYLOV = {"pcg": 0, "fcg": 1}
+KRYLOV = {"pcg": 0, "fcg": 1, "gmres": 2}
 MAX_LEVELS = 8
 
 # exported entry points, as declared in include/semcheb.h
@@ -36,7 +36,7 @@ class SemOptions(C.Structure):
         ("smoother", C.c_int32), ("pre_order", C.c_int32), ("post_order", C.c_int32),
         ("precision", C.c_int32), ("krylov", C.c_int32), ("num_lambda_max", C.c_int32),
         ("lambda_max", C.c_double * MAX_LEVELS), ("lambda_scale", C.c_double), ("device", C.c_int32),
-        ("coarse_planes", C.c_int32),
+        ("coarse_planes", C.c_int32), ("gmres_restart", C.c_int32),
     ]
 
 
@@ -107,7 +107,8 @@ def check(status: int, ctx=None) -> int:
 
 
 def make_options(N=7, smoother="cheb4opt", pre=4, post=0, precision="fp64", krylov="fcg",
-                 orders=None, lambda_max=None, lambda_scale=1.0, device=0, coarse_planes=0) -> SemOptions:
+                 orders=None, lambda_max=None, lambda_scale=1.0, device=0, coarse_planes=0,
+                 restart=30) -> SemOptions:
     lib = load()
     o = SemOptions()
     lib.sem_options_default(C.byref(o))
@@ -127,4 +128,5 @@ def make_options(N=7, smoother="cheb4opt", pre=4, post=0, precision="fp64", kryl
     o.lambda_scale = float(lambda_scale)
     o.device = int(device)
     o.coarse_planes = int(coarse_planes)
+    o.gmres_restart = int(restart)
     return o

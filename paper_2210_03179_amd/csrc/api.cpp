@@ -104,7 +104,14 @@ sem_status validate_common(const sem_options *o, std::string &err) {
     return SEM_EINVAL;
   }
   if (o->precision != SEM_FP64 && o->precision != SEM_MIXED) { err = "unknown precision"; return SEM_EINVAL; }
-  if (o->krylov != SEM_PCG && o->krylov != SEM_FCG) { err = "unknown Krylov method"; return SEM_EINVAL; }
+  if (o->krylov != SEM_PCG && o->krylov != SEM_FCG && o->krylov != SEM_GMRES) {
+    err = "unknown Krylov method";
+    return SEM_EINVAL;
+  }
+  if (o->gmres_restart < 0 || o->gmres_restart > kMaxRestart) {
+    err = "gmres_restart must lie in 0..32 (0 = 30)";
+    return SEM_EINVAL;
+  }
   if (o->num_lambda_max < 0 || o->num_lambda_max > SEM_MAX_LEVELS) { err = "bad num_lambda_max"; return SEM_EINVAL; }
   if (o->lambda_scale < 0) { err = "lambda_scale must be >= 0"; return SEM_EINVAL; }
   return SEM_OK;
@@ -202,22 +209,41 @@ void coarse_solve64(sem_ctx *c, const double *b, double *x, hipStream_t s) {
     launch_gemv(C.n, C.n, C.Minv, b, nullptr, x, 0, s);
     return;
   }
-  const int nb = (int)C.start.size() - 1;
-  // forward: y_0 = b_0 (read in place), y_b = b_b - L_b y_{b-1}
-  auto yb = [&](int q) { return (q == 0 ? b : (const double *)C.y) + C.start[q]; };
-  for (int q = 1; q < nb; ++q) {
-    const int64_t P = C.start[q + 1] - C.start[q], Pp = C.start[q] - C.start[q - 1];
-    launch_gemv(P, Pp, C.Lb[q], yb(q - 1), b + C.start[q], C.y + C.start[q], 1, s);
+  // Block-tridiagonal substitution from both ends (blocks above `mid` top-down, below
+  // it bottom-up): each launch advances both sweeps by one block.
+  const int nb = (int)C.start.size() - 1, m = C.mid;
+  auto rows = [&](int q) { return C.start[q + 1] - C.start[q]; };
+  // y of the end blocks is b itself (read in place)
+  auto yb = [&](int q) { return (q == 0 || q == nb - 1 ? b : (const double *)C.y) + C.start[q]; };
+  for (int step = 1;; ++step) {  // forward: y_q = b_q - L_q y_p, p the neighbour away from mid
+    GemvJob jobs[2];
+    int nj = 0;
+    const int top = step, bot = nb - 1 - step;
+    if (top < m) jobs[nj++] = GemvJob{b + C.start[top], C.y + C.start[top], rows(top), 1,
+                                      {{C.Lb[top], yb(top - 1), rows(top - 1), -1.0}}};
+    if (bot > m) jobs[nj++] = GemvJob{b + C.start[bot], C.y + C.start[bot], rows(bot), 1,
+                                      {{C.Lb[bot], yb(bot + 1), rows(bot + 1), -1.0}}};
+    if (nj == 0) break;
+    launch_gemv_jobs(nj, jobs, s);
   }
-  // backward: x_last = S^{-1} y_last, x_b = S_b^{-1} y_b - W_b x_{b+1}
-  {
-    const int q = nb - 1;
-    const int64_t P = C.start[q + 1] - C.start[q];
-    launch_gemv(P, P, C.Mb[q], yb(q), nullptr, x + C.start[q], 0, s);
+  {  // middle: x_m = Minv_m b_m - Xtop y_{m-1} - Xbot y_{m+1}
+    GemvJob jb{nullptr, x + C.start[m], rows(m), 1, {{C.Mb[m], b + C.start[m], rows(m), 1.0}}};
+    if (m > 0) jb.seg[jb.nseg++] = GemvSeg{C.Xtop, yb(m - 1), rows(m - 1), -1.0};
+    if (m < nb - 1) jb.seg[jb.nseg++] = GemvSeg{C.Xbot, yb(m + 1), rows(m + 1), -1.0};
+    launch_gemv_jobs(1, &jb, s);
   }
-  for (int q = nb - 2; q >= 0; --q) {
-    const int64_t P = C.start[q + 1] - C.start[q], Pn = C.start[q + 2] - C.start[q + 1];
-    launch_gemv2(P, P, C.Mb[q], yb(q), Pn, C.Wb[q], x + C.start[q + 1], x + C.start[q], s);
+  for (int step = 1;; ++step) {  // backward: x_q = Minv_q y_q - W_q x_n, n the neighbour towards mid
+    GemvJob jobs[2];
+    int nj = 0;
+    const int top = m - step, bot = m + step;
+    if (top >= 0) jobs[nj++] = GemvJob{nullptr, x + C.start[top], rows(top), 2,
+                                       {{C.Mb[top], yb(top), rows(top), 1.0},
+                                        {C.Wb[top], x + C.start[top + 1], rows(top + 1), -1.0}}};
+    if (bot < nb) jobs[nj++] = GemvJob{nullptr, x + C.start[bot], rows(bot), 2,
+                                       {{C.Mb[bot], yb(bot), rows(bot), 1.0},
+                                        {C.Wb[bot], x + C.start[bot - 1], rows(bot - 1), -1.0}}};
+    if (nj == 0) break;
+    launch_gemv_jobs(nj, jobs, s);
   }
 }
 
@@ -252,7 +278,7 @@ void vcycle(sem_ctx *c, int j, hipStream_t s) {
     apply_level<T>(L, x, w, s);
     launch_resid_weight<T>(L, w, b, r, s);
   } else {
-    hipMemsetAsync(x, 0, L.n * sizeof(T), s);
+    launch_zero<T>(L.n, x, s);
     launch_resid_weight<T>(L, (const T *)nullptr, b, r, s);
   }
   Level &C = c->levels[j + 1];
@@ -290,6 +316,49 @@ void vcycle_top(sem_ctx *c, const double *r, double *z, hipStream_t s, bool r32_
     L0.b64 = sb;
     L0.x64 = sx;
   }
+}
+
+// The V-cycle of the Krylov solve as a replayed HIP graph. A cycle chains dozens of
+// short dependent kernels (most of them in the coarse solve); launched one by one,
+// their host-side launch cost exceeds their run time. The graph of each (r, z)
+// buffer pair is captured once on a private stream; kernel arguments (level
+// buffers, Chebyshev coefficients, operator variants) are fixed after setup, and
+// the cycle records no memset or host copy. Operator-application counters advance
+// by the captured cycle's counts at every replay.
+sem_status vcycle_replay(sem_ctx *c, const double *r, double *z, hipStream_t s, bool r32_ready) {
+  if (!c->use_graphs) {
+    vcycle_top(c, r, z, s, r32_ready);
+    return SEM_OK;
+  }
+  // a mixed cycle whose single-precision input is already in place does not read r
+  const double *key = (c->opt.precision == SEM_MIXED && r32_ready) ? nullptr : r;
+  for (auto &g : c->graphs) {
+    if (g.r == key && g.z == z && g.r32 == r32_ready) {
+      HIPCHK(c, hipGraphLaunch(g.exec, s));
+      for (size_t j = 0; j < c->levels.size(); ++j) c->levels[j].applies += g.applies[j];
+      return SEM_OK;
+    }
+  }
+  if (!c->capture_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+  std::vector<int64_t> before;
+  for (auto &L : c->levels) before.push_back(L.applies);
+  HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeRelaxed));
+  vcycle_top(c, r, z, c->capture_stream, r32_ready);
+  hipGraph_t graph = nullptr;
+  HIPCHK(c, hipStreamEndCapture(c->capture_stream, &graph));
+  sem_ctx::CycleGraph g{key, z, r32_ready, nullptr, {}};
+  const hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    c->err = std::string("hipGraphInstantiate failed: ") + hipGetErrorString(e);
+    return SEM_EHIP;
+  }
+  for (size_t j = 0; j < c->levels.size(); ++j) {
+    g.applies.push_back(c->levels[j].applies - before[j]);
+    c->levels[j].applies = before[j];
+  }
+  c->graphs.push_back(g);
+  return vcycle_replay(c, r, z, s, r32_ready);
 }
 
 // w = A u on the finest level with a reduction partial of p . w when p is given.
@@ -406,8 +475,16 @@ sem_status alloc_krylov(sem_ctx *c, int64_t n) {
   TRY(dalloc(c, &c->kp, n));
   TRY(dalloc(c, &c->kw, n));
   TRY(dalloc(c, &c->scal, S_COUNT));
-  TRY(dalloc(c, &c->partials, std::max<size_t>((size_t)kReduceBlocks * 3, (size_t)(n / 256 + 2))));
+  TRY(dalloc(c, &c->partials, std::max<size_t>((size_t)kReduceBlocks * kMaxRestart, (size_t)(n / 256 + 2))));
   HIPCHK(c, hipHostMalloc((void **)&c->pinned, S_COUNT * sizeof(double), hipHostMallocDefault));
+  if (c->opt.krylov == SEM_GMRES) {
+    const int m = c->opt.gmres_restart > 0 ? c->opt.gmres_restart : 30;
+    c->gld = (n + 31) / 32 * 32;
+    TRY(dalloc(c, &c->gV, (size_t)(m + 1) * c->gld));
+    TRY(dalloc(c, &c->gZ, (size_t)m * c->gld));
+    TRY(dalloc(c, &c->gH, (size_t)kGmresScalars));
+    HIPCHK(c, hipHostMalloc((void **)&c->gpinned, kGmresScalars * sizeof(double), hipHostMallocDefault));
+  }
   return SEM_OK;
 }
 
@@ -415,6 +492,20 @@ sem_status alloc_krylov(sem_ctx *c, int64_t n) {
 // setup stream) and keep the fastest per precision. Variants differ only in load
 // scheduling and register allocation, not in arithmetic, so results are identical.
 sem_status autotune_operator(sem_ctx *c, hipStream_t s) {
+  // SEMCHEB_AX_VARIANT=v fixes variant v on every level (tests cover each variant this
+  // way); SEMCHEB_AUTOTUNE=0 keeps variant 0.
+  if (const char *fv = std::getenv("SEMCHEB_AX_VARIANT")) {
+    const int v = std::atoi(fv);
+    if (v < 0 || v >= kAxVariants) {
+      c->err = "SEMCHEB_AX_VARIANT must be in [0, " + std::to_string(kAxVariants) + ")";
+      return SEM_EINVAL;
+    }
+    for (auto &L : c->levels) {
+      L.ax_variant64 = v < kAxVariants64 ? v : 0;  // variant 5 exists for BF16 factors only
+      L.ax_variant32 = v;
+    }
+    return SEM_OK;
+  }
   const char *env = std::getenv("SEMCHEB_AUTOTUNE");
   if (env && env[0] == '0') return SEM_OK;
   hipEvent_t e0, e1;
@@ -431,7 +522,9 @@ sem_status autotune_operator(sem_ctx *c, hipStream_t s) {
       if (!fp64 && !(mixed && L.Gbf && L.w32)) continue;
       if (fp64 && !L.w64) continue;
       float best = 1e30f;
-      for (int v = 0; v < kAxVariants; ++v) {
+      const int nvar = fp64 ? kAxVariants64 : kAxVariants;
+      for (int v = nvar; v < kAxVariants; ++v) (fp64 ? L.ax_time64_us : L.ax_time32_us)[v] = -1.0f;
+      for (int v = 0; v < nvar; ++v) {
         int &var = fp64 ? L.ax_variant64 : L.ax_variant32;
         var = v;
         auto run = [&]() {
@@ -451,7 +544,7 @@ sem_status autotune_operator(sem_ctx *c, hipStream_t s) {
       }
       const float *tt = fp64 ? L.ax_time64_us : L.ax_time32_us;
       int bv = 0;
-      for (int v = 1; v < kAxVariants; ++v)
+      for (int v = 1; v < nvar; ++v)
         if (tt[v] < tt[bv]) bv = v;
       (fp64 ? L.ax_variant64 : L.ax_variant32) = bv;
     }
@@ -489,6 +582,9 @@ sem_status init_device(sem_ctx *c, hipStream_t s) {
     return SEM_ENODEV;
   }
   HIPCHK(c, hipSetDevice(c->device));
+  // SEMCHEB_GRAPHS=0 launches every V-cycle kernel directly instead of replaying graphs
+  const char *env = std::getenv("SEMCHEB_GRAPHS");
+  c->use_graphs = !(env && env[0] == '0');
   (void)s;
   return SEM_OK;
 }
@@ -617,15 +713,19 @@ sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipS
       TRY(upload(c, &C.Minv, bt.Minv[0].data(), bt.Minv[0].size(), s));
     } else {
       const int nb = (int)start.size() - 1;
+      C.mid = bt.mid;
       C.Mb.assign(nb, nullptr);
       C.Lb.assign(nb, nullptr);
       C.Wb.assign(nb, nullptr);
       for (int q = 0; q < nb; ++q) {
         TRY(upload(c, &C.Mb[q], bt.Minv[q].data(), bt.Minv[q].size(), s));
-        if (q > 0) TRY(upload(c, &C.Lb[q], bt.Lmat[q].data(), bt.Lmat[q].size(), s));
-        if (q + 1 < nb) TRY(upload(c, &C.Wb[q], bt.Wmat[q].data(), bt.Wmat[q].size(), s));
+        if (!bt.Lmat[q].empty()) TRY(upload(c, &C.Lb[q], bt.Lmat[q].data(), bt.Lmat[q].size(), s));
+        if (!bt.Wmat[q].empty()) TRY(upload(c, &C.Wb[q], bt.Wmat[q].data(), bt.Wmat[q].size(), s));
         HIPCHK(c, hipStreamSynchronize(s));
       }
+      if (!bt.Xtop.empty()) TRY(upload(c, &C.Xtop, bt.Xtop.data(), bt.Xtop.size(), s));
+      if (!bt.Xbot.empty()) TRY(upload(c, &C.Xbot, bt.Xbot.data(), bt.Xbot.size(), s));
+      HIPCHK(c, hipStreamSynchronize(s));
     }
   }
   TRY(alloc_krylov(c, c->levels[0].n));
@@ -745,8 +845,12 @@ void release(sem_ctx *c) {
   if (!c->host_only) {
     hipSetDevice(c->device);
     hipDeviceSynchronize();
+    for (auto &g : c->graphs) hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+    if (c->capture_stream) hipStreamDestroy(c->capture_stream);
     for (void *p : c->allocations) hipFree(p);
     if (c->pinned) hipHostFree(c->pinned);
+    if (c->gpinned) hipHostFree(c->gpinned);
   }
   c->allocations.clear();
   delete c;
@@ -775,6 +879,7 @@ void sem_options_default(sem_options *o) {
   o->lambda_scale = 1.0;
   o->device = 0;
   o->coarse_planes = 0;
+  o->gmres_restart = 30;
 }
 
 sem_status sem_setup_box(const sem_box_mesh *mesh, const sem_options *opt, void *stream, sem_ctx **out) {
@@ -854,6 +959,108 @@ sem_status sem_vcycle(sem_ctx *c, const double *r, double *z, void *stream) {
   return SEM_OK;
 }
 
+// Restarted flexible GMRES(m), classical Gram-Schmidt (Sec. 6.1): per iteration one V-cycle,
+// one operator apply, the projections of w on the basis in one reduction (multi-dot), and
+// w -= V h with its norm in the second; the Hessenberg matrix, its Givens rotations and
+// the triangular solve live on the host (m <= 32). r holds r_0 = b - A u on entry,
+// rn = ||r_0||; history[0] is already set by the caller.
+sem_status gmres_solve(sem_ctx *c, const double *b, double *u, double *r, double rr, double bnorm,
+                       double rtol, int32_t maxit, int32_t *iters, double *relres, double *history,
+                       hipStream_t s) {
+  static_assert(kGmresScalars >= 2 * kMaxRestart + 2, "GMRES scalar block too small");
+  if (maxit == 0) {
+    c->err = "maximum number of iterations reached";
+    return SEM_ENOTCONV;
+  }
+  const int64_t n = c->levels[0].n, ld = c->gld;
+  const int m = c->opt.gmres_restart > 0 ? c->opt.gmres_restart : 30;
+  const int nb = kReduceBlocks;
+  double *Vb = c->gV, *Zb = c->gZ, *w = c->kw, *dh = c->gH, *hh = c->gpinned;
+  double *dnrm = dh + kMaxRestart, *dy = dh + kMaxRestart + 1;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  auto Hc = [&](int i, int j) -> double & { return H[(size_t)j * (m + 1) + i]; };
+  int it = 0;
+  bool first = true;
+  for (;;) {
+    double beta = std::sqrt(rr);
+    if (!first) {  // restart: r = b - A u
+      fine_apply(c, u, w, nullptr, s);
+      launch_axpby(n, 1.0, b, -1.0, w, r, s);
+      launch_dots<double>(n, 1, r, r, nullptr, nullptr, nullptr, nullptr, c->partials, nb, s);
+      launch_finalize_many(nb, 1, c->partials, dnrm, s);
+      HIPCHK(c, hipMemcpyAsync(hh + kMaxRestart, dnrm, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      beta = std::sqrt(hh[kMaxRestart]);
+      if (!std::isfinite(beta)) { c->err = "non-finite residual at a GMRES restart"; return SEM_ENAN; }
+      if (beta <= rtol * bnorm) return SEM_OK;
+    } else {
+      hh[kMaxRestart] = rr;  // ||r_0||^2 as reduced on the device
+      HIPCHK(c, hipMemcpyAsync(dnrm, hh + kMaxRestart, sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    first = false;
+    launch_scale_inv_sqrt(n, r, dnrm, Vb, s);  // v_0 = r / beta
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    bool done = false;
+    for (int j = 0; j < m; ++j) {
+      double *vj = Vb + (int64_t)j * ld, *zj = Zb + (int64_t)j * ld;
+      TRY(vcycle_replay(c, vj, zj, s, false));  // z_j = M v_j
+      fine_apply(c, zj, w, nullptr, s);           // w = A z_j
+      launch_multi_dot(n, j + 1, Vb, ld, w, c->partials, nb, s);
+      launch_finalize_many(nb, j + 1, c->partials, dh, s);
+      launch_multi_axpy(n, j + 1, Vb, ld, dh, -1.0, w, c->partials, nb, s);
+      launch_finalize_many(nb, 1, c->partials, dnrm, s);
+      HIPCHK(c, hipMemcpyAsync(hh, dh, (kMaxRestart + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      const double hn = std::sqrt(hh[kMaxRestart]);
+      bool finite = std::isfinite(hn);
+      for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(hh[i]);
+      if (!finite) { c->err = "non-finite value in the GMRES iteration"; return SEM_ENAN; }
+      for (int i = 0; i <= j; ++i) Hc(i, j) = hh[i];
+      Hc(j + 1, j) = hn;
+      if (hn > 0.0) launch_scale_inv_sqrt(n, w, dnrm, Vb + (int64_t)(j + 1) * ld, s);
+      for (int i = 0; i < j; ++i) {  // previous rotations
+        const double t = cs[i] * Hc(i, j) + sn[i] * Hc(i + 1, j);
+        Hc(i + 1, j) = -sn[i] * Hc(i, j) + cs[i] * Hc(i + 1, j);
+        Hc(i, j) = t;
+      }
+      const double d = std::sqrt(Hc(j, j) * Hc(j, j) + Hc(j + 1, j) * Hc(j + 1, j));
+      cs[j] = Hc(j, j) / d;
+      sn[j] = Hc(j + 1, j) / d;
+      Hc(j, j) = d;
+      Hc(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++it;
+      k = j + 1;
+      const double res = std::fabs(g[j + 1]);
+      if (history) history[it] = res;
+      if (iters) *iters = it;
+      if (relres) *relres = res / bnorm;
+      if (res <= rtol * bnorm || hn == 0.0) {
+        done = true;
+        break;
+      }
+      if (it >= maxit) break;
+    }
+    for (int i = k - 1; i >= 0; --i) {  // R y = g
+      double acc = g[i];
+      for (int l = i + 1; l < k; ++l) acc -= Hc(i, l) * y[l];
+      y[i] = acc / Hc(i, i);
+    }
+    for (int i = 0; i < k; ++i) hh[kMaxRestart + 1 + i] = y[i];
+    HIPCHK(c, hipMemcpyAsync(dy, hh + kMaxRestart + 1, k * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_multi_axpy(n, k, Zb, ld, dy, 1.0, u, nullptr, nb, s);  // x += Z y
+    HIPCHK(c, hipStreamSynchronize(s));  // the pinned y must not change before the copy ran
+    if (done) return SEM_OK;
+    if (it >= maxit) {
+      c->err = "maximum number of iterations reached";
+      return SEM_ENOTCONV;
+    }
+  }
+}
+
 sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_t maxit, int32_t *iters,
                      double *relres, double *history, void *stream) {
   TRY(need_device(c));
@@ -892,7 +1099,13 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
     if (relres) *relres = rn / bnorm;
     return SEM_OK;
   }
-  vcycle_top(c, r, z, s);
+  if (c->opt.krylov == SEM_GMRES) {
+    const sem_status st = gmres_solve(c, b, u, r, c->pinned[S_RR], bnorm, rtol, maxit, iters, relres, history, s);
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipGetLastError());
+    return st;
+  }
+  TRY(vcycle_replay(c, r, z, s, false));
   launch_dots<double>(n, 1, r, z, nullptr, nullptr, nullptr, nullptr, c->partials, kReduceBlocks, s);
   launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_RZ, FIN_INIT_RZ, s);
   HIPCHK(c, hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -925,7 +1138,7 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
       break;
     }
     if (it == maxit) break;
-    vcycle_top(c, r, z, s, mixed);
+    TRY(vcycle_replay(c, r, z, s, mixed));
     if (flexible) {
       launch_dots<double>(n, 2, z, r, z, r2, nullptr, nullptr, c->partials, kReduceBlocks, s);
       launch_finalize(kReduceBlocks, 2, c->partials, c->scal, S_ZR, FIN_BETA_FCG, s);
@@ -1004,7 +1217,7 @@ sem_status sem_host_array(const sem_ctx *c, const char *what, int32_t j, double 
   const std::string w(what);
   const bool sem = c->kind == LVL_SEM;
   if (w == "ax_tuning") {
-    // per level: variant64, 3 timings (us), variant32, 3 timings (us)
+    // per level: variant64, kAxVariants timings (us), variant32, kAxVariants timings (us)
     for (auto &L : c->levels) {
       tmp.push_back(L.ax_variant64);
       for (int v = 0; v < kAxVariants; ++v) tmp.push_back(L.ax_time64_us[v]);

@@ -30,16 +30,16 @@ struct Box {
   int N, nex, ney, nez, nx, ny, nz;
 };
 
-// Element copies of lattice coordinate I (1 <= I <= nex*N-1) along one axis.
-__device__ __forceinline__ int copies_1d(int I, int N, int *el, int *loc) {
-  const int q = I / N, r = I - q * N;
-  if (r == 0) {
-    el[0] = q - 1; loc[0] = N;
-    el[1] = q;     loc[1] = 0;
-    return 2;
-  }
-  el[0] = q; loc[0] = r;
-  return 1;
+// Element coordinates of element e (x fastest). 32-bit unsigned arithmetic: element and
+// unknown counts are below 2^31 (checked at setup), and a 64-bit division would expand
+// into a long instruction sequence in kernels that are bound by instruction issue.
+struct Exyz {
+  int x, y, z;
+};
+__device__ __forceinline__ Exyz elem_xyz(const Box &b, int64_t e) {
+  const unsigned eu = (unsigned)e, nx = (unsigned)b.nex, ny = (unsigned)b.ney;
+  const unsigned q = eu / nx;
+  return Exyz{(int)(eu - q * nx), (int)(q % ny), (int)(q / ny)};
 }
 
 // Lattice coordinates (1-based) of unknown g; 32-bit arithmetic (n < 2^31 is checked at setup).
@@ -51,6 +51,28 @@ __device__ __forceinline__ Ijk ijk_of(const Box &b, int64_t g) {
   const unsigned q = gg / nx;
   return Ijk{(int)(gg - q * nx) + 1, (int)(q % ny) + 1, (int)(q / ny) + 1};
 }
+// c += step unknowns in lattice order (step >= 0)
+__device__ __forceinline__ void ijk_advance(const Box &b, Ijk &c, int step) {
+  c.I += step;
+  while (c.I > b.nx) {
+    c.I -= b.nx;
+    if (++c.J > b.ny) {
+      c.J = 1;
+      ++c.K;
+    }
+  }
+}
+
+// First unknown of a thread in the vector kernels of 256-thread blocks that give
+// each thread VEC unknowns: a block covers 256*VEC consecutive unknowns, each wave
+// 64*VEC of them, and lane l takes l, l+64, l+128, ... So every load instruction of
+// a wave reads 64 consecutive unknowns (coalesced plain vectors; the element copies
+// that the summation gathers for consecutive unknowns share cache lines).
+template <int VEC>
+__device__ __forceinline__ int64_t strided_first(unsigned blk) {
+  return (int64_t)blk * (256 * VEC) + (threadIdx.x >> 6) * (64 * VEC) + (threadIdx.x & 63);
+}
+
 __device__ __forceinline__ void ijk_next(const Box &b, Ijk &c) {
   if (++c.I > b.nx) {
     c.I = 1;
@@ -61,23 +83,34 @@ __device__ __forceinline__ void ijk_next(const Box &b, Ijk &c) {
   }
 }
 
-// Sum of the element-local copies of the unknown at lattice point c (direct stiffness summation).
+// Sum of the element-local copies of the unknown at lattice point c (direct stiffness
+// summation). Along each axis a coordinate on an element face has two copies (element
+// q-1 at local N, element q at local 0), otherwise one. All eight candidate loads are
+// issued at once under their validity predicates and summed in the fixed order
+// z-copy, y-copy, x-copy (missing copies add +0, which leaves the sum unchanged).
 template <typename T>
 __device__ __forceinline__ T dss_ijk(const T *__restrict__ wL, const Box &b, const Ijk &c) {
-  const int I = c.I, J = c.J, K = c.K;
-  int exs[2], is[2], eys[2], js[2], ezs[2], ks[2];
-  const int cx = copies_1d(I, b.N, exs, is);
-  const int cy = copies_1d(J, b.N, eys, js);
-  const int cz = copies_1d(K, b.N, ezs, ks);
-  const int n1 = b.N + 1;
+  const int N = b.N, n1 = N + 1;
   const int64_t n3 = (int64_t)n1 * n1 * n1;
-  T s = 0;
-  for (int c = 0; c < cz; ++c)
-    for (int bq = 0; bq < cy; ++bq)
-      for (int a = 0; a < cx; ++a) {
-        const int64_t e = exs[a] + (int64_t)b.nex * (eys[bq] + (int64_t)b.ney * ezs[c]);
-        s += wL[e * n3 + (ks[c] * n1 + js[bq]) * n1 + is[a]];
-      }
+  const int qx = c.I / N, qy = c.J / N, qz = c.K / N;
+  const int rx = c.I - qx * N, ry = c.J - qy * N, rz = c.K - qz * N;
+  const bool fx = rx == 0, fy = ry == 0, fz = rz == 0;
+  const int ex = fx ? qx - 1 : qx, ey = fy ? qy - 1 : qy, ez = fz ? qz - 1 : qz;
+  const int ix = fx ? N : rx, iy = fy ? N : ry, iz = fz ? N : rz;
+  const int64_t base = (ex + (int64_t)b.nex * (ey + (int64_t)b.ney * ez)) * n3 + (iz * n1 + iy) * n1 + ix;
+  const int64_t dx = n3 - N;
+  const int64_t dy = (int64_t)b.nex * n3 - (int64_t)N * n1;
+  const int64_t dz = (int64_t)b.nex * b.ney * n3 - (int64_t)N * n1 * n1;
+  T w[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int a = q & 1, bq = (q >> 1) & 1, cq = q >> 2;
+    const bool valid = (a == 0 || fx) && (bq == 0 || fy) && (cq == 0 || fz);
+    w[q] = valid ? wL[base + a * dx + bq * dy + cq * dz] : T(0);
+  }
+  T s = w[0];
+#pragma unroll
+  for (int q = 1; q < 8; ++q) s += w[q];
   return s;
 }
 
@@ -95,29 +128,6 @@ __device__ __forceinline__ double inv_mult_ijk(const Box &b, const Ijk &c) {
   return 1.0 / m;
 }
 __device__ __forceinline__ double inv_mult(const Box &b, int64_t g) { return inv_mult_ijk(b, ijk_of(b, g)); }
-
-// VEC consecutive elements of a vector as one 16-byte access.
-template <typename T, int VEC>
-struct Pack {
-  T v[VEC];
-};
-template <typename T, int VEC>
-__device__ __forceinline__ Pack<T, VEC> ld(const T *__restrict__ p) {
-  typedef T vt __attribute__((ext_vector_type(VEC)));
-  const vt x = *reinterpret_cast<const vt *>(p);
-  Pack<T, VEC> r;
-#pragma unroll
-  for (int q = 0; q < VEC; ++q) r.v[q] = x[q];
-  return r;
-}
-template <typename T, int VEC>
-__device__ __forceinline__ void st(T *__restrict__ p, const Pack<T, VEC> &r) {
-  typedef T vt __attribute__((ext_vector_type(VEC)));
-  vt x;
-#pragma unroll
-  for (int q = 0; q < VEC; ++q) x[q] = r.v[q];
-  *reinterpret_cast<vt *>(p) = x;
-}
 
 __device__ __forceinline__ int64_t lattice_index(const Box &b, int I, int J, int K) {
   if (I < 1 || I > b.nx || J < 1 || J > b.ny || K < 1 || K > b.nz) return -1;
@@ -152,6 +162,8 @@ struct AxShape {
 
 // PF = 1: the factors of plane k+1 are loaded while plane k computes (more registers);
 // PF = 0: each plane loads its own factors (fewer registers, latency hidden by occupancy).
+// The plane loop stays rolled (the FP64 kernel would not fit its registers
+// unrolled); register arrays are then indexed through selects on k.
 template <int N, typename T, typename GT, int PF = 1>
 __device__ __forceinline__ void ax_body(unsigned blk, const Box &b, int64_t E, const T *__restrict__ u,
                                         const GT *__restrict__ G, const T *__restrict__ Dm,
@@ -175,9 +187,10 @@ __device__ __forceinline__ void ax_body(unsigned blk, const Box &b, int64_t E, c
   [[maybe_unused]] T DTi[n1], DTj[n1];
   int ex = 0, ey = 0, ez = 0;
   if (active) {
-    ex = (int)(e % b.nex);
-    ey = (int)((e / b.nex) % b.ney);
-    ez = (int)(e / ((int64_t)b.nex * b.ney));
+    const Exyz ec = elem_xyz(b, e);
+    ex = ec.x;
+    ey = ec.y;
+    ez = ec.z;
   }
   const int I = ex * N + i, J = ey * N + j;
   const bool inIJ = active && I >= 1 && I <= b.nx && J >= 1 && J <= b.ny;
@@ -185,8 +198,12 @@ __device__ __forceinline__ void ax_body(unsigned blk, const Box &b, int64_t E, c
   const int64_t plane = (int64_t)b.nx * b.ny;
 #pragma unroll
   for (int k = 0; k < n1; ++k) {
+    // unconditional load from a valid index, then select: no branch per load, so the
+    // whole column is in flight at once
     const int K = ez * N + k;
-    ureg[k] = (inIJ && K >= 1 && K <= b.nz) ? u[gIJ + plane * (K - 1)] : T(0);
+    const bool ok = inIJ && K >= 1 && K <= b.nz;
+    const T v = u[ok ? gIJ + plane * (K - 1) : 0];
+    ureg[k] = ok ? v : T(0);
     wreg[k] = T(0);
   }
   __syncthreads();
@@ -268,6 +285,246 @@ __device__ __forceinline__ void ax_body(unsigned blk, const Box &b, int64_t E, c
   }
 }
 
+
+// Same operator with the element's whole u tile resident in LDS: plane k of the tile
+// feeds the r and s derivatives and, once consumed, is overwritten by that plane's
+// r/s transpose contributions; the t-direction transpose accumulates in registers
+// indexed at compile time. No select-indexed register arrays, two barriers per plane.
+template <int N, typename T, typename GT, int PF = 1>
+__device__ __forceinline__ void ax_body_tile(unsigned blk, const Box &b, int64_t E, const T *__restrict__ u,
+                                             const GT *__restrict__ G, const T *__restrict__ Dm,
+                                             T *__restrict__ wL) {
+  using S = AxShape<N>;
+  constexpr int n1 = S::n1, n3 = n1 * n1 * n1;
+  __shared__ T sD[n1 * n1];
+  __shared__ T su[S::epb][n1][n1][n1];
+  __shared__ T sr[S::epb][n1][n1];
+  __shared__ T ss[S::epb][n1][n1];
+  const int t = threadIdx.x;
+  const int le = t / S::tpe;
+  const int ij = t - le * S::tpe;
+  const int i = ij % n1, j = ij / n1;
+  const int64_t e = (int64_t)blk * S::epb + le;
+  const bool active = (le < S::epb) && (e < E);
+  const int lec = active ? le : 0;
+  for (int q = t; q < n1 * n1; q += S::block) sD[q] = Dm[q];
+
+  T ureg[n1], tt[n1];
+  int ex = 0, ey = 0, ez = 0;
+  if (active) {
+    const Exyz ec = elem_xyz(b, e);
+    ex = ec.x;
+    ey = ec.y;
+    ez = ec.z;
+  }
+  const int I = ex * N + i, J = ey * N + j;
+  const bool inIJ = active && I >= 1 && I <= b.nx && J >= 1 && J <= b.ny;
+  const int64_t gIJ = (int64_t)(I - 1) + (int64_t)b.nx * (J - 1);
+  const int64_t plane = (int64_t)b.nx * b.ny;
+#pragma unroll
+  for (int k = 0; k < n1; ++k) {
+    // unconditional load from a valid index, then select: no branch per load, so the
+    // whole column is in flight at once
+    const int K = ez * N + k;
+    const bool ok = inIJ && K >= 1 && K <= b.nz;
+    const T v = u[ok ? gIJ + plane * (K - 1) : 0];
+    ureg[k] = ok ? v : T(0);
+    tt[k] = T(0);
+  }
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < n1; ++k) su[lec][k][j][i] = ureg[k];
+  }
+  __syncthreads();
+  T Di[n1];
+  [[maybe_unused]] T Dj[n1], DTi[n1], DTj[n1];
+#pragma unroll
+  for (int l = 0; l < n1; ++l) {
+    Di[l] = sD[i * n1 + l];
+    if constexpr (sizeof(T) == 4) {
+      Dj[l] = sD[j * n1 + l];
+      DTi[l] = sD[l * n1 + i];
+      DTj[l] = sD[l * n1 + j];
+    }
+  }
+  const GT *Ge = G + (active ? e : 0) * 6 * n3 + j * n1 + i;
+  T g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0;
+  if (PF && active) {
+    g0 = load_factor<GT, T>(Ge + 0 * n3);
+    g1 = load_factor<GT, T>(Ge + 1 * n3);
+    g2 = load_factor<GT, T>(Ge + 2 * n3);
+    g3 = load_factor<GT, T>(Ge + 3 * n3);
+    g4 = load_factor<GT, T>(Ge + 4 * n3);
+    g5 = load_factor<GT, T>(Ge + 5 * n3);
+  }
+#pragma unroll 1
+  for (int k = 0; k < n1; ++k) {
+    T h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0, h5 = 0;
+    const int qn = (PF ? k + 1 : k) * n1 * n1;
+    if (active && (PF ? k + 1 < n1 : true)) {
+      h0 = load_factor<GT, T>(Ge + 0 * n3 + qn);
+      h1 = load_factor<GT, T>(Ge + 1 * n3 + qn);
+      h2 = load_factor<GT, T>(Ge + 2 * n3 + qn);
+      h3 = load_factor<GT, T>(Ge + 3 * n3 + qn);
+      h4 = load_factor<GT, T>(Ge + 4 * n3 + qn);
+      h5 = load_factor<GT, T>(Ge + 5 * n3 + qn);
+    }
+    if (!PF) {
+      g0 = h0; g1 = h1; g2 = h2; g3 = h3; g4 = h4; g5 = h5;
+    }
+    T ur = 0, us = 0, ut = 0;
+#pragma unroll
+    for (int l = 0; l < n1; ++l) {
+      ur += Di[l] * su[lec][k][j][l];
+      if constexpr (sizeof(T) == 4) us += Dj[l] * su[lec][k][l][i];
+      else us += sD[j * n1 + l] * su[lec][k][l][i];
+      ut += Dm[k * n1 + l] * ureg[l];  // wave-uniform: scalar loads
+    }
+    const T wr = g0 * ur + g1 * us + g2 * ut;
+    const T ws = g1 * ur + g3 * us + g4 * ut;
+    const T wt = g2 * ur + g4 * us + g5 * ut;
+    if (active) {
+      sr[lec][j][i] = wr;
+      ss[lec][j][i] = ws;
+    }
+    __syncthreads();
+    T acc = 0;
+#pragma unroll
+    for (int l = 0; l < n1; ++l) {
+      if constexpr (sizeof(T) == 4) acc += DTi[l] * sr[lec][j][l] + DTj[l] * ss[lec][l][i];
+      else acc += sD[l * n1 + i] * sr[lec][j][l] + sD[l * n1 + j] * ss[lec][l][i];
+    }
+    if (active) su[lec][k][j][i] = acc;  // every read of plane k happened before the barrier
+#pragma unroll
+    for (int l = 0; l < n1; ++l) tt[l] += Dm[k * n1 + l] * wt;
+    g0 = h0; g1 = h1; g2 = h2; g3 = h3; g4 = h4; g5 = h5;
+    __syncthreads();
+  }
+  if (active) {
+    T *we = wL + e * n3;
+#pragma unroll
+    for (int k = 0; k < n1; ++k) we[(k * n1 + j) * n1 + i] = su[lec][k][j][i] + tt[k];
+  }
+}
+
+// Single-precision operator with BF16 factors whose element factor blocks are copied
+// to LDS by the global-to-LDS DMA loads at the start (the factors of consecutive
+// elements are contiguous): the plane loop then issues no global loads, so a wave
+// pays one memory latency per element instead of one per plane. The u tile is
+// LDS-resident as in ax_body_tile.
+template <int N>
+__device__ __forceinline__ void ax_body_dma(unsigned blk, const Box &b, int64_t E, const float *__restrict__ u,
+                                            const uint16_t *__restrict__ G, const float *__restrict__ Dm,
+                                            float *__restrict__ wL) {
+  using S = AxShape<N>;
+  using T = float;
+  constexpr int n1 = S::n1, n3 = n1 * n1 * n1;
+  constexpr int kElemBytes = 6 * n3 * 2;
+  constexpr int kChunk = (kElemBytes % 16 == 0) ? 16 : 4;  // bytes per lane and DMA load
+  constexpr int kWaves = S::block / 64;
+  __shared__ __align__(16) uint16_t sG[S::epb * 6 * n3];
+  __shared__ T sD[n1 * n1];
+  __shared__ T su[S::epb][n1][n1][n1];
+  __shared__ T sr[S::epb][n1][n1];
+  __shared__ T ss[S::epb][n1][n1];
+  const int t = threadIdx.x;
+  const int le = t / S::tpe;
+  const int ij = t - le * S::tpe;
+  const int i = ij % n1, j = ij / n1;
+  const int64_t e0 = (int64_t)blk * S::epb;
+  const int64_t e = e0 + le;
+  const bool active = (le < S::epb) && (e < E);
+  const int lec = active ? le : 0;
+  for (int q = t; q < n1 * n1; q += S::block) sD[q] = Dm[q];
+  T ureg[n1], tt[n1];
+  int ex = 0, ey = 0, ez = 0;
+  if (active) {
+    const Exyz ec = elem_xyz(b, e);
+    ex = ec.x;
+    ey = ec.y;
+    ez = ec.z;
+  }
+  const int I = ex * N + i, J = ey * N + j;
+  const bool inIJ = active && I >= 1 && I <= b.nx && J >= 1 && J <= b.ny;
+  const int64_t gIJ = (int64_t)(I - 1) + (int64_t)b.nx * (J - 1);
+  const int64_t plane = (int64_t)b.nx * b.ny;
+#pragma unroll
+  for (int k = 0; k < n1; ++k) {
+    // unconditional load from a valid index, then select: no branch per load, so the
+    // whole column is in flight at once
+    const int K = ez * N + k;
+    const bool ok = inIJ && K >= 1 && K <= b.nz;
+    const T v = u[ok ? gIJ + plane * (K - 1) : 0];
+    ureg[k] = ok ? v : T(0);
+    tt[k] = T(0);
+  }
+  {  // factor blocks of this block's elements -> sG, issued after the u gathers so that
+     // both are in flight together (every address below lies inside those blocks)
+    const int64_t nel = (E - e0) < S::epb ? (E - e0) : S::epb;
+    const int nchunks = (int)(nel * kElemBytes / kChunk);
+    const char *src = reinterpret_cast<const char *>(G + e0 * 6 * n3);
+    const int wave = t >> 6, lane = t & 63;
+    for (int c0 = wave * 64; c0 < nchunks; c0 += kWaves * 64) {
+      if (c0 + lane < nchunks) {
+        const void *gp = src + (int64_t)(c0 + lane) * kChunk;
+        auto *lp = (__attribute__((address_space(3))) void *)(reinterpret_cast<char *>(sG) + c0 * kChunk);
+        if constexpr (kChunk == 16) __builtin_amdgcn_global_load_lds(gp, lp, 16, 0, 0);
+        else __builtin_amdgcn_global_load_lds(gp, lp, 4, 0, 0);
+      }
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < n1; ++k) su[lec][k][j][i] = ureg[k];
+  }
+  // the DMA loads are not tracked by the compiler: wait for all of them explicitly,
+  // then the barrier publishes every wave's share of sG
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  T Di[n1], Dj[n1], DTi[n1], DTj[n1];
+#pragma unroll
+  for (int l = 0; l < n1; ++l) {
+    Di[l] = sD[i * n1 + l];
+    Dj[l] = sD[j * n1 + l];
+    DTi[l] = sD[l * n1 + i];
+    DTj[l] = sD[l * n1 + j];
+  }
+  const uint16_t *Ge = sG + lec * 6 * n3 + j * n1 + i;
+#pragma unroll 1
+  for (int k = 0; k < n1; ++k) {
+    const int q = k * n1 * n1;
+    const T g0 = bf16_to_float(Ge[0 * n3 + q]), g1 = bf16_to_float(Ge[1 * n3 + q]);
+    const T g2 = bf16_to_float(Ge[2 * n3 + q]), g3 = bf16_to_float(Ge[3 * n3 + q]);
+    const T g4 = bf16_to_float(Ge[4 * n3 + q]), g5 = bf16_to_float(Ge[5 * n3 + q]);
+    T ur = 0, us = 0, ut = 0;
+#pragma unroll
+    for (int l = 0; l < n1; ++l) {
+      ur += Di[l] * su[lec][k][j][l];
+      us += Dj[l] * su[lec][k][l][i];
+      ut += Dm[k * n1 + l] * ureg[l];  // wave-uniform: scalar loads
+    }
+    const T wr = g0 * ur + g1 * us + g2 * ut;
+    const T ws = g1 * ur + g3 * us + g4 * ut;
+    const T wt = g2 * ur + g4 * us + g5 * ut;
+    if (active) {
+      sr[lec][j][i] = wr;
+      ss[lec][j][i] = ws;
+    }
+    __syncthreads();
+    T acc = 0;
+#pragma unroll
+    for (int l = 0; l < n1; ++l) acc += DTi[l] * sr[lec][j][l] + DTj[l] * ss[lec][l][i];
+    if (active) su[lec][k][j][i] = acc;
+#pragma unroll
+    for (int l = 0; l < n1; ++l) tt[l] += Dm[k * n1 + l] * wt;
+    __syncthreads();
+  }
+  if (active) {
+    T *we = wL + e * n3;
+#pragma unroll
+    for (int k = 0; k < n1; ++k) we[(k * n1 + j) * n1 + i] = su[lec][k][j][i] + tt[k];
+  }
+}
 
 }  // namespace dev
 }  // namespace semcheb

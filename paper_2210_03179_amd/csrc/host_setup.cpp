@@ -320,21 +320,28 @@ bool spd_inverse(std::vector<double> &A, int64_t n) {
   return true;
 }
 
+// Block-tridiagonal elimination from both ends ("burn at both ends"): blocks above the
+// middle block m are eliminated top-down, blocks below it bottom-up, and the two
+// sweeps meet in m. The forward and backward substitutions then take about nb/2
+// dependent steps, each covering one block of either sweep.
 bool block_tridiag_factor(const Csr &A, const std::vector<int64_t> &start, BlockTri &out,
                           std::string &err) {
   const int nb = (int)start.size() - 1;
+  const int m = nb / 2;
   out.start = start;
+  out.mid = m;
   out.Minv.assign(nb, {});
   out.Lmat.assign(nb, {});
-  out.Up.assign(nb, {});
+  out.Wmat.assign(nb, {});
   auto block_of = [&](int64_t idx) {
     return (int)(std::upper_bound(start.begin(), start.end(), idx) - start.begin()) - 1;
   };
-  // sub-blocks of A as CSR restricted to (rows of bi, cols of bj), cols local to bj
+  auto rows = [&](int b) { return start[b + 1] - start[b]; };
+  // sub-block A_{bi,bj} as CSR, column indices local to bj
   auto extract = [&](int bi, int bj) {
     Csr S;
-    S.nrows = start[bi + 1] - start[bi];
-    S.ncols = start[bj + 1] - start[bj];
+    S.nrows = rows(bi);
+    S.ncols = rows(bj);
     S.rowptr.assign(S.nrows + 1, 0);
     for (int64_t r = start[bi]; r < start[bi + 1]; ++r) {
       for (int64_t p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p) {
@@ -348,72 +355,104 @@ bool block_tridiag_factor(const Csr &A, const std::vector<int64_t> &start, Block
     }
     return S;
   };
-  // couplings beyond neighbouring blocks are not allowed
   for (int64_t r = 0; r < A.nrows; ++r)
     for (int64_t p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p)
       if (std::abs(block_of(r) - block_of(A.col[p])) > 1) {
         err = "coarse matrix is not block tridiagonal in the chosen blocking";
         return false;
       }
-  for (int b = 0; b < nb; ++b) {
-    const int64_t Pb = start[b + 1] - start[b];
-    std::vector<double> S((size_t)Pb * Pb, 0.0);
-    Csr Abb = extract(b, b);
-    for (int64_t r = 0; r < Pb; ++r)
-      for (int64_t p = Abb.rowptr[r]; p < Abb.rowptr[r + 1]; ++p) S[r * Pb + Abb.col[p]] += Abb.val[p];
-    if (b > 0) {
-      const int64_t Pp = start[b] - start[b - 1];
-      Csr Alo = extract(b, b - 1);   // A_{b,b-1}
-      Csr Aup = extract(b - 1, b);   // A_{b-1,b}
-      std::vector<double> &Lm = out.Lmat[b];
-      Lm.assign((size_t)Pb * Pp, 0.0);
-      const std::vector<double> &Mp = out.Minv[b - 1];
+  // Lout = A_{b,p} Minv[p] (dense) and S -= Lout A_{p,b}
+  auto eliminate = [&](int b, int p, std::vector<double> &S, std::vector<double> &Lout) {
+    const int64_t Pb = rows(b), Pp = rows(p);
+    const Csr Abp = extract(b, p), Apb = extract(p, b);
+    const std::vector<double> &Mp = out.Minv[p];
+    Lout.assign((size_t)Pb * Pp, 0.0);
 #pragma omp parallel for schedule(static)
-      for (int64_t r = 0; r < Pb; ++r)
-        for (int64_t p = Alo.rowptr[r]; p < Alo.rowptr[r + 1]; ++p) {
-          const double v = Alo.val[p];
-          const double *Mrow = &Mp[(size_t)Alo.col[p] * Pp];
-          double *Lrow = &Lm[(size_t)r * Pp];
-          for (int64_t c = 0; c < Pp; ++c) Lrow[c] += v * Mrow[c];
-        }
-      // S -= L_b A_{b-1,b}
-#pragma omp parallel for schedule(static)
-      for (int64_t r = 0; r < Pb; ++r) {
-        const double *Lrow = &Lm[(size_t)r * Pp];
-        double *Srow = &S[(size_t)r * Pb];
-        for (int64_t q = 0; q < Pp; ++q) {
-          const double l = Lrow[q];
-          if (l == 0.0) continue;
-          for (int64_t p = Aup.rowptr[q]; p < Aup.rowptr[q + 1]; ++p) Srow[Aup.col[p]] -= l * Aup.val[p];
-        }
+    for (int64_t r = 0; r < Pb; ++r) {
+      double *Lrow = &Lout[(size_t)r * Pp];
+      for (int64_t q = Abp.rowptr[r]; q < Abp.rowptr[r + 1]; ++q) {
+        const double v = Abp.val[q];
+        const double *Mrow = &Mp[(size_t)Abp.col[q] * Pp];
+        for (int64_t c = 0; c < Pp; ++c) Lrow[c] += v * Mrow[c];
+      }
+      double *Srow = &S[(size_t)r * Pb];
+      for (int64_t q = 0; q < Pp; ++q) {
+        const double l = Lrow[q];
+        if (l == 0.0) continue;
+        for (int64_t t = Apb.rowptr[q]; t < Apb.rowptr[q + 1]; ++t) Srow[Apb.col[t]] -= l * Apb.val[t];
       }
     }
-    if (!spd_inverse(S, Pb)) {
+  };
+  auto diag_block = [&](int b) {
+    const int64_t Pb = rows(b);
+    std::vector<double> S((size_t)Pb * Pb, 0.0);
+    const Csr Abb = extract(b, b);
+    for (int64_t r = 0; r < Pb; ++r)
+      for (int64_t p = Abb.rowptr[r]; p < Abb.rowptr[r + 1]; ++p) S[r * Pb + Abb.col[p]] += Abb.val[p];
+    return S;
+  };
+  auto invert = [&](int b, std::vector<double> &S) {
+    if (!spd_inverse(S, rows(b))) {
       err = "coarse Schur complement is not positive definite (block " + std::to_string(b) + ")";
       return false;
     }
     out.Minv[b] = std::move(S);
-    if (b + 1 < nb) out.Up[b] = extract(b, b + 1);
-  }
-  // W_b = S_b^{-1} A_{b,b+1} (dense), so that x_b = S_b^{-1} y_b - W_b x_{b+1}
-  out.Wmat.assign(nb, {});
-  for (int b = 0; b + 1 < nb; ++b) {
-    const int64_t Pb = start[b + 1] - start[b], Pn = start[b + 2] - start[b + 1];
-    const Csr &U = out.Up[b];
+    return true;
+  };
+  // W[b] = Minv[b] A_{b,q} (dense), q the neighbour on the middle's side
+  auto make_w = [&](int b, int q) {
+    const int64_t Pb = rows(b), Pq = rows(q);
+    const Csr U = extract(b, q);
     const std::vector<double> &M = out.Minv[b];
     std::vector<double> &W = out.Wmat[b];
-    W.assign((size_t)Pb * Pn, 0.0);
+    W.assign((size_t)Pb * Pq, 0.0);
 #pragma omp parallel for schedule(static)
     for (int64_t r = 0; r < Pb; ++r) {
       const double *Mrow = &M[(size_t)r * Pb];
-      double *Wrow = &W[(size_t)r * Pn];
-      for (int64_t q = 0; q < Pb; ++q) {
-        const double m = Mrow[q];
-        if (m == 0.0) continue;
-        for (int64_t p = U.rowptr[q]; p < U.rowptr[q + 1]; ++p) Wrow[U.col[p]] += m * U.val[p];
+      double *Wrow = &W[(size_t)r * Pq];
+      for (int64_t t = 0; t < Pb; ++t) {
+        const double mv = Mrow[t];
+        if (mv == 0.0) continue;
+        for (int64_t p = U.rowptr[t]; p < U.rowptr[t + 1]; ++p) Wrow[U.col[p]] += mv * U.val[p];
       }
     }
+  };
+  for (int b = 0; b < m; ++b) {  // top sweep
+    std::vector<double> S = diag_block(b);
+    if (b > 0) eliminate(b, b - 1, S, out.Lmat[b]);
+    if (!invert(b, S)) return false;
+    make_w(b, b + 1);
   }
+  for (int b = nb - 1; b > m; --b) {  // bottom sweep
+    std::vector<double> S = diag_block(b);
+    if (b < nb - 1) eliminate(b, b + 1, S, out.Lmat[b]);
+    if (!invert(b, S)) return false;
+    make_w(b, b - 1);
+  }
+  // middle block: both neighbours eliminated into it
+  std::vector<double> S = diag_block(m), Ltop, Lbot;
+  if (m > 0) eliminate(m, m - 1, S, Ltop);
+  if (m < nb - 1) eliminate(m, m + 1, S, Lbot);
+  if (!invert(m, S)) return false;
+  // x_m = Minv_m b_m - (Minv_m Ltop) y_{m-1} - (Minv_m Lbot) y_{m+1}
+  const int64_t Pm = rows(m);
+  auto times_minv = [&](const std::vector<double> &Lx, int64_t Pn, std::vector<double> &X) {
+    const std::vector<double> &M = out.Minv[m];
+    X.assign((size_t)Pm * Pn, 0.0);
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < Pm; ++r) {
+      double *Xrow = &X[(size_t)r * Pn];
+      for (int64_t t = 0; t < Pm; ++t) {
+        const double mv = M[(size_t)r * Pm + t];
+        const double *Lrow = &Lx[(size_t)t * Pn];
+        for (int64_t c = 0; c < Pn; ++c) Xrow[c] += mv * Lrow[c];
+      }
+    }
+  };
+  out.Xtop.clear();
+  out.Xbot.clear();
+  if (m > 0) times_minv(Ltop, rows(m - 1), out.Xtop);
+  if (m < nb - 1) times_minv(Lbot, rows(m + 1), out.Xbot);
   return true;
 }
 

@@ -49,10 +49,11 @@ Csr assemble_q1(const BoxLevelHost &lev);
 // contiguous blocks with couplings only between neighbouring blocks.
 struct BlockTri {
   std::vector<int64_t> start;               // block b covers [start[b], start[b+1])
-  std::vector<std::vector<double>> Minv;    // S_b^{-1}, dense row-major
-  std::vector<std::vector<double>> Lmat;    // A_{b,b-1} S_{b-1}^{-1}, dense (b >= 1)
-  std::vector<std::vector<double>> Wmat;    // S_b^{-1} A_{b,b+1}, dense (b < nb-1)
-  std::vector<Csr> Up;                      // A_{b,b+1} (rows of b, cols local to b+1)
+  int mid = 0;                              // blocks < mid eliminated top-down, > mid bottom-up
+  std::vector<std::vector<double>> Minv;    // inverse Schur complement of block b, dense row-major
+  std::vector<std::vector<double>> Lmat;    // A_{b,p} Minv[p], p the neighbour away from mid (b != mid)
+  std::vector<std::vector<double>> Wmat;    // Minv[b] A_{b,q}, q the neighbour towards mid (b != mid)
+  std::vector<double> Xtop, Xbot;           // Minv[mid] A_{mid,mid-1} Minv[mid-1], same with mid+1
 };
 bool block_tridiag_factor(const Csr &A, const std::vector<int64_t> &start, BlockTri &out,
                           std::string &err);
@@ -111,18 +112,22 @@ struct Level {
   int64_t applies = 0;
   // operator kernel variant per precision, chosen at setup by timing (kAxVariants)
   int ax_variant64 = 0, ax_variant32 = 0;
-  float ax_time64_us[3] = {0, 0, 0}, ax_time32_us[3] = {0, 0, 0};
+  float ax_time64_us[6] = {}, ax_time32_us[6] = {};  // kAxVariants
 };
-constexpr int kAxVariants = 3;
+constexpr int kGmresScalars = 2 * 32 + 2;  // projections (<= 32), ||w||^2, y (<= 32)
+constexpr int kAxVariants = 6;    // variant 5 (factors staged by DMA) exists for BF16 factors only
+constexpr int kAxVariants64 = 5;
 
 struct CoarseSolver {
   bool dense = true;
   int64_t n = 0;
   // dense inverse (FD, or a single block)
   double *Minv = nullptr;
-  // block tridiagonal
+  // block tridiagonal, eliminated from both ends towards block `mid`
   std::vector<int64_t> start;
+  int mid = 0;
   std::vector<double *> Mb, Lb, Wb;
+  double *Xtop = nullptr, *Xbot = nullptr;
   double *b = nullptr, *y = nullptr, *x = nullptr, *t = nullptr;
   std::vector<double> host_dense;  // small problems: assembled matrix for inspection
 };
@@ -184,6 +189,21 @@ struct sem_ctx {
   int npartials = 0;           // partials written by the last fused apply
   double *pinned = nullptr;    // host-pinned scalar mirror
   double *zout = nullptr;      // set during a mixed one-sided cycle: widened output target
+  // GMRES(m) work: basis V (m+1 vectors) and preconditioned directions Z (m vectors), leading
+  // dimension gld; device scalars gH (projections, ||w||^2, y) and their pinned host mirror
+  double *gV = nullptr, *gZ = nullptr, *gH = nullptr, *gpinned = nullptr;
+  int64_t gld = 0;
+  // V-cycles of the Krylov solve replayed as captured HIP graphs, one per (r, z, r32) triple
+  struct CycleGraph {
+    const double *r;
+    double *z;
+    bool r32;
+    hipGraphExec_t exec;
+    std::vector<int64_t> applies;  // operator applications per level of one cycle
+  };
+  std::vector<CycleGraph> graphs;
+  bool use_graphs = true;
+  hipStream_t capture_stream = nullptr;
   std::string err;
   std::vector<void *> allocations;
   sem_batch *batch = nullptr;  // set for batched contexts (kind == 2)

@@ -46,9 +46,22 @@ template <typename T>
 void launch_csr(const DevCsr &A, const T *val, const T *x, const T *b, T *y, int mode, hipStream_t s);
 void launch_gemv(int64_t nrows, int64_t ncols, const double *M, const double *x, const double *b, double *y,
                  int sub, hipStream_t s);
-// y = M1 x1 - M2 x2 (dense row-major, nrows rows)
-void launch_gemv2(int64_t nrows, int64_t n1c, const double *M1, const double *x1, int64_t n2c, const double *M2,
-                  const double *x2, double *y, hipStream_t s);
+// Up to two independent products in one launch, one 256-thread block per output row:
+// y[r] = (b ? b[r] : 0) + sum_s sign_s * (M_s[r, :] . x_s), M_s dense row-major with ncols columns.
+struct GemvSeg {
+  const double *M;
+  const double *x;
+  int64_t ncols;
+  double sign;
+};
+struct GemvJob {
+  const double *b;
+  double *y;
+  int64_t nrows;
+  int32_t nseg;  // 1..3
+  GemvSeg seg[3];
+};
+void launch_gemv_jobs(int njobs, const GemvJob *jobs, hipStream_t s);
 template <typename T>
 void launch_dots(int64_t n, int nd, const T *x0, const T *y0, const T *x1, const T *y1, const T *x2,
                  const T *y2, double *partials, int nblocks, hipStream_t s);
@@ -61,6 +74,24 @@ void launch_convert(int64_t n, const double *in, float *out, hipStream_t s);
 void launch_convert(int64_t n, const float *in, double *out, hipStream_t s);
 void launch_axpby(int64_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s);
 void launch_mul(int64_t n, const double *a, const double *b, double *out, hipStream_t s);
+// GMRES(m) vector kernels, m <= kMaxRestart. V points at k vectors of length n with
+// leading dimension ldv (vector i at V + i*ldv).
+constexpr int kMaxRestart = 32;
+// partials[blk*k + q] = (sum over the block's range of V_q . w), q < k <= kMaxRestart
+void launch_multi_dot(int64_t n, int k, const double *V, int64_t ldv, const double *w, double *partials,
+                      int nblocks, hipStream_t s);
+// out[q] = sum_b partials[b*nd + q] in block order, one block per q (nd <= kMaxRestart + 1)
+void launch_finalize_many(int nblocks, int nd, const double *partials, double *out, hipStream_t s);
+// y += sign * (sum_{q<k} c_q V_q) with c in device memory (k <= kMaxRestart); when partials is
+// not null, partials[blk] = (sum over the block's range of y_new^2)
+void launch_multi_axpy(int64_t n, int k, const double *V, int64_t ldv, const double *c, double sign, double *y,
+                       double *partials, int nblocks, hipStream_t s);
+// y = x / sqrt(*nrm2)
+void launch_scale_inv_sqrt(int64_t n, const double *x, const double *nrm2, double *y, hipStream_t s);
+
+// out[0..n) = 0 with a kernel (no memset node when the caller captures a graph)
+template <typename T>
+void launch_zero(int64_t n, T *out, hipStream_t s);
 bool launch_adjoint(const Level &L, const double *lam, const double *u, double *dG, hipStream_t s);
 
 }  // namespace semcheb

@@ -19,12 +19,16 @@ namespace {
 using namespace dev;
 
 // Variants of the operator kernel chosen per level by the setup-time autotuner:
-// PF (factor prefetch) and OCC (waves per SIMD requested from the register allocator).
-template <int N, typename T, typename GT, int PF, int OCC>
+// PF (factor prefetch), OCC (waves per SIMD requested from the register allocator)
+// and TILE (0: u column in registers with one LDS plane, 1: whole u tile in LDS,
+// 2: u tile and the element's BF16 factors in LDS, single precision only).
+template <int N, typename T, typename GT, int PF, int OCC, int TILE = 0>
 __global__ void __launch_bounds__(AxShape<N>::block, OCC)
 ax_local_kernel(Box b, int64_t E, const T *__restrict__ u, const GT *__restrict__ G,
                 const T *__restrict__ Dm, T *__restrict__ wL) {
-  ax_body<N, T, GT, PF>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
+  if constexpr (TILE == 2) ax_body_dma<N>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
+  else if constexpr (TILE == 1) ax_body_tile<N, T, GT, PF>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
+  else ax_body<N, T, GT, PF>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
 }
 
 // ------------------------------------------------------------------ summation / vector kernels
@@ -47,32 +51,30 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
   return s;
 }
 
-// One thread per VEC consecutive unknowns (no grid-stride loop: every load of a
-// thread is independent of the others), one partial per block.
+// One thread per VEC unknowns spaced a wavefront apart (see strided_first), one
+// partial per block; no grid-stride loop, so every load of a thread is independent.
 template <typename T, int VEC>
 __device__ __forceinline__ void dss_dot_body(unsigned blk, const Box &b, int64_t n, const T *__restrict__ wL,
                                              T *__restrict__ out, const T *__restrict__ p,
                                              double *__restrict__ partial) {
   __shared__ double sm[4];
   double acc = 0.0;
-  const int64_t g0 = ((int64_t)blk * blockDim.x + threadIdx.x) * VEC;
+  const int64_t g0 = strided_first<VEC>(blk);
   if (g0 < n) {
-    const bool full = g0 + VEC <= n;
-    Pack<T, VEC> pv, ov;
-    if (full) pv = ld<T, VEC>(p + g0);
-    else
-      for (int q = 0; q < VEC; ++q) pv.v[q] = g0 + q < n ? p[g0 + q] : T(0);
+    T pv[VEC], ov[VEC];
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) pv[q] = (g0 + 64 * q < n) ? p[g0 + 64 * q] : T(0);
     Ijk cc = ijk_of(b, g0);
 #pragma unroll
     for (int q = 0; q < VEC; ++q) {
-      ov.v[q] = (g0 + q < n) ? dss_ijk(wL, b, cc) : T(0);
-      acc += (double)pv.v[q] * (double)ov.v[q];
-      ijk_next(b, cc);
+      ov[q] = (g0 + 64 * q < n) ? dss_ijk(wL, b, cc) : T(0);
+      if (q + 1 < VEC) ijk_advance(b, cc, 64);
     }
-    if (full) st<T, VEC>(out + g0, ov);
-    else
-      for (int q = 0; q < VEC; ++q)
-        if (g0 + q < n) out[g0 + q] = ov.v[q];
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      acc += (double)pv[q] * (double)ov[q];
+      if (g0 + 64 * q < n) out[g0 + 64 * q] = ov[q];
+    }
   }
   const double s = block_sum(acc, sm);
   if (threadIdx.x == 0) *partial = s;
@@ -90,63 +92,47 @@ dss_dot_kernel(Box b, int64_t n, const T *__restrict__ wL, T *__restrict__ out,
 //   if SUB_AD:  rr -= (mode 1 ? invdiag * Ad : Ad)
 //   dd = (D_INIT ? 0 : d) * a + bc * (mode 4 ? invdiag * rr : rr)
 //   x  = (X_INIT ? 0 : x) + c * dd
-// One thread updates VEC consecutive unknowns (16-byte accesses of the plain
-// vectors); the last thread handles a partial pack element by element.
+// One thread updates VEC unknowns spaced a wavefront apart (see strided_first).
 template <typename T, bool SEM, int VEC>
 __device__ __forceinline__ void cheb_body(unsigned blk, const Box &b, int64_t n, const T *__restrict__ wsrc,
                                           const T *__restrict__ bvec, const T *__restrict__ r_in,
                                           T *__restrict__ r_out, T *__restrict__ d, T *__restrict__ x,
                                           const T *__restrict__ invdiag, T a, T bc, T c, int flags, int mode) {
-  const int64_t g0 = ((int64_t)blk * blockDim.x + threadIdx.x) * VEC;
+  const int64_t g0 = strided_first<VEC>(blk);
   if (g0 >= n) return;
-  const bool full = g0 + VEC <= n;
-  const int cnt = full ? VEC : (int)(n - g0);
   const T *rsrc = (flags & CHEB_R_FROM_B) ? bvec : r_in;
-  Pack<T, VEC> s, rr, dd, xx, ad;
-  if (full) {
-    s = ld<T, VEC>(invdiag + g0);
-    rr = ld<T, VEC>(rsrc + g0);
-    if (!(flags & CHEB_D_INIT)) dd = ld<T, VEC>(d + g0);
-    if (!(flags & CHEB_X_INIT)) xx = ld<T, VEC>(x + g0);
-    if (!SEM && (flags & CHEB_SUB_AD)) ad = ld<T, VEC>(wsrc + g0);
-  } else {
-    for (int q = 0; q < cnt; ++q) {
-      s.v[q] = invdiag[g0 + q];
-      rr.v[q] = rsrc[g0 + q];
-      if (!(flags & CHEB_D_INIT)) dd.v[q] = d[g0 + q];
-      if (!(flags & CHEB_X_INIT)) xx.v[q] = x[g0 + q];
-      if (!SEM && (flags & CHEB_SUB_AD)) ad.v[q] = wsrc[g0 + q];
-    }
+  T sv[VEC], rr[VEC], dd[VEC], xx[VEC], ad[VEC];
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) {
+    const int64_t g = g0 + 64 * q;
+    const bool ok = g < n;
+    sv[q] = ok ? invdiag[g] : T(0);
+    rr[q] = ok ? rsrc[g] : T(0);
+    dd[q] = (ok && !(flags & CHEB_D_INIT)) ? d[g] : T(0);
+    xx[q] = (ok && !(flags & CHEB_X_INIT)) ? x[g] : T(0);
+    ad[q] = (!SEM && ok && (flags & CHEB_SUB_AD)) ? wsrc[g] : T(0);
   }
   if (SEM && (flags & CHEB_SUB_AD)) {
     Ijk cc = ijk_of(b, g0);
 #pragma unroll
     for (int q = 0; q < VEC; ++q) {
-      if (q < cnt) ad.v[q] = dss_ijk(wsrc, b, cc);
-      ijk_next(b, cc);
+      if (g0 + 64 * q < n) ad[q] = dss_ijk(wsrc, b, cc);
+      if (q + 1 < VEC) ijk_advance(b, cc, 64);
     }
   }
 #pragma unroll
   for (int q = 0; q < VEC; ++q) {
-    T r = rr.v[q];
-    if (flags & CHEB_S_ON_R) r = s.v[q] * r;
-    if (flags & CHEB_SUB_AD) r = (mode == 1) ? r - s.v[q] * ad.v[q] : r - ad.v[q];
-    rr.v[q] = r;
-    T dn = (flags & CHEB_D_INIT) ? T(0) : a * dd.v[q];
-    dn = dn + bc * (mode == 4 ? s.v[q] * r : r);
-    dd.v[q] = dn;
-    const T xo = (flags & CHEB_X_INIT) ? T(0) : xx.v[q];
-    xx.v[q] = xo + c * dn;
-  }
-  if (full) {
-    if (flags & CHEB_WRITE_R) st<T, VEC>(r_out + g0, rr);
-    st<T, VEC>(d + g0, dd);
-    st<T, VEC>(x + g0, xx);
-  } else {
-    for (int q = 0; q < cnt; ++q) {
-      if (flags & CHEB_WRITE_R) r_out[g0 + q] = rr.v[q];
-      d[g0 + q] = dd.v[q];
-      x[g0 + q] = xx.v[q];
+    T r = rr[q];
+    if (flags & CHEB_S_ON_R) r = sv[q] * r;
+    if (flags & CHEB_SUB_AD) r = (mode == 1) ? r - sv[q] * ad[q] : r - ad[q];
+    T dn = (flags & CHEB_D_INIT) ? T(0) : a * dd[q];
+    dn = dn + bc * (mode == 4 ? sv[q] * r : r);
+    const T xn = ((flags & CHEB_X_INIT) ? T(0) : xx[q]) + c * dn;
+    const int64_t g = g0 + 64 * q;
+    if (g < n) {
+      if (flags & CHEB_WRITE_R) r_out[g] = r;
+      d[g] = dn;
+      x[g] = xn;
     }
   }
 }
@@ -165,30 +151,21 @@ cheb_kernel(Box b, int64_t n, const T *__restrict__ wsrc, const T *__restrict__ 
 template <typename T, int VEC>
 __device__ __forceinline__ void resid_weight_body(unsigned blk, const Box &b, int64_t n, const T *__restrict__ wL,
                                                   const T *__restrict__ bvec, T *__restrict__ rw) {
-  const int64_t g0 = ((int64_t)blk * blockDim.x + threadIdx.x) * VEC;
+  const int64_t g0 = strided_first<VEC>(blk);
   if (g0 >= n) return;
-  const bool full = g0 + VEC <= n;
-  const int cnt = full ? VEC : (int)(n - g0);
-  Pack<T, VEC> r;
-  if (full) {
-    r = ld<T, VEC>(bvec + g0);
-  } else {
-    for (int q = 0; q < cnt; ++q) r.v[q] = bvec[g0 + q];
-  }
+  T r[VEC];
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) r[q] = (g0 + 64 * q < n) ? bvec[g0 + 64 * q] : T(0);
   Ijk cc = ijk_of(b, g0);
 #pragma unroll
   for (int q = 0; q < VEC; ++q) {
-    if (q < cnt) {
-      T v = r.v[q];
+    const int64_t g = g0 + 64 * q;
+    if (g < n) {
+      T v = r[q];
       if (wL) v -= dss_ijk(wL, b, cc);
-      r.v[q] = v * (T)inv_mult_ijk(b, cc);
+      rw[g] = v * (T)inv_mult_ijk(b, cc);
     }
-    ijk_next(b, cc);
-  }
-  if (full) {
-    st<T, VEC>(rw + g0, r);
-  } else {
-    for (int q = 0; q < cnt; ++q) rw[g0 + q] = r.v[q];
+    if (q + 1 < VEC) ijk_advance(b, cc, 64);
   }
 }
 
@@ -211,25 +188,31 @@ __global__ void resid_plain_kernel(int64_t n, const T *__restrict__ ad, const T 
 // ------------------------------------------------------------------ order transfers
 // Restriction P^T: for every coarse element, gather the weighted fine residual,
 // contract with J^T along i, j, k and write coarse element-local values.
-template <typename T>
+// NF, NC > 0 fix the fine and coarse orders at compile time and BS the block size
+// (index arithmetic and loop trip counts then resolve at compile time); 0 reads them at run time.
+template <typename T, int NF = 0, int NC = 0, int BS = 0>
 __device__ __forceinline__ void restrict_body(int64_t e, const Box &fb, const Box &cb, int64_t E,
                                               const T *__restrict__ rw, const T *__restrict__ Jm,
                                               T *__restrict__ rcL, T *smem) {
-  const int nf = fb.N + 1, nc = cb.N + 1;
+  const int nf = NF > 0 ? NF + 1 : fb.N + 1, nc = NC > 0 ? NC + 1 : cb.N + 1;
+  const int Nf = nf - 1;
+  const int bs = BS > 0 ? BS : (int)blockDim.x;
   T *sJ = smem;                                 // nf*nc
   T *sf = sJ + nf * nc;                         // nf^3 (later nf*nc*nc)
   T *t1 = sf + nf * nf * nf;                    // nf*nf*nc
   if (e >= E) return;
-  const int ex = (int)(e % fb.nex), ey = (int)((e / fb.nex) % fb.ney), ez = (int)(e / ((int64_t)fb.nex * fb.ney));
-  for (int q = threadIdx.x; q < nf * nc; q += blockDim.x) sJ[q] = Jm[q];
-  for (int q = threadIdx.x; q < nf * nf * nf; q += blockDim.x) {
+  const Exyz ec = elem_xyz(fb, e);
+  const int ex = ec.x, ey = ec.y, ez = ec.z;
+  for (int q = threadIdx.x; q < nf * nc; q += bs) sJ[q] = Jm[q];
+  for (int q = threadIdx.x; q < nf * nf * nf; q += bs) {
     const int i = q % nf, j = (q / nf) % nf, k = q / (nf * nf);
-    const int64_t g = lattice_index(fb, ex * fb.N + i, ey * fb.N + j, ez * fb.N + k);
-    sf[q] = g >= 0 ? rw[g] : T(0);
+    const int64_t g = lattice_index(fb, ex * Nf + i, ey * Nf + j, ez * Nf + k);
+    const T v = rw[g >= 0 ? g : 0];  // unconditional load, then select
+    sf[q] = g >= 0 ? v : T(0);
   }
   __syncthreads();
   // t1[k][j][a] = sum_i J[i][a] sf[k][j][i]
-  for (int q = threadIdx.x; q < nf * nf * nc; q += blockDim.x) {
+  for (int q = threadIdx.x; q < nf * nf * nc; q += bs) {
     const int a = q % nc, j = (q / nc) % nf, k = q / (nc * nf);
     T s = 0;
     for (int i = 0; i < nf; ++i) s += sJ[i * nc + a] * sf[(k * nf + j) * nf + i];
@@ -237,7 +220,7 @@ __device__ __forceinline__ void restrict_body(int64_t e, const Box &fb, const Bo
   }
   __syncthreads();
   // sf[k][b][a] = sum_j J[j][b] t1[k][j][a]
-  for (int q = threadIdx.x; q < nf * nc * nc; q += blockDim.x) {
+  for (int q = threadIdx.x; q < nf * nc * nc; q += bs) {
     const int a = q % nc, bq = (q / nc) % nc, k = q / (nc * nc);
     T s = 0;
     for (int j = 0; j < nf; ++j) s += sJ[j * nc + bq] * t1[(k * nf + j) * nc + a];
@@ -246,7 +229,7 @@ __device__ __forceinline__ void restrict_body(int64_t e, const Box &fb, const Bo
   __syncthreads();
   // out[c][b][a] = sum_k J[k][c] sf[k][b][a]
   T *out = rcL + e * nc * nc * nc;
-  for (int q = threadIdx.x; q < nc * nc * nc; q += blockDim.x) {
+  for (int q = threadIdx.x; q < nc * nc * nc; q += bs) {
     const int a = q % nc, bq = (q / nc) % nc, c = q / (nc * nc);
     T s = 0;
     for (int k = 0; k < nf; ++k) s += sJ[k * nc + c] * sf[(k * nc + bq) * nc + a];
@@ -254,36 +237,40 @@ __device__ __forceinline__ void restrict_body(int64_t e, const Box &fb, const Bo
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256)
+template <typename T, int NF, int NC>
+__global__ void __launch_bounds__(128)
 restrict_kernel(Box fb, Box cb, int64_t E, const T *__restrict__ rw, const T *__restrict__ Jm,
                 T *__restrict__ rcL) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  restrict_body<T>(blockIdx.x, fb, cb, E, rw, Jm, rcL, reinterpret_cast<T *>(smem_raw));
+  restrict_body<T, NF, NC, 128>(blockIdx.x, fb, cb, E, rw, Jm, rcL, reinterpret_cast<T *>(smem_raw));
 }
 
 // Prolongation x_f += P x_c: every fine element interpolates the coarse element
 // values and updates the fine unknowns it owns (local i, j, k < N_f).
-template <typename T>
+template <typename T, int NF = 0, int NC = 0, int BS = 0>
 __device__ __forceinline__ void prolong_body(int64_t e, const Box &fb, const Box &cb, int64_t E,
                                              const T *__restrict__ xc, const T *__restrict__ Jm,
                                              T *__restrict__ xf, double *__restrict__ zout, T *smem) {
-  const int nf = fb.N + 1, nc = cb.N + 1;
+  const int nf = NF > 0 ? NF + 1 : fb.N + 1, nc = NC > 0 ? NC + 1 : cb.N + 1;
+  const int Nf = nf - 1, Nc = nc - 1;
+  const int bs = BS > 0 ? BS : (int)blockDim.x;
   T *sJ = smem;                                 // nf*nc
   T *sc = sJ + nf * nc;                         // nc^3
   T *t1 = sc + nc * nc * nc;                    // nc*nc*nf
   T *t2 = t1 + nc * nc * nf;                    // nc*nf*nf
   if (e >= E) return;
-  const int ex = (int)(e % fb.nex), ey = (int)((e / fb.nex) % fb.ney), ez = (int)(e / ((int64_t)fb.nex * fb.ney));
-  for (int q = threadIdx.x; q < nf * nc; q += blockDim.x) sJ[q] = Jm[q];
-  for (int q = threadIdx.x; q < nc * nc * nc; q += blockDim.x) {
+  const Exyz ec = elem_xyz(fb, e);
+  const int ex = ec.x, ey = ec.y, ez = ec.z;
+  for (int q = threadIdx.x; q < nf * nc; q += bs) sJ[q] = Jm[q];
+  for (int q = threadIdx.x; q < nc * nc * nc; q += bs) {
     const int a = q % nc, bq = (q / nc) % nc, c = q / (nc * nc);
-    const int64_t g = lattice_index(cb, ex * cb.N + a, ey * cb.N + bq, ez * cb.N + c);
-    sc[q] = g >= 0 ? xc[g] : T(0);
+    const int64_t g = lattice_index(cb, ex * Nc + a, ey * Nc + bq, ez * Nc + c);
+    const T v = xc[g >= 0 ? g : 0];
+    sc[q] = g >= 0 ? v : T(0);
   }
   __syncthreads();
   // t1[c][b][i] = sum_a J[i][a] sc[c][b][a]
-  for (int q = threadIdx.x; q < nc * nc * nf; q += blockDim.x) {
+  for (int q = threadIdx.x; q < nc * nc * nf; q += bs) {
     const int i = q % nf, bq = (q / nf) % nc, c = q / (nf * nc);
     T s = 0;
     for (int a = 0; a < nc; ++a) s += sJ[i * nc + a] * sc[(c * nc + bq) * nc + a];
@@ -291,16 +278,17 @@ __device__ __forceinline__ void prolong_body(int64_t e, const Box &fb, const Box
   }
   __syncthreads();
   // t2[c][j][i] = sum_b J[j][b] t1[c][b][i]
-  for (int q = threadIdx.x; q < nc * nf * nf; q += blockDim.x) {
+  for (int q = threadIdx.x; q < nc * nf * nf; q += bs) {
     const int i = q % nf, j = (q / nf) % nf, c = q / (nf * nf);
     T s = 0;
     for (int bq = 0; bq < nc; ++bq) s += sJ[j * nc + bq] * t1[(c * nc + bq) * nf + i];
     t2[(c * nf + j) * nf + i] = s;
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < fb.N * fb.N * fb.N; q += blockDim.x) {
-    const int i = q % fb.N, j = (q / fb.N) % fb.N, k = q / (fb.N * fb.N);
-    const int64_t g = lattice_index(fb, ex * fb.N + i, ey * fb.N + j, ez * fb.N + k);
+#pragma unroll 1
+  for (int q = threadIdx.x; q < Nf * Nf * Nf; q += bs) {
+    const int i = q % Nf, j = (q / Nf) % Nf, k = q / (Nf * Nf);
+    const int64_t g = lattice_index(fb, ex * Nf + i, ey * Nf + j, ez * Nf + k);
     if (g < 0) continue;
     T s = 0;
     for (int c = 0; c < nc; ++c) s += sJ[k * nc + c] * t2[(c * nf + j) * nf + i];
@@ -309,12 +297,12 @@ __device__ __forceinline__ void prolong_body(int64_t e, const Box &fb, const Box
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256)
+template <typename T, int NF, int NC>
+__global__ void __launch_bounds__(128)
 prolong_kernel(Box fb, Box cb, int64_t E, const T *__restrict__ xc, const T *__restrict__ Jm,
                T *__restrict__ xf, double *__restrict__ zout) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  prolong_body<T>(blockIdx.x, fb, cb, E, xc, Jm, xf, zout, reinterpret_cast<T *>(smem_raw));
+  prolong_body<T, NF, NC, 128>(blockIdx.x, fb, cb, E, xc, Jm, xf, zout, reinterpret_cast<T *>(smem_raw));
 }
 
 // ------------------------------------------------------------------ sparse / dense
@@ -373,11 +361,46 @@ __device__ __forceinline__ void gemv_row(int64_t row, int64_t nrows, int64_t n1c
   if (threadIdx.x == 0) y[row] = sub ? bvec[row] - s : s;
 }
 
-__global__ void __launch_bounds__(256)
-gemv_kernel(int64_t nrows, int64_t n1c, const double *__restrict__ M1, const double *__restrict__ x1,
-            int64_t n2c, const double *__restrict__ M2, const double *__restrict__ x2,
-            const double *__restrict__ bvec, double *__restrict__ y, int sub) {
-  gemv_row(blockIdx.x, nrows, n1c, M1, x1, n2c, M2, x2, bvec, y, sub);
+
+struct GemvJobs {
+  int njobs;
+  GemvJob job[2];
+};
+
+// One wavefront per output row, four rows per block: a lane keeps up to kRowUnroll
+// loads of the row in flight and the row sum is a fixed-order wave reduction
+// (no LDS, no barrier).
+constexpr int kRowUnroll = 16;
+__global__ void __launch_bounds__(256) gemv_jobs_kernel(const GemvJobs J) {
+  const int lane = threadIdx.x & 63;
+  int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t total = J.job[0].nrows + (J.njobs > 1 ? J.job[1].nrows : 0);
+  if (row >= total) return;
+  const bool second = J.njobs > 1 && row >= J.job[0].nrows;  // wave-uniform
+  const GemvJob jb = second ? J.job[1] : J.job[0];
+  if (second) row -= J.job[0].nrows;
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if (q >= jb.nseg) break;
+    const GemvSeg g = jb.seg[q];
+    const double *Mr = g.M + row * g.ncols;
+    double part = 0.0;
+    for (int64_t c0 = 0; c0 < g.ncols; c0 += 64 * kRowUnroll) {
+      double mv[kRowUnroll], xv[kRowUnroll];
+#pragma unroll
+      for (int u = 0; u < kRowUnroll; ++u) {
+        const int64_t c = c0 + lane + 64 * u;
+        mv[u] = c < g.ncols ? Mr[c] : 0.0;
+        xv[u] = c < g.ncols ? g.x[c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kRowUnroll; ++u) part += mv[u] * xv[u];
+    }
+    acc += g.sign * part;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) jb.y[row] = (jb.b ? jb.b[row] : 0.0) + acc;
 }
 
 // ------------------------------------------------------------------ reductions
@@ -435,6 +458,71 @@ finalize_kernel(int nblocks, int nd, const double *__restrict__ partials, double
   }
 }
 
+// ------------------------------------------------------------------ GMRES vector kernels
+// Classical Gram-Schmidt projections V_q . w for all q < k in one pass over w; per-thread
+// accumulators are compile-time indexed (guards on q < k, wave-uniform).
+__global__ void __launch_bounds__(256)
+multi_dot_kernel(int64_t n, int k, const double *__restrict__ V, int64_t ldv, const double *__restrict__ w,
+                 double *__restrict__ partials) {
+  __shared__ double sm[4];
+  double acc[kMaxRestart];
+#pragma unroll
+  for (int q = 0; q < kMaxRestart; ++q) acc[q] = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+    const double wg = w[g];
+#pragma unroll
+    for (int q = 0; q < kMaxRestart; ++q)
+      if (q < k) acc[q] += V[q * ldv + g] * wg;
+  }
+#pragma unroll
+  for (int q = 0; q < kMaxRestart; ++q) {
+    if (q < k) {
+      const double t = block_sum(acc[q], sm);
+      if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * k + q] = t;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+finalize_many_kernel(int nblocks, int nd, const double *__restrict__ partials, double *__restrict__ out) {
+  __shared__ double sm[4];
+  const int q = blockIdx.x;
+  double a = 0.0;
+  for (int bq = threadIdx.x; bq < nblocks; bq += blockDim.x) a += partials[(int64_t)bq * nd + q];
+  const double t = block_sum(a, sm);
+  if (threadIdx.x == 0) out[q] = t;
+}
+
+__global__ void __launch_bounds__(256)
+multi_axpy_kernel(int64_t n, int k, const double *__restrict__ V, int64_t ldv, const double *__restrict__ c,
+                  double sign, double *__restrict__ y, double *__restrict__ partials) {
+  __shared__ double sm[4];
+  __shared__ double sc[kMaxRestart];
+  if (threadIdx.x < k) sc[threadIdx.x] = c[threadIdx.x];
+  __syncthreads();
+  double acc = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxRestart; ++q)
+      if (q < k) t += sc[q] * V[q * ldv + g];
+    const double v = y[g] + sign * t;
+    y[g] = v;
+    acc += v * v;
+  }
+  if (partials) {
+    const double t = block_sum(acc, sm);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  }
+}
+
+__global__ void scale_inv_sqrt_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ nrm2,
+                                      double *__restrict__ y) {
+  const double d = sqrt(*nrm2);
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) y[g] = x[g] / d;
+}
+
 // x += alpha p; r_new = r - alpha w; partial ||r_new||^2. alpha = scal[RZ] / scal[PW].
 // r32 (optional): single-precision copy of r_new, the input of a mixed-precision cycle.
 __global__ void __launch_bounds__(256)
@@ -477,6 +565,12 @@ __global__ void axpby_kernel(int64_t n, double a, const double *__restrict__ x, 
   if (g < n) out[g] = a * x[g] + b * (y ? y[g] : 0.0);
 }
 
+template <typename T>
+__global__ void zero_kernel(int64_t n, T *__restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) out[g] = T(0);
+}
+
 __global__ void mul_kernel(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
                            double *__restrict__ out) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -504,9 +598,10 @@ adjoint_kernel(Box b, int64_t E, const double *__restrict__ lam, const double *_
   double lreg[n1], ureg[n1];
   int ex = 0, ey = 0, ez = 0;
   if (active) {
-    ex = (int)(e % b.nex);
-    ey = (int)((e / b.nex) % b.ney);
-    ez = (int)(e / ((int64_t)b.nex * b.ney));
+    const Exyz ec = elem_xyz(b, e);
+    ex = ec.x;
+    ey = ec.y;
+    ez = ec.z;
   }
   const int I = ex * N + i, J = ey * N + j;
   const bool inIJ = active && I >= 1 && I <= b.nx && J >= 1 && J <= b.ny;
@@ -764,7 +859,20 @@ template <int N, typename T, typename GT>
 void launch_ax_n(const Level &L, const T *u, const GT *G, const T *D, T *wL, int variant, hipStream_t s) {
   using S = AxShape<N>;
   const unsigned grid = (unsigned)((L.E + S::epb - 1) / S::epb);
-  if (variant == 1)
+  if constexpr (sizeof(GT) == 2) {
+    if (variant == 5) {
+      hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, S::min_waves, 2>), dim3(grid), dim3(S::block), 0, s,
+                         mkbox(L), L.E, u, G, D, wL);
+      return;
+    }
+  }
+  if (variant == 3)
+    hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 1, 1, 1>), dim3(grid), dim3(S::block), 0, s, mkbox(L), L.E, u,
+                       G, D, wL);
+  else if (variant == 4)
+    hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, S::min_waves, 1>), dim3(grid), dim3(S::block), 0, s,
+                       mkbox(L), L.E, u, G, D, wL);
+  else if (variant == 1)
     hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, S::min_waves>), dim3(grid), dim3(S::block), 0, s, mkbox(L),
                        L.E, u, G, D, wL);
   else if (variant == 2)
@@ -869,12 +977,22 @@ void launch_resid_weight(const Level &L, const T *wL, const T *b, T *rw, hipStre
 template void launch_resid_weight<double>(const Level &, const double *, const double *, double *, hipStream_t);
 template void launch_resid_weight<float>(const Level &, const float *, const float *, float *, hipStream_t);
 
+// (fine, coarse) order pairs with compiled-in sizes: the N -> N/2 -> 1 schedules for
+// N = 2..12 and the (7,5,3,1) schedule; other pairs use the run-time sized kernels.
+#define SEMCHEB_TRANSFER_PAIRS(X) \
+  X(2, 1) X(3, 1) X(4, 1) X(5, 1) X(6, 1) X(4, 2) X(5, 2) X(6, 3) X(7, 3) X(8, 4) X(9, 4) X(10, 5) \
+  X(11, 5) X(12, 6) X(7, 5) X(5, 3)
+
 template <typename T>
 void launch_restrict(const Level &F, const Level &C, const T *rw, const T *J, T *rcL, hipStream_t s) {
   const int nf = F.N + 1, nc = C.N + 1;
   const size_t lds = sizeof(T) * (size_t)(nf * nc + nf * nf * nf + nf * nf * nc);
-  hipLaunchKernelGGL((restrict_kernel<T>), dim3((unsigned)F.E), dim3(128), lds, s, mkbox(F), mkbox(C), F.E, rw,
-                     J, rcL);
+  auto kern = restrict_kernel<T, 0, 0>;
+#define SEMCHEB_PICK(A, B) \
+  if (F.N == A && C.N == B) kern = restrict_kernel<T, A, B>;
+  SEMCHEB_TRANSFER_PAIRS(SEMCHEB_PICK)
+#undef SEMCHEB_PICK
+  hipLaunchKernelGGL(kern, dim3((unsigned)F.E), dim3(128), lds, s, mkbox(F), mkbox(C), F.E, rw, J, rcL);
 }
 template void launch_restrict<double>(const Level &, const Level &, const double *, const double *, double *,
                                       hipStream_t);
@@ -885,8 +1003,12 @@ template <typename T>
 void launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *xf, double *zout, hipStream_t s) {
   const int nf = F.N + 1, nc = C.N + 1;
   const size_t lds = sizeof(T) * (size_t)(nf * nc + nc * nc * nc + nc * nc * nf + nc * nf * nf);
-  hipLaunchKernelGGL((prolong_kernel<T>), dim3((unsigned)F.E), dim3(128), lds, s, mkbox(F), mkbox(C), F.E, xc,
-                     J, xf, zout);
+  auto kern = prolong_kernel<T, 0, 0>;
+#define SEMCHEB_PICK(A, B) \
+  if (F.N == A && C.N == B) kern = prolong_kernel<T, A, B>;
+  SEMCHEB_TRANSFER_PAIRS(SEMCHEB_PICK)
+#undef SEMCHEB_PICK
+  hipLaunchKernelGGL(kern, dim3((unsigned)F.E), dim3(128), lds, s, mkbox(F), mkbox(C), F.E, xc, J, xf, zout);
 }
 template void launch_prolong<double>(const Level &, const Level &, const double *, const double *, double *,
                                      double *, hipStream_t);
@@ -905,14 +1027,20 @@ template void launch_csr<float>(const DevCsr &, const float *, const float *, co
 
 void launch_gemv(int64_t nrows, int64_t ncols, const double *M, const double *x, const double *b, double *y,
                  int sub, hipStream_t s) {
-  hipLaunchKernelGGL(gemv_kernel, dim3((unsigned)nrows), dim3(256), 0, s, nrows, ncols, M, x, (int64_t)0,
-                     (const double *)nullptr, (const double *)nullptr, b, y, sub);
+  GemvJob jb{sub ? b : nullptr, y, nrows, 1, {{M, x, ncols, sub ? -1.0 : 1.0}}};
+  launch_gemv_jobs(1, &jb, s);
 }
 
-void launch_gemv2(int64_t nrows, int64_t n1c, const double *M1, const double *x1, int64_t n2c, const double *M2,
-                  const double *x2, double *y, hipStream_t s) {
-  hipLaunchKernelGGL(gemv_kernel, dim3((unsigned)nrows), dim3(256), 0, s, nrows, n1c, M1, x1, n2c, M2, x2,
-                     (const double *)nullptr, y, 0);
+void launch_gemv_jobs(int njobs, const GemvJob *jobs, hipStream_t s) {
+  GemvJobs J{};
+  J.njobs = njobs;
+  int64_t rows = 0;
+  for (int q = 0; q < njobs; ++q) {
+    J.job[q] = jobs[q];
+    rows += jobs[q].nrows;
+  }
+  if (rows == 0) return;
+  hipLaunchKernelGGL(gemv_jobs_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, J);
 }
 
 template <typename T>
@@ -948,6 +1076,28 @@ void launch_convert(int64_t n, const float *in, double *out, hipStream_t s) {
 void launch_axpby(int64_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s) {
   hipLaunchKernelGGL(axpby_kernel, dim3(nblk(n)), dim3(256), 0, s, n, a, x, b, y, out);
 }
+
+void launch_multi_dot(int64_t n, int k, const double *V, int64_t ldv, const double *w, double *partials,
+                      int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(multi_dot_kernel, dim3(nblocks), dim3(256), 0, s, n, k, V, ldv, w, partials);
+}
+void launch_finalize_many(int nblocks, int nd, const double *partials, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_many_kernel, dim3(nd), dim3(256), 0, s, nblocks, nd, partials, out);
+}
+void launch_multi_axpy(int64_t n, int k, const double *V, int64_t ldv, const double *c, double sign, double *y,
+                       double *partials, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(multi_axpy_kernel, dim3(nblocks), dim3(256), 0, s, n, k, V, ldv, c, sign, y, partials);
+}
+void launch_scale_inv_sqrt(int64_t n, const double *x, const double *nrm2, double *y, hipStream_t s) {
+  hipLaunchKernelGGL(scale_inv_sqrt_kernel, dim3(nblk(n)), dim3(256), 0, s, n, x, nrm2, y);
+}
+
+template <typename T>
+void launch_zero(int64_t n, T *out, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(zero_kernel<T>, dim3(nblk(n)), dim3(256), 0, s, n, out);
+}
+template void launch_zero<double>(int64_t, double *, hipStream_t);
+template void launch_zero<float>(int64_t, float *, hipStream_t);
 
 void launch_mul(int64_t n, const double *a, const double *b, double *out, hipStream_t s) {
   hipLaunchKernelGGL(mul_kernel, dim3(nblk(n)), dim3(256), 0, s, n, a, b, out);

@@ -136,7 +136,7 @@ class SemSolver(_Base):
 
     def __init__(self, verts, N=7, smoother="cheb4opt", pre=4, post=0, precision="fp64",
                  krylov="fcg", orders=None, lambda_max=None, lambda_scale=1.0, device=0,
-                 coarse_planes=0):
+                 coarse_planes=0, restart=30):
         super().__init__()
         verts = np.ascontiguousarray(np.asarray(verts, dtype=np.float64))
         if verts.ndim != 4 or verts.shape[3] != 3:
@@ -145,7 +145,7 @@ class SemSolver(_Base):
         mesh = L.SemBoxMesh(verts.shape[2] - 1, verts.shape[1] - 1, verts.shape[0] - 1,
                             verts.ctypes.data_as(C.POINTER(C.c_double)))
         opt = L.make_options(N, smoother, pre, post, precision, krylov, orders, lambda_max,
-                             lambda_scale, device, coarse_planes)
+                             lambda_scale, device, coarse_planes, restart)
         ctx = C.c_void_p()
         stream = _stream() if device >= 0 else C.c_void_p(0)
         L.check(self._lib.sem_setup_box(C.byref(mesh), C.byref(opt), stream, C.byref(ctx)))
@@ -208,9 +208,10 @@ class FdSolver(_Base):
     """2D finite-difference Poisson with Galerkin geometric multigrid (the paper's Sec. 3 problem)."""
 
     def __init__(self, n=64, Lx=1.0, Ly=1.0, factor=2, coarsest_n=8, smoother="cheb4", pre=4, post=0,
-                 krylov="fcg", lambda_max=None, lambda_scale=1.0, device=0):
+                 krylov="fcg", lambda_max=None, lambda_scale=1.0, device=0, restart=30):
         super().__init__()
-        opt = L.make_options(1, smoother, pre, post, "fp64", krylov, None, lambda_max, lambda_scale, device)
+        opt = L.make_options(1, smoother, pre, post, "fp64", krylov, None, lambda_max, lambda_scale, device,
+                             0, restart)
         ctx = C.c_void_p()
         stream = _stream() if device >= 0 else C.c_void_p(0)
         L.check(self._lib.sem_setup_fd2d(int(n), float(Lx), float(Ly), int(factor), int(coarsest_n),

@@ -48,6 +48,27 @@ def test_apply_A_parity(m, N):
     assert relmax(w, box.apply(u)) < 1e-14 * (N + 1) ** 2
 
 
+@pytest.mark.parametrize("variant", range(6))
+@pytest.mark.parametrize("N", [2, 3, 7, 9])
+def test_operator_variants_parity(N, variant, monkeypatch):
+    # every operator kernel variant the autotuner may pick, FP64 and FP32/BF16, against the oracle
+    print(f"operator variant {variant} N={N}", flush=True)
+    monkeypatch.setenv("SEMCHEB_AX_VARIANT", str(variant))
+    V = wl.deformed_box((3, 2, 3), 0.05)
+    box = SemBox(V, N)
+    s = SemSolver(V, N=N, lambda_max=[1.0] * 8, orders=[N, 1], precision="mixed")
+    u = wl.uniform_noise(box.n, 12)
+    w = host(s.apply_A(dev(u)))
+    assert relmax(w, box.apply(u)) < 1e-14 * (N + 1) ** 2
+    # element-local outputs: FP64 path exact to rounding; FP32 arithmetic with BF16 factors
+    # within the factors' 2^-8 relative rounding
+    wl64 = host(s.apply_local(dev(u)))
+    wl32 = s.apply_local(dev(u).float()).double().cpu().numpy()
+    ref = box.apply_local(box.scatter(u)).ravel()
+    assert relmax(wl64, ref) < 1e-14 * (N + 1) ** 2
+    assert relmax(wl32, ref) < 1e-2  # BF16 rounding of the factors alone gives up to 2.4e-3 here
+
+
 def test_apply_A_order1_and_deterministic():
     V = wl.deformed_box((3, 3, 2), 0.05)
     s = SemSolver(V, N=2, orders=[2, 1], lambda_max=[1.0])
@@ -137,6 +158,34 @@ def test_cfg2_solve_parity(cfg2):
     u, info, res = _solve_parity(s, ref, box.apply, b, flexible=True)
     # fine-grid mat-vecs = iterations x (m + n + 1)
     assert s.apply_counts()[0] == info.iterations * (4 + 0 + 1)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_matches_direct_launches(cfg2, precision, monkeypatch):
+    # V-cycles replayed from captured graphs (default) against the same kernels launched one by
+    # one: every replay of a solve, and repeated solves with host work in between, are bitwise equal
+    V, ref, box, b, lmax = cfg2
+    print(f"graph replay {precision}", flush=True)
+    # both contexts use the same operator variant (the autotuner may pick different ones, whose
+    # rounding differs)
+    monkeypatch.setenv("SEMCHEB_AX_VARIANT", "0")
+    monkeypatch.setenv("SEMCHEB_GRAPHS", "0")
+    direct = SemSolver(V, N=7, precision=precision, lambda_max=lmax)
+    monkeypatch.delenv("SEMCHEB_GRAPHS")
+    graph = SemSolver(V, N=7, precision=precision, lambda_max=lmax)
+    ud, infod = direct.solve(dev(b))
+    direct.reset_counts()
+    direct.solve(dev(b))
+    counts_direct = direct.apply_counts()
+    for rep in range(3):
+        graph.reset_counts()
+        ug, infog = graph.solve(dev(b))
+        assert infog.iterations == infod.iterations
+        assert np.array_equal(infog.history, infod.history), rep
+        assert torch.equal(ug, ud), rep
+        assert graph.apply_counts() == counts_direct
+        zg = graph.vcycle(dev(b))  # eager cycle between replays
+        assert torch.isfinite(zg).all()
 
 
 @pytest.mark.parametrize("kind,pre,post,kry", [("cheb4", 2, 2, "pcg"), ("cheb1", 3, 3, "pcg"),
@@ -243,6 +292,22 @@ def test_blocked_coarse_solve_parity(small_case, planes):
     ref = mg.sem_hierarchy(V, N, cheb.CHEB4, 2, 2, lmax=lmax)
     s = SemSolver(V, N=N, smoother="cheb4", pre=2, post=2, lambda_max=lmax, coarse_planes=planes)
     r = wl.uniform_noise(ref.levels[0].n, 6)
+    z = host(s.vcycle(dev(r)))
+    zo = ref.vcycle(r)
+    assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+
+
+@pytest.mark.parametrize("nz,planes", [(9, 1), (8, 1), (9, 3), (6, 2)])
+def test_blocked_coarse_solve_block_counts(nz, planes):
+    # two-ended block elimination with an even (8) and odd (7, 3) number of blocks and a
+    # ragged last block (8 planes in blocks of 3)
+    print(f"blocked coarse nz={nz} planes={planes}", flush=True)
+    V = wl.deformed_box((3, 2, nz), 0.05)
+    N = 3
+    ref = mg.sem_hierarchy(V, N, cheb.CHEB4, 2, 0)
+    lmax = [lev.lmax for lev in ref.levels[:-1]]
+    s = SemSolver(V, N=N, smoother="cheb4", pre=2, post=0, lambda_max=lmax, coarse_planes=planes)
+    r = wl.uniform_noise(ref.levels[0].n, 16)
     z = host(s.vcycle(dev(r)))
     zo = ref.vcycle(r)
     assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
