@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--order", type=int, default=7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batched measurement")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the 64-system batched measurement (for profiler runs)")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--kernel-only", action="store_true",
                     help="set up the FP64 and mixed contexts with fixed lambda_max and only launch the "
@@ -231,6 +233,9 @@ def main():
     if args.kernel_only:
         kernel_only(args)
         return
+    if args.batched_only:
+        print(json.dumps({"batched": bench_batched(max(1, args.steps // 2))}), flush=True)
+        return
     m, N = args.m, args.order
     V = wl.deformed_box(m, 0.05)
     t0 = time.perf_counter()
@@ -283,6 +288,8 @@ def main():
     v64, vmx = int(tune64[0]), int(tunemx[1 + nvar])
     k64 = "ax_local_kernel<%d, double, double, %d, %d, %d>" % ((N,) + _variant_args(v64, N))
     kmx = "ax_local_kernel<%d, float, bf16, %d, %d, %d>" % ((N,) + _variant_args(vmx, N))
+    log(f"operator variants (us) fp64 {[round(x, 1) for x in tune64[1:1 + nvar]]} -> {v64}, "
+        f"bf16 {[round(x, 1) for x in tunemx[2 + nvar:2 + 2 * nvar]]} -> {vmx}")
     tr64 = measured_traffic(k64) if N == 7 and m == 32 else None
     trmx = measured_traffic(kmx) if N == 7 and m == 32 else None
     out = {
@@ -323,6 +330,16 @@ def main():
                                       "bytes_per_launch": bytesmx,
                                       "traffic": round(trmx / t_axmx / 1e9, 1) if trmx else None}},
     }
+    # Table ksp-comparison analogue: time per iteration of GMRES(30) (classical Gram-Schmidt)
+    # against flexible CG, same mixed-precision preconditioner
+    sgm = SemSolver(V, N=N, smoother="cheb4opt", pre=4, post=0, precision="mixed", krylov="gmres",
+                    restart=30, lambda_max=smx.lambda_max())
+    _, infogm, dtgm, _, eachgm = time_solves(sgm, b, max(1, args.steps // 2), 1)
+    out["gmres30"] = {"ms_per_solve": round(dtgm * 1e3, 4), "iterations": infogm.iterations,
+                      "ms_per_iteration": round(dtgm * 1e3 / max(infogm.iterations, 1), 4),
+                      "fcg_ms_per_iteration": round(dtmx * 1e3 / max(infomx.iterations, 1), 4)}
+    log(f"gmres(30): {out['gmres30']}")
+    del sgm
     if not args.no_batched:
         log("batched systems ...")
         out["batched"] = bench_batched(max(1, args.steps // 2))

@@ -501,7 +501,7 @@ sem_status autotune_operator(sem_ctx *c, hipStream_t s) {
       return SEM_EINVAL;
     }
     for (auto &L : c->levels) {
-      L.ax_variant64 = v < kAxVariants64 ? v : 0;  // variant 5 exists for BF16 factors only
+      L.ax_variant64 = v < kAxVariants64 ? v : 0;
       L.ax_variant32 = v;
     }
     return SEM_OK;
@@ -513,7 +513,10 @@ sem_status autotune_operator(sem_ctx *c, hipStream_t s) {
   HIPCHK(c, hipEventCreate(&e1));
   const bool mixed = c->opt.precision == SEM_MIXED;
   HIPCHK(c, hipMemsetAsync(c->kr, 0, c->levels[0].n * sizeof(double), s));
-  const int reps = 4;
+  // three interleaved rounds of (one warm-up + three timed launches) per variant; a
+  // variant's time is its best round, so clock ramps and other transients during setup
+  // do not decide the choice
+  const int reps = 3, rounds = 3;
   sem_status st = SEM_OK;
   for (size_t j = 0; j + 1 < c->levels.size() && st == SEM_OK; ++j) {
     Level &L = c->levels[j];
@@ -521,26 +524,29 @@ sem_status autotune_operator(sem_ctx *c, hipStream_t s) {
       const bool fp64 = prec == 0;
       if (!fp64 && !(mixed && L.Gbf && L.w32)) continue;
       if (fp64 && !L.w64) continue;
-      float best = 1e30f;
       const int nvar = fp64 ? kAxVariants64 : kAxVariants;
-      for (int v = nvar; v < kAxVariants; ++v) (fp64 ? L.ax_time64_us : L.ax_time32_us)[v] = -1.0f;
-      for (int v = 0; v < nvar; ++v) {
-        int &var = fp64 ? L.ax_variant64 : L.ax_variant32;
-        var = v;
-        auto run = [&]() {
-          if (fp64) launch_ax(L, (const double *)c->kr, L.w64, s);
-          else launch_ax(L, (const float *)c->kr, L.w32, s);
-        };
-        run();
-        hipEventRecord(e0, s);
-        for (int r = 0; r < reps; ++r) run();
-        hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) { st = SEM_EHIP; break; }
-        float ms = 0;
-        hipEventElapsedTime(&ms, e0, e1);
-        const float us = ms * 1000.0f / reps;
-        (fp64 ? L.ax_time64_us : L.ax_time32_us)[v] = us;
-        if (us < best) best = us;
+      float *times = fp64 ? L.ax_time64_us : L.ax_time32_us;
+      for (int v = 0; v < kAxVariants; ++v) times[v] = v < nvar ? 1e30f : -1.0f;
+      for (int round = 0; round < rounds && st == SEM_OK; ++round) {
+        for (int v = 0; v < nvar; ++v) {
+          int &var = fp64 ? L.ax_variant64 : L.ax_variant32;
+          var = v;
+          auto run = [&]() {
+            if (fp64) launch_ax(L, (const double *)c->kr, L.w64, s);
+            else launch_ax(L, (const float *)c->kr, L.w32, s);
+          };
+          run();
+          hipEventRecord(e0, s);
+          for (int r = 0; r < reps; ++r) run();
+          hipEventRecord(e1, s);
+          if (hipEventSynchronize(e1) != hipSuccess) {
+            st = SEM_EHIP;
+            break;
+          }
+          float ms = 0;
+          hipEventElapsedTime(&ms, e0, e1);
+          times[v] = std::min(times[v], ms * 1000.0f / reps);
+        }
       }
       const float *tt = fp64 ? L.ax_time64_us : L.ax_time32_us;
       int bv = 0;

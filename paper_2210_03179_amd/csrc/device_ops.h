@@ -26,8 +26,27 @@ template <>
 __device__ __forceinline__ float load_factor<float, float>(const float *p) { return *p; }
 
 // ------------------------------------------------------------------ box geometry helpers
+// Division by the (small) element order with a precomputed multiply-high reciprocal
+// (Granlund-Montgomery, rounding the reciprocal up): with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1, x / d = (mulhi(x, m) + x) >> l for every
+// 0 <= x < 2^31, which covers all lattice coordinates.
+struct FastDiv {
+  uint32_t m;
+  int l;
+};
+__host__ __device__ inline FastDiv make_fastdiv(int d) {
+  int l = 0;
+  while ((1 << l) < d) ++l;
+  const uint64_t m = ((uint64_t(1) << 32) * (uint64_t)((1 << l) - d)) / (uint64_t)d + 1;
+  return FastDiv{(uint32_t)m, l};
+}
+__device__ __forceinline__ int fdiv(const FastDiv &f, int x) {
+  return (int)((__umulhi((uint32_t)x, f.m) + (uint32_t)x) >> f.l);
+}
+
 struct Box {
   int N, nex, ney, nez, nx, ny, nz;
+  FastDiv fN;  // division by N
 };
 
 // Element coordinates of element e (x fastest). 32-bit unsigned arithmetic: element and
@@ -88,11 +107,13 @@ __device__ __forceinline__ void ijk_next(const Box &b, Ijk &c) {
 // q-1 at local N, element q at local 0), otherwise one. All eight candidate loads are
 // issued at once under their validity predicates and summed in the fixed order
 // z-copy, y-copy, x-copy (missing copies add +0, which leaves the sum unchanged).
+// `faces` (optional) receives the number of axes on which the point lies on an element
+// face: the unknown has 2^faces element copies.
 template <typename T>
-__device__ __forceinline__ T dss_ijk(const T *__restrict__ wL, const Box &b, const Ijk &c) {
+__device__ __forceinline__ T dss_ijk(const T *__restrict__ wL, const Box &b, const Ijk &c, int *faces = nullptr) {
   const int N = b.N, n1 = N + 1;
   const int64_t n3 = (int64_t)n1 * n1 * n1;
-  const int qx = c.I / N, qy = c.J / N, qz = c.K / N;
+  const int qx = fdiv(b.fN, c.I), qy = fdiv(b.fN, c.J), qz = fdiv(b.fN, c.K);
   const int rx = c.I - qx * N, ry = c.J - qy * N, rz = c.K - qz * N;
   const bool fx = rx == 0, fy = ry == 0, fz = rz == 0;
   const int ex = fx ? qx - 1 : qx, ey = fy ? qy - 1 : qy, ez = fz ? qz - 1 : qz;
@@ -111,7 +132,14 @@ __device__ __forceinline__ T dss_ijk(const T *__restrict__ wL, const Box &b, con
   T s = w[0];
 #pragma unroll
   for (int q = 1; q < 8; ++q) s += w[q];
+  if (faces) *faces = (int)fx + (int)fy + (int)fz;
   return s;
+}
+
+// Number of axes on which lattice point c lies on an element face (2^faces copies).
+__device__ __forceinline__ int face_count(const Box &b, const Ijk &c) {
+  const int rx = c.I - fdiv(b.fN, c.I) * b.N, ry = c.J - fdiv(b.fN, c.J) * b.N, rz = c.K - fdiv(b.fN, c.K) * b.N;
+  return (int)(rx == 0) + (int)(ry == 0) + (int)(rz == 0);
 }
 
 template <typename T>
@@ -119,15 +147,8 @@ __device__ __forceinline__ T dss_at(const T *__restrict__ wL, const Box &b, int6
   return dss_ijk(wL, b, ijk_of(b, g));
 }
 
-// 1 / (number of element copies) of an unknown: a power of two, so exact.
-__device__ __forceinline__ double inv_mult_ijk(const Box &b, const Ijk &c) {
-  int m = 1;
-  if (c.I % b.N == 0) m *= 2;
-  if (c.J % b.N == 0) m *= 2;
-  if (c.K % b.N == 0) m *= 2;
-  return 1.0 / m;
-}
-__device__ __forceinline__ double inv_mult(const Box &b, int64_t g) { return inv_mult_ijk(b, ijk_of(b, g)); }
+// 1 / (number of element copies) of an unknown with `faces` face axes: a power of two, so exact.
+__device__ __forceinline__ double inv_mult_faces(int faces) { return 1.0 / (double)(1 << faces); }
 
 __device__ __forceinline__ int64_t lattice_index(const Box &b, int I, int J, int K) {
   if (I < 1 || I > b.nx || J < 1 || J > b.ny || K < 1 || K > b.nz) return -1;
@@ -524,6 +545,103 @@ __device__ __forceinline__ void ax_body_dma(unsigned blk, const Box &b, int64_t 
 #pragma unroll
     for (int k = 0; k < n1; ++k) we[(k * n1 + j) * n1 + i] = su[lec][k][j][i] + tt[k];
   }
+}
+
+// FP64 operator at N = 7 (one element per wave) with the factors streamed through a
+// ring of kRing planes in LDS by global-to-LDS DMA: while plane k computes, planes
+// k+1 .. k+kRing-1 are in flight, and no factor lives in registers. A plane is six
+// 512-byte component chunks, moved by three 16-byte-per-lane DMA loads (lanes 0-31 and
+// 32-63 take two components). The DMA writes are not tracked by the compiler: before
+// plane k is read, an explicit s_waitcnt leaves in flight only the loads of later planes,
+// and before a slot is refilled every LDS read of it has completed.
+template <int N>
+__device__ __forceinline__ void ax_body_ring64(unsigned blk, const Box &b, int64_t E, const double *__restrict__ u,
+                                               const double *__restrict__ G, const double *__restrict__ Dm,
+                                               double *__restrict__ wL) {
+  static_assert(N == 7, "the ring variant assumes one 64-lane element per wave");
+  using T = double;
+  constexpr int n1 = N + 1, n2 = n1 * n1, n3 = n1 * n2;
+  constexpr int kRing = 4;
+  __shared__ __align__(16) T sG[kRing][6][n2];
+  __shared__ T sD[n2];
+  __shared__ T su[n1][n1][n1];
+  __shared__ T sr[n1][n1];
+  __shared__ T ss[n1][n1];
+  const int t = threadIdx.x;  // 64 threads
+  const int i = t % n1, j = t / n1;
+  const int64_t e = blk;
+  if (e >= E) return;  // one element per block: the whole block leaves together
+  sD[t] = Dm[t];
+  T ureg[n1], tt[n1];
+  const Exyz ec = elem_xyz(b, e);
+  const int I = ec.x * N + i, J = ec.y * N + j;
+  const bool inIJ = I >= 1 && I <= b.nx && J >= 1 && J <= b.ny;
+  const int64_t gIJ = (int64_t)(I - 1) + (int64_t)b.nx * (J - 1);
+  const int64_t plane = (int64_t)b.nx * b.ny;
+#pragma unroll
+  for (int k = 0; k < n1; ++k) {
+    const int K = ec.z * N + k;
+    const bool ok = inIJ && K >= 1 && K <= b.nz;
+    const T v = u[ok ? gIJ + plane * (K - 1) : 0];
+    ureg[k] = ok ? v : T(0);
+    tt[k] = T(0);
+  }
+  // lane t moves bytes [16 (t % 32), +16) of component 2p + t / 32 of plane k
+  const char *gsrc = reinterpret_cast<const char *>(G + e * 6 * n3) + (t >> 5) * (n3 * 8) + (t & 31) * 16;
+  auto issue = [&](int k) {
+    char *dst = reinterpret_cast<char *>(&sG[k % kRing][0][0]);
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      __builtin_amdgcn_global_load_lds(gsrc + (int64_t)(2 * p) * (n3 * 8) + (int64_t)k * (n2 * 8),
+                                       (__attribute__((address_space(3))) void *)(dst + p * 1024), 16, 0, 0);
+  };
+#pragma unroll
+  for (int k = 0; k < kRing; ++k) issue(k);
+#pragma unroll
+  for (int k = 0; k < n1; ++k) su[k][j][i] = ureg[k];
+  __syncthreads();
+  T Di[n1];
+#pragma unroll
+  for (int l = 0; l < n1; ++l) Di[l] = sD[i * n1 + l];
+#pragma unroll 1
+  for (int k = 0; k < n1; ++k) {
+    // loads issued after plane k's: planes k+1 .. min(k+kRing-1, n1-1), three each
+    const int later = (n1 - 1 - k) < (kRing - 1) ? (n1 - 1 - k) : (kRing - 1);
+    if (later >= 3) asm volatile("s_waitcnt vmcnt(9)" ::: "memory");
+    else if (later == 2) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+    else if (later == 1) asm volatile("s_waitcnt vmcnt(3)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    const T *gk = &sG[k % kRing][0][t];
+    const T g0 = gk[0 * n2], g1 = gk[1 * n2], g2 = gk[2 * n2], g3 = gk[3 * n2], g4 = gk[4 * n2], g5 = gk[5 * n2];
+    T ur = 0, us = 0, ut = 0;
+#pragma unroll
+    for (int l = 0; l < n1; ++l) {
+      ur += Di[l] * su[k][j][l];
+      us += sD[j * n1 + l] * su[k][l][i];
+      ut += Dm[k * n1 + l] * ureg[l];  // wave-uniform: scalar loads
+    }
+    const T wr = g0 * ur + g1 * us + g2 * ut;
+    const T ws = g1 * ur + g3 * us + g4 * ut;
+    const T wt = g2 * ur + g4 * us + g5 * ut;
+    sr[j][i] = wr;
+    ss[j][i] = ws;
+    __syncthreads();
+    T acc = 0;
+#pragma unroll
+    for (int l = 0; l < n1; ++l) acc += sD[l * n1 + i] * sr[j][l] + sD[l * n1 + j] * ss[l][i];
+    su[k][j][i] = acc;
+#pragma unroll
+    for (int l = 0; l < n1; ++l) tt[l] += Dm[k * n1 + l] * wt;
+    __syncthreads();
+    if (k + kRing < n1) {
+      // every LDS read of slot k % kRing (the g values above) has completed
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      issue(k + kRing);
+    }
+  }
+  T *we = wL + e * n3;
+#pragma unroll
+  for (int k = 0; k < n1; ++k) we[(k * n1 + j) * n1 + i] = su[k][j][i] + tt[k];
 }
 
 }  // namespace dev

@@ -115,8 +115,10 @@ struct Level {
   float ax_time64_us[6] = {}, ax_time32_us[6] = {};  // kAxVariants
 };
 constexpr int kGmresScalars = 2 * 32 + 2;  // projections (<= 32), ||w||^2, y (<= 32)
-constexpr int kAxVariants = 6;    // variant 5 (factors staged by DMA) exists for BF16 factors only
-constexpr int kAxVariants64 = 5;
+// variant 5 stages factors by DMA: the whole element block for BF16 factors, a ring of
+// planes for FP64 factors at N = 7 (other FP64 orders launch variant 0 for it)
+constexpr int kAxVariants = 6;
+constexpr int kAxVariants64 = 6;
 
 struct CoarseSolver {
   bool dense = true;

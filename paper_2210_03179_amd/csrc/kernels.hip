@@ -21,12 +21,14 @@ using namespace dev;
 // Variants of the operator kernel chosen per level by the setup-time autotuner:
 // PF (factor prefetch), OCC (waves per SIMD requested from the register allocator)
 // and TILE (0: u column in registers with one LDS plane, 1: whole u tile in LDS,
-// 2: u tile and the element's BF16 factors in LDS, single precision only).
+// 2: u tile and the element's BF16 factors in LDS, single precision only; 3: u tile and a
+// ring of FP64 factor planes in LDS, N = 7 only).
 template <int N, typename T, typename GT, int PF, int OCC, int TILE = 0>
 __global__ void __launch_bounds__(AxShape<N>::block, OCC)
 ax_local_kernel(Box b, int64_t E, const T *__restrict__ u, const GT *__restrict__ G,
                 const T *__restrict__ Dm, T *__restrict__ wL) {
-  if constexpr (TILE == 2) ax_body_dma<N>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
+  if constexpr (TILE == 3) ax_body_ring64<N>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
+  else if constexpr (TILE == 2) ax_body_dma<N>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
   else if constexpr (TILE == 1) ax_body_tile<N, T, GT, PF>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
   else ax_body<N, T, GT, PF>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
 }
@@ -162,8 +164,10 @@ __device__ __forceinline__ void resid_weight_body(unsigned blk, const Box &b, in
     const int64_t g = g0 + 64 * q;
     if (g < n) {
       T v = r[q];
-      if (wL) v -= dss_ijk(wL, b, cc);
-      rw[g] = v * (T)inv_mult_ijk(b, cc);
+      int faces;
+      if (wL) v -= dss_ijk(wL, b, cc, &faces);
+      else faces = face_count(b, cc);
+      rw[g] = v * (T)inv_mult_faces(faces);
     }
     if (q + 1 < VEC) ijk_advance(b, cc, 64);
   }
@@ -303,6 +307,118 @@ prolong_kernel(Box fb, Box cb, int64_t E, const T *__restrict__ xc, const T *__r
                T *__restrict__ xf, double *__restrict__ zout) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   prolong_body<T, NF, NC, 128>(blockIdx.x, fb, cb, E, xc, Jm, xf, zout, reinterpret_cast<T *>(smem_raw));
+}
+
+// Transfers for compiled (fine, coarse) order pairs: a block covers EX consecutive
+// elements along x (same ey, ez), so its fine-lattice rows are EX*Nf contiguous unknowns
+// (coalesced loads and stores instead of Nf-long runs per element). The per-element
+// contractions and their summation order are those of restrict_body / prolong_body.
+template <int NF, int NC, typename T>
+constexpr int rows_ex() {
+  return (sizeof(T) == 4 ? 64 : 32) / NF < 1 ? 1 : ((sizeof(T) == 4 ? 64 : 32) / NF > 8 ? 8 : (sizeof(T) == 4 ? 64 : 32) / NF);
+}
+
+template <typename T, int NF, int NC>
+__global__ void __launch_bounds__(256)
+restrict_rows_kernel(Box fb, Box cb, const T *__restrict__ rw, const T *__restrict__ Jm, T *__restrict__ rcL) {
+  constexpr int nf = NF + 1, nc = NC + 1, EX = rows_ex<NF, NC, T>(), RW = EX * NF + 1;
+  __shared__ T sJ[nf * nc];
+  __shared__ T srow[nf * nf * RW];         // fine rows [k][j][i_global]
+  __shared__ T t1[EX * nf * nf * nc];      // [el][k][j][a]
+  __shared__ T t2[EX * nf * nc * nc];      // [el][k][b][a]
+  const int ngx = (fb.nex + EX - 1) / EX;
+  const int gx = blockIdx.x % ngx;
+  const int ey = (blockIdx.x / ngx) % fb.ney, ez = blockIdx.x / (ngx * fb.ney);
+  const int ex0 = gx * EX;
+  const int nel = fb.nex - ex0 < EX ? fb.nex - ex0 : EX;
+  const int t = threadIdx.x;
+  for (int q = t; q < nf * nc; q += 256) sJ[q] = Jm[q];
+  for (int q = t; q < nf * nf * RW; q += 256) {
+    const int ig = q % RW, j = (q / RW) % nf, k = q / (RW * nf);
+    const int64_t g = lattice_index(fb, ex0 * NF + ig, ey * NF + j, ez * NF + k);
+    const T v = rw[g >= 0 ? g : 0];
+    srow[q] = g >= 0 ? v : T(0);
+  }
+  __syncthreads();
+  for (int q = t; q < EX * nf * nf * nc; q += 256) {  // t1[el][k][j][a] = sum_i J[i][a] f[k][j][i]
+    const int a = q % nc, j = (q / nc) % nf, k = (q / (nc * nf)) % nf, el = q / (nc * nf * nf);
+    const T *row = srow + (k * nf + j) * RW + el * NF;
+    T acc = 0;
+#pragma unroll
+    for (int i = 0; i < nf; ++i) acc += sJ[i * nc + a] * row[i];
+    t1[q] = acc;
+  }
+  __syncthreads();
+  for (int q = t; q < EX * nf * nc * nc; q += 256) {  // t2[el][k][b][a] = sum_j J[j][b] t1[el][k][j][a]
+    const int a = q % nc, bq = (q / nc) % nc, k = (q / (nc * nc)) % nf, el = q / (nc * nc * nf);
+    T acc = 0;
+#pragma unroll
+    for (int j = 0; j < nf; ++j) acc += sJ[j * nc + bq] * t1[((el * nf + k) * nf + j) * nc + a];
+    t2[q] = acc;
+  }
+  __syncthreads();
+  const int64_t e0 = ex0 + (int64_t)fb.nex * (ey + (int64_t)fb.ney * ez);
+  for (int q = t; q < nel * nc * nc * nc; q += 256) {  // out[el][c][b][a] = sum_k J[k][c] t2[el][k][b][a]
+    const int a = q % nc, bq = (q / nc) % nc, c = (q / (nc * nc)) % nc, el = q / (nc * nc * nc);
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < nf; ++k) acc += sJ[k * nc + c] * t2[((el * nf + k) * nc + bq) * nc + a];
+    rcL[(e0 + el) * (nc * nc * nc) + (c * nc + bq) * nc + a] = acc;
+  }
+}
+
+template <typename T, int NF, int NC>
+__global__ void __launch_bounds__(256)
+prolong_rows_kernel(Box fb, Box cb, const T *__restrict__ xc, const T *__restrict__ Jm, T *__restrict__ xf,
+                    double *__restrict__ zout) {
+  constexpr int nf = NF + 1, nc = NC + 1, EX = rows_ex<NF, NC, T>();
+  __shared__ T sJ[nf * nc];
+  __shared__ T sc[EX * nc * nc * nc];      // [el][c][b][a]
+  __shared__ T t1[EX * nc * nc * nf];      // [el][c][b][i]
+  __shared__ T t2[EX * nc * nf * nf];      // [el][c][j][i]
+  const int ngx = (fb.nex + EX - 1) / EX;
+  const int gx = blockIdx.x % ngx;
+  const int ey = (blockIdx.x / ngx) % fb.ney, ez = blockIdx.x / (ngx * fb.ney);
+  const int ex0 = gx * EX;
+  const int nel = fb.nex - ex0 < EX ? fb.nex - ex0 : EX;
+  const int t = threadIdx.x;
+  for (int q = t; q < nf * nc; q += 256) sJ[q] = Jm[q];
+  for (int q = t; q < EX * nc * nc * nc; q += 256) {
+    const int a = q % nc, bq = (q / nc) % nc, c = (q / (nc * nc)) % nc, el = q / (nc * nc * nc);
+    const int64_t g = el < nel ? lattice_index(cb, (ex0 + el) * NC + a, ey * NC + bq, ez * NC + c) : -1;
+    const T v = xc[g >= 0 ? g : 0];
+    sc[q] = g >= 0 ? v : T(0);
+  }
+  __syncthreads();
+  for (int q = t; q < EX * nc * nc * nf; q += 256) {  // t1[el][c][b][i] = sum_a J[i][a] sc[el][c][b][a]
+    const int i = q % nf, bq = (q / nf) % nc, c = (q / (nf * nc)) % nc, el = q / (nf * nc * nc);
+    T acc = 0;
+#pragma unroll
+    for (int a = 0; a < nc; ++a) acc += sJ[i * nc + a] * sc[((el * nc + c) * nc + bq) * nc + a];
+    t1[q] = acc;
+  }
+  __syncthreads();
+  for (int q = t; q < EX * nc * nf * nf; q += 256) {  // t2[el][c][j][i] = sum_b J[j][b] t1[el][c][b][i]
+    const int i = q % nf, j = (q / nf) % nf, c = (q / (nf * nf)) % nc, el = q / (nf * nf * nc);
+    T acc = 0;
+#pragma unroll
+    for (int bq = 0; bq < nc; ++bq) acc += sJ[j * nc + bq] * t1[((el * nc + c) * nc + bq) * nf + i];
+    t2[q] = acc;
+  }
+  __syncthreads();
+  // owned fine nodes (local i, j, k < NF) of the run: rows of nel*NF contiguous unknowns
+  const int RL = nel * NF;
+  for (int q = t; q < NF * NF * RL; q += 256) {
+    const int ig = q % RL, j = (q / RL) % NF, k = q / (RL * NF);
+    const int el = ig / NF, i = ig - el * NF;
+    const int64_t g = lattice_index(fb, ex0 * NF + ig, ey * NF + j, ez * NF + k);
+    if (g < 0) continue;
+    T acc = 0;
+#pragma unroll
+    for (int c = 0; c < nc; ++c) acc += sJ[k * nc + c] * t2[((el * nc + c) * nf + j) * nf + i];
+    if (zout) zout[g] = (double)(xf[g] + acc);
+    else xf[g] += acc;
+  }
 }
 
 // ------------------------------------------------------------------ sparse / dense
@@ -660,7 +776,7 @@ __device__ __forceinline__ int table_slot(const LaunchTable &t, unsigned b) {
   return lo;
 }
 __device__ __forceinline__ Box lbox(const BatchLevelDev &L) {
-  return Box{L.N, L.nex, L.ney, L.nez, L.nx, L.ny, L.nz};
+  return Box{L.N, L.nex, L.ney, L.nez, L.nx, L.ny, L.nz, make_fastdiv(L.N)};
 }
 #define SEMCHEB_BATCH_SYS                                  \
   const int slot_ = table_slot(tab, blockIdx.x);           \
@@ -850,7 +966,7 @@ b_vec_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, int op) {
 
 inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
-inline Box mkbox(const Level &L) { return Box{L.N, L.nex, L.ney, L.nez, L.nx, L.ny, L.nz}; }
+inline Box mkbox(const Level &L) { return Box{L.N, L.nex, L.ney, L.nez, L.nx, L.ny, L.nz, make_fastdiv(L.N)}; }
 inline bool al16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 // variant 0: prefetch, compiler's register choice; 1: no prefetch, AxShape::min_waves;
@@ -859,6 +975,13 @@ template <int N, typename T, typename GT>
 void launch_ax_n(const Level &L, const T *u, const GT *G, const T *D, T *wL, int variant, hipStream_t s) {
   using S = AxShape<N>;
   const unsigned grid = (unsigned)((L.E + S::epb - 1) / S::epb);
+  if constexpr (sizeof(GT) == 8 && N == 7) {
+    if (variant == 5) {
+      hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, 4, 3>), dim3(grid), dim3(S::block), 0, s, mkbox(L), L.E, u,
+                         G, D, wL);
+      return;
+    }
+  }
   if constexpr (sizeof(GT) == 2) {
     if (variant == 5) {
       hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, S::min_waves, 2>), dim3(grid), dim3(S::block), 0, s,
@@ -987,12 +1110,18 @@ template <typename T>
 void launch_restrict(const Level &F, const Level &C, const T *rw, const T *J, T *rcL, hipStream_t s) {
   const int nf = F.N + 1, nc = C.N + 1;
   const size_t lds = sizeof(T) * (size_t)(nf * nc + nf * nf * nf + nf * nf * nc);
-  auto kern = restrict_kernel<T, 0, 0>;
-#define SEMCHEB_PICK(A, B) \
-  if (F.N == A && C.N == B) kern = restrict_kernel<T, A, B>;
+#define SEMCHEB_PICK(A, B)                                                                              \
+  if (F.N == A && C.N == B) {                                                                           \
+    constexpr int ex = rows_ex<A, B, T>();                                                              \
+    const unsigned grid = (unsigned)(((F.nex + ex - 1) / ex) * (int64_t)F.ney * F.nez);                \
+    hipLaunchKernelGGL((restrict_rows_kernel<T, A, B>), dim3(grid), dim3(256), 0, s, mkbox(F), mkbox(C), rw, \
+                       J, rcL);                                                                         \
+    return;                                                                                             \
+  }
   SEMCHEB_TRANSFER_PAIRS(SEMCHEB_PICK)
 #undef SEMCHEB_PICK
-  hipLaunchKernelGGL(kern, dim3((unsigned)F.E), dim3(128), lds, s, mkbox(F), mkbox(C), F.E, rw, J, rcL);
+  hipLaunchKernelGGL((restrict_kernel<T, 0, 0>), dim3((unsigned)F.E), dim3(128), lds, s, mkbox(F), mkbox(C), F.E,
+                     rw, J, rcL);
 }
 template void launch_restrict<double>(const Level &, const Level &, const double *, const double *, double *,
                                       hipStream_t);
@@ -1003,12 +1132,18 @@ template <typename T>
 void launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *xf, double *zout, hipStream_t s) {
   const int nf = F.N + 1, nc = C.N + 1;
   const size_t lds = sizeof(T) * (size_t)(nf * nc + nc * nc * nc + nc * nc * nf + nc * nf * nf);
-  auto kern = prolong_kernel<T, 0, 0>;
-#define SEMCHEB_PICK(A, B) \
-  if (F.N == A && C.N == B) kern = prolong_kernel<T, A, B>;
+#define SEMCHEB_PICK(A, B)                                                                              \
+  if (F.N == A && C.N == B) {                                                                           \
+    constexpr int ex = rows_ex<A, B, T>();                                                              \
+    const unsigned grid = (unsigned)(((F.nex + ex - 1) / ex) * (int64_t)F.ney * F.nez);                \
+    hipLaunchKernelGGL((prolong_rows_kernel<T, A, B>), dim3(grid), dim3(256), 0, s, mkbox(F), mkbox(C), xc, J, \
+                       xf, zout);                                                                       \
+    return;                                                                                             \
+  }
   SEMCHEB_TRANSFER_PAIRS(SEMCHEB_PICK)
 #undef SEMCHEB_PICK
-  hipLaunchKernelGGL(kern, dim3((unsigned)F.E), dim3(128), lds, s, mkbox(F), mkbox(C), F.E, xc, J, xf, zout);
+  hipLaunchKernelGGL((prolong_kernel<T, 0, 0>), dim3((unsigned)F.E), dim3(128), lds, s, mkbox(F), mkbox(C), F.E, xc,
+                     J, xf, zout);
 }
 template void launch_prolong<double>(const Level &, const Level &, const double *, const double *, double *,
                                      double *, hipStream_t);
