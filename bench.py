@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--order", type=int, default=7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batched measurement")
+    ap.add_argument("--no-schwarz", action="store_true", help="skip the Chebyshev-Schwarz measurement")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the 64-system batched measurement (for profiler runs)")
     ap.add_argument("--kernel-reps", type=int, default=20)
@@ -276,6 +277,13 @@ def main():
     t_axmx = time_kernel(lambda: smx.apply_local(u32, w32), args.kernel_reps)
     bytesmx = 16.0 * nloc + 4.0 * n
     t_apply = time_kernel(lambda: s64.apply_A(u_rand, w_loc[:n]), args.kernel_reps)
+    # achievable streaming bandwidth on this device: a 2 GiB device-to-device copy
+    # (1 GiB read + 1 GiB written), the reference the operator's fraction can also be read against
+    cpy_src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    cpy_dst = torch.empty_like(cpy_src)
+    t_copy = time_kernel(lambda: cpy_dst.copy_(cpy_src), 10)
+    copy_gbs = 2.0 * cpy_src.numel() * 8 / t_copy / 1e9
+    del cpy_src, cpy_dst
     log(f"ax fp64 {t_ax64 * 1e6:.1f} us ({bytes64 / t_ax64 / 1e9:.0f} GB/s), "
         f"ax bf16 {t_axmx * 1e6:.1f} us ({bytesmx / t_axmx / 1e9:.0f} GB/s), apply_A fp64 {t_apply * 1e6:.1f} us")
 
@@ -323,6 +331,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4),
                      "traffic": round(tr64 / t_ax64 / 1e9, 1) if tr64 else None,
+                     "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(ach / copy_gbs, 4),
                      "kernel": k64, "kernel_us": round(t_ax64 * 1e6, 2),
                      "bytes_per_launch": bytes64, "traffic_bytes_per_launch": tr64,
                      "mixed_kernel": {"kernel": kmx, "kernel_us": round(t_axmx * 1e6, 2),
@@ -340,6 +349,19 @@ def main():
                       "fcg_ms_per_iteration": round(dtmx * 1e3 / max(infomx.iterations, 1), 4)}
     log(f"gmres(30): {out['gmres30']}")
     del sgm
+    if not args.no_schwarz:
+        # Chebyshev-accelerated RAS smoothing with FDM local solves (Sec. 4.1), 4th kind (2,0),
+        # same hierarchy and mixed precision, GMRES(30) as in the paper's Schwarz runs
+        t0 = time.perf_counter()
+        ssw = SemSolver(V, N=N, smoother="cheb4", pre=2, post=0, precision="mixed", krylov="gmres", restart=30,
+                        schwarz="ras")
+        t_sw_setup = time.perf_counter() - t0
+        _, infosw, dtsw, _, _ = time_solves(ssw, b, max(1, args.steps // 2), 1)
+        out["schwarz_ras_cheb4_2_0"] = {"ms_per_solve": round(dtsw * 1e3, 4), "iterations": infosw.iterations,
+                                        "ms_per_iteration": round(dtsw * 1e3 / max(infosw.iterations, 1), 4),
+                                        "setup_s": round(t_sw_setup, 2), "lambda_max": ssw.lambda_max()}
+        log(f"schwarz RAS: {out['schwarz_ras_cheb4_2_0']}")
+        del ssw
     if not args.no_batched:
         log("batched systems ...")
         out["batched"] = bench_batched(max(1, args.steps // 2))

@@ -73,9 +73,21 @@ enum {
   SEM_CHEB4_OPT = 5  /* optimised 4th kind, beta from Table beta_coef (order <= 16) */
 };
 enum { SEM_FP64 = 0, SEM_MIXED = 1 }; /* precision of the V-cycle */
-/* Krylov method: PCG, flexible CG (Polak-Ribiere beta), or restarted flexible
- * GMRES(m) with classical Gram-Schmidt (Sec. 6.1: two reductions per iteration) */
-enum { SEM_PCG = 0, SEM_FCG = 1, SEM_GMRES = 2 };
+/* Basic smoother accelerated by the Chebyshev algorithms (Sec. 4.1): point Jacobi
+ * diag(A)^{-1}, or the Schwarz smoothers of eq. asm with fast-diagonalisation solves on
+ * element subdomains extended by one node per side (N+3 unknowns per axis, the element
+ * approximated by the box of its mean edge lengths): ASM sums the overlapping subdomain
+ * results and divides by the number of subdomains per node, RAS keeps each element's own
+ * nodes and averages shared element nodes. Schwarz needs SEM levels of order >= 3 on every
+ * smoothed level; lambda_max(S A) is estimated unless given: the largest real part of
+ * the eigenvalues of the Hessenberg matrix of 30 Arnoldi steps on S A. */
+enum { SEM_JACOBI = 0, SEM_ASM = 1, SEM_RAS = 2 };
+/* Outer method: PCG, flexible CG (Polak-Ribiere beta), restarted flexible GMRES(m)
+ * with classical Gram-Schmidt (Sec. 6.1: two reductions per iteration), or SEM_MG,
+ * multigrid as the solver (Sec. 3: the stationary V-cycle iteration whose average
+ * convergence rate, eq. avg-convergence-rate, is compared with Lemma
+ * multilevel-poly-bound and the critical C of the one-sided cycle) */
+enum { SEM_PCG = 0, SEM_FCG = 1, SEM_GMRES = 2, SEM_MG = 3 };
 
 #define SEM_MAX_LEVELS 8
 
@@ -87,13 +99,14 @@ typedef struct {
   int32_t pre_order;                /* m: order of pre-smoothing (0..32) */
   int32_t post_order;               /* n: order of post-smoothing, 0 = one-sided */
   int32_t precision;                /* SEM_FP64 or SEM_MIXED */
-  int32_t krylov;                   /* SEM_PCG, SEM_FCG or SEM_GMRES */
+  int32_t krylov;                   /* SEM_PCG, SEM_FCG, SEM_GMRES or SEM_MG */
   int32_t num_lambda_max;           /* 0: estimate every smoothed level at setup */
   double lambda_max[SEM_MAX_LEVELS];/* lambda_max(S_j A_j) per smoothed level */
   double lambda_scale;              /* factor applied to estimated values (0 -> 1) */
   int32_t device;                   /* HIP device ordinal; -1: host-only context */
   int32_t coarse_planes;            /* planes per block of the coarse solve, 0 = auto */
   int32_t gmres_restart;            /* m of GMRES(m), 1..32; 0 = 30 */
+  int32_t schwarz;                  /* smoother inside Chebyshev: SEM_JACOBI, SEM_ASM or SEM_RAS */
 } sem_options;
 
 /* Structured hexahedral box mesh: (nex+1)(ney+1)(nez+1) vertices, x fastest.
@@ -105,7 +118,8 @@ typedef struct {
 } sem_box_mesh;
 
 /* Fills *opt with: N = 7, default schedule, SEM_CHEB4_OPT, (4,0), FP64,
- * SEM_FCG, estimated lambda_max, lambda_scale 1, device 0, GMRES restart 30. */
+ * SEM_FCG, estimated lambda_max, lambda_scale 1, device 0, GMRES restart 30,
+ * Jacobi smoothing. */
 void sem_options_default(sem_options *opt);
 
 /* Set up the SEM hierarchy on a box mesh: GLL data, geometric factors, Jacobi
@@ -165,7 +179,11 @@ sem_status sem_vcycle(sem_ctx *ctx, const double *r, double *z, void *stream);
  * h_{j+1,j} = ||w|| (second reduction), Givens rotations on the host; the
  * residual used for stopping and in `history` is the rotated recurrence
  * |g_{j+1}|, the true residual norm of the current iterate in exact
- * arithmetic. Each restart recomputes r = b - A x. The V-cycles of the solve
+ * arithmetic. Each restart recomputes r = b - A x.
+ * With SEM_MG every iteration is u += V(r), r = b - A u (one V-cycle and one fine
+ * operator application); stopping and `history` use this true residual, so
+ * rho = (||r_N|| / ||r_0||)^(1/N) is the paper's average convergence rate. A
+ * single-precision cycle makes it iterative refinement. The V-cycles of the solve
  * are captured once per context as HIP graphs (on a private stream) and
  * replayed on `stream`; SEMCHEB_GRAPHS=0 in the environment at setup launches
  * them kernel by kernel instead (same kernels, bitwise identical results). */
@@ -205,17 +223,30 @@ sem_status sem_reset_counts(sem_ctx *ctx);
  * problems only), "ax_tuning" (all levels, `level` ignored: per level the
  * chosen FP64 operator variant, the measured time in microseconds of each of
  * the 6 variants (-1 where not timed), then the same for single precision).
+ * FD contexts: "diag", "matrix" (dense A_j, small problems only), "lambda_max",
+ * and the sparse A_j and interpolation P_j (level j+1 -> j; Sec. 3: bilinear
+ * interpolation, A_{j+1} = P_j^T A_j P_j) in CSR form as "csr_rowptr", "csr_col",
+ * "csr_val", "interp_rowptr", "interp_col", "interp_val" (indices as exact doubles).
  * Returns SEM_EINVAL if `n` does not equal the array size, with the size
  * written to *needed when it is not NULL. */
 sem_status sem_host_array(const sem_ctx *ctx, const char *what, int32_t level, double *out,
                           int64_t n, int64_t *needed);
+
+/* Change the Chebyshev kind and the (m, n) smoothing orders of a context after
+ * setup (Sec. 2: the (k,k) / (2k,0) and general m + n = 2k comparisons need many
+ * cycles on one hierarchy). Nothing set up depends on them: the hierarchy,
+ * lambda_max and the coarse solve are kept. Waits for the device, then drops the
+ * captured V-cycle graphs (captured again on next use). Same validation as setup
+ * (SEM_EINVAL); batched contexts are refused. */
+sem_status sem_set_smoothing(sem_ctx *ctx, int32_t smoother, int32_t pre_order, int32_t post_order);
 
 /* Batched problems: nsys (1..64) independent SEM systems on box meshes with their
  * own orders (orders[s] in 4..12, schedule N, floor(N/2), 1), all with the smoother,
  * cycle and Krylov settings of *opt and a mixed-precision cycle (FP32 arithmetic,
  * BF16 geometric factors, FP64 Krylov and coarse solve). lambda_max is estimated per
  * system and level. meshes, orders: host arrays of nsys entries. Same errors as
- * sem_setup_box, plus SEM_EINVAL for pre_order < 1 or a given lambda_max/schedule. */
+ * sem_setup_box, plus SEM_EINVAL for pre_order < 1, a given lambda_max/schedule, or
+ * an outer method other than SEM_PCG and SEM_FCG. */
 sem_status sem_setup_batched(int32_t nsys, const sem_box_mesh *meshes, const int32_t *orders,
                              const sem_options *opt, void *stream, sem_ctx **out);
 

@@ -97,21 +97,27 @@ class ApplyCounter:
         return self.A(x)
 
 
-def smooth(kind: str, k: int, A, Sinv: np.ndarray, lmax: float, b: np.ndarray,
+def smooth(kind: str, k: int, A, Sinv, lmax: float, b: np.ndarray,
            x0: np.ndarray | None = None) -> np.ndarray:
     """Order-k Chebyshev smoothing of A x = b starting from x0 (None means x0 = 0).
 
     From a zero initial guess the first residual is b itself, so the smoother
-    applies A k-1 times; from a nonzero guess it applies A k times.
+    applies A k-1 times; from a nonzero guess it applies A k times. Sinv is the
+    Jacobi diag(A)^{-1} as an array, or any linear smoother S as a callable r -> S r
+    (the Schwarz smoothers of Sec. 4.1 enter Algorithms 1 and 2 the same way).
     """
     if k <= 0:
         return np.zeros_like(b) if x0 is None else x0.copy()
+    if callable(Sinv):
+        S = Sinv
+    else:
+        S = lambda r: Sinv * r  # noqa: E731
     if kind in (CHEB1, CHEB1_OPT):
-        return _cheb1(k, A, Sinv, lmax, lambda_min_fraction(kind, k) * lmax, b, x0)
-    return _cheb4(k, A, Sinv, lmax, betas(kind, k), b, x0)
+        return _cheb1(k, A, S, lmax, lambda_min_fraction(kind, k) * lmax, b, x0)
+    return _cheb4(k, A, S, lmax, betas(kind, k), b, x0)
 
 
-def _cheb1(k, A, Sinv, lmax, lmin, b, x0):
+def _cheb1(k, A, S, lmax, lmin, b, x0):
     # Algorithm 1
     theta = 0.5 * (lmax + lmin)
     delta = 0.5 * (lmax - lmin)
@@ -119,21 +125,21 @@ def _cheb1(k, A, Sinv, lmax, lmin, b, x0):
     rho = 1.0 / sigma
     if x0 is None:
         x = np.zeros_like(b)
-        r = Sinv * b
+        r = S(b)
     else:
         x = x0.copy()
-        r = Sinv * (b - A(x))
+        r = S(b - A(x))
     d = r / theta
     for _ in range(1, k):
         x = x + d
-        r = r - Sinv * A(d)
+        r = r - S(A(d))
         rho_new = 1.0 / (2.0 * sigma - rho)
         d = rho_new * rho * d + (2.0 * rho_new / delta) * r
         rho = rho_new
     return x + d
 
 
-def _cheb4(k, A, Sinv, lmax, beta, b, x0):
+def _cheb4(k, A, S, lmax, beta, b, x0):
     # Algorithm 2
     if x0 is None:
         x = np.zeros_like(b)
@@ -141,9 +147,9 @@ def _cheb4(k, A, Sinv, lmax, beta, b, x0):
     else:
         x = x0.copy()
         r = b - A(x)
-    d = (4.0 / 3.0) * (1.0 / lmax) * (Sinv * r)
+    d = (4.0 / 3.0) * (1.0 / lmax) * S(r)
     for i in range(1, k):
         x = x + beta[i - 1] * d
         r = r - A(d)
-        d = ((2 * i - 1) / (2 * i + 3)) * d + ((8 * i + 4) / (2 * i + 3)) * (1.0 / lmax) * (Sinv * r)
+        d = ((2 * i - 1) / (2 * i + 3)) * d + ((8 * i + 4) / (2 * i + 3)) * (1.0 / lmax) * S(r)
     return x + beta[k - 1] * d

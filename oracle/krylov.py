@@ -140,3 +140,27 @@ def fgmres(A, b: np.ndarray, M, tol: float = 1e-8, restart: int = 30,
             return SolveResult(x, it, True, hist)
         if it >= maxit:
             return SolveResult(x, it, False, hist)
+
+
+def mg_solver(A, b: np.ndarray, M, tol: float = 1e-6, maxit: int = 500) -> SolveResult:
+    """Multigrid as the solver (paper, Sec. 3, where its observed convergence rate is set
+    against Lemma multilevel-poly-bound): the stationary iteration
+        x_i = x_{i-1} + M(b - A x_{i-1}),  x_0 = 0,
+    with M one V-cycle. The residual b - A x_i is formed from the iterate every time;
+    history holds ||b|| and ||b - A x_i||; stop when ||b - A x_i|| <= tol ||b||. The error
+    obeys e_i = (I - M A) e_{i-1}, so the average rate of eq. avg-convergence-rate tends
+    to the spectral radius of I - M A."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    bnorm = float(np.linalg.norm(b))
+    hist = [bnorm]
+    if bnorm == 0.0:
+        return SolveResult(x, 0, True, hist)
+    for it in range(1, maxit + 1):
+        x = x + M(r)
+        r = b - A(x)
+        rn = float(np.linalg.norm(r))
+        hist.append(rn)
+        if rn <= tol * bnorm:
+            return SolveResult(x, it, True, hist)
+    return SolveResult(x, maxit, False, hist)

@@ -27,7 +27,7 @@ from .lanczos import lambda_max_SA
 @dataclass
 class Level:
     A: Callable[[np.ndarray], np.ndarray]
-    Sinv: np.ndarray          # diag(A)^{-1}
+    Sinv: object              # diag(A)^{-1} (array), or a Schwarz smoother (callable)
     n: int
     lmax: float = 0.0         # lambda_max(S A)
     applies: int = 0          # operator applications performed on this level
@@ -83,21 +83,39 @@ def default_orders(N: int) -> list:
     return out
 
 
+def lambda_max_nonsym(A, S, n: int) -> float:
+    """Largest real part of the eigenvalues of S A for a non-symmetric smoother S (the
+    Schwarz smoothers; Sec. 4.1 notes that their spectra have small imaginary parts),
+    from the dense matrix S A."""
+    SA = np.column_stack([S(A(e)) for e in np.eye(n)])
+    return float(np.max(np.linalg.eigvals(SA).real))
+
+
 def sem_hierarchy(verts, N: int, kind: str, pre: int, post: int, orders=None,
-                  lmax=None, lanczos_seed: int = 7) -> Hierarchy:
+                  lmax=None, lanczos_seed: int = 7, schwarz: str | None = None) -> Hierarchy:
     """p-multigrid hierarchy with rediscretised SEM levels on the same vertices.
 
     lmax: optional list of lambda_max(S_j A_j) per smoothed level; otherwise
     each is estimated (dense eigensolve for small levels, Lanczos otherwise).
+    schwarz: None for Jacobi smoothing, "asm" or "ras" for the Schwarz smoothers of
+    Sec. 4.1 (eq. asm) inside the same Chebyshev algorithms; their lambda_max is
+    estimated densely (small problems only) unless given.
     """
+    from .schwarz import SchwarzLevel
     orders = default_orders(N) if orders is None else list(orders)
     boxes = [SemBox(verts, o) for o in orders]
     levels = []
     for j, bx in enumerate(boxes):
-        lev = Level(A=bx.apply, Sinv=1.0 / bx.diag(), n=bx.n)
-        if j < len(boxes) - 1:
-            lev.lmax = float(lmax[j]) if lmax is not None else lambda_max_SA(
-                bx.apply, lev.Sinv, bx.n, seed=lanczos_seed)
+        smoothed = j < len(boxes) - 1
+        S = SchwarzLevel(bx, schwarz) if (schwarz and smoothed) else 1.0 / bx.diag()
+        lev = Level(A=bx.apply, Sinv=S, n=bx.n)
+        if smoothed:
+            if lmax is not None:
+                lev.lmax = float(lmax[j])
+            elif schwarz:
+                lev.lmax = lambda_max_nonsym(bx.apply, S, bx.n)
+            else:
+                lev.lmax = lambda_max_SA(bx.apply, lev.Sinv, bx.n, seed=lanczos_seed)
         levels.append(lev)
     tr = [SemTransfer(boxes[j], boxes[j + 1]) for j in range(len(boxes) - 1)]
     coarse = exact_coarse(boxes[-1].assemble())

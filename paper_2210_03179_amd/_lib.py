@@ -17,7 +17,8 @@ STATUS_NAMES = {0: "SEM_OK", -1: "SEM_EINVAL", -2: "SEM_ENOMEM", -3: "SEM_EHIP",
                 -5: "SEM_ENOTCONV", -6: "SEM_EBREAKDOWN", -7: "SEM_ENAN", -8: "SEM_ENODEV"}
 SMOOTHERS = {"cheb1": 1, "cheb1opt": 2, "cheb4": 4, "cheb4opt": 5}
 PRECISIONS = {"fp64": 0, "mixed": 1}
-KRYLOV = {"pcg": 0, "fcg": 1, "gmres": 2}
+KRYLOV = {"pcg": 0, "fcg": 1, "gmres": 2, "mg": 3}
+SCHWARZ = {None: 0, "jacobi": 0, "asm": 1, "ras": 2}
 MAX_LEVELS = 8
 
 # exported entry points, as declared in include/semcheb.h
@@ -25,7 +26,7 @@ EXPORTS = (
     "sem_options_default", "sem_setup_box", "sem_setup_fd2d", "sem_sizes", "sem_level_info",
     "sem_apply_A", "sem_apply_local", "sem_vcycle", "sem_solve", "sem_coords", "sem_mass_apply", "sem_get_factors",
     "sem_set_factors", "sem_adjoint_contract", "sem_apply_counts", "sem_reset_counts",
-    "sem_host_array", "sem_beta_table", "sem_destroy", "sem_last_error", "sem_global_error",
+    "sem_host_array", "sem_set_smoothing", "sem_beta_table", "sem_destroy", "sem_last_error", "sem_global_error",
     "sem_setup_batched", "sem_batch_info", "sem_solve_batched",
 )
 
@@ -36,7 +37,7 @@ class SemOptions(C.Structure):
         ("smoother", C.c_int32), ("pre_order", C.c_int32), ("post_order", C.c_int32),
         ("precision", C.c_int32), ("krylov", C.c_int32), ("num_lambda_max", C.c_int32),
         ("lambda_max", C.c_double * MAX_LEVELS), ("lambda_scale", C.c_double), ("device", C.c_int32),
-        ("coarse_planes", C.c_int32), ("gmres_restart", C.c_int32),
+        ("coarse_planes", C.c_int32), ("gmres_restart", C.c_int32), ("schwarz", C.c_int32),
     ]
 
 
@@ -81,6 +82,7 @@ def load() -> C.CDLL:
         "sem_apply_counts": (i32, [vp, P(i64), i32]),
         "sem_reset_counts": (i32, [vp]),
         "sem_host_array": (i32, [vp, C.c_char_p, i32, P(dbl), i64, P(i64)]),
+        "sem_set_smoothing": (i32, [vp, i32, i32, i32]),
         "sem_beta_table": (i32, [i32, P(dbl)]),
         "sem_setup_batched": (i32, [i32, P(SemBoxMesh), P(i32), P(SemOptions), vp, P(vp)]),
         "sem_batch_info": (i32, [vp, P(i32), P(i64)]),
@@ -108,7 +110,7 @@ def check(status: int, ctx=None) -> int:
 
 def make_options(N=7, smoother="cheb4opt", pre=4, post=0, precision="fp64", krylov="fcg",
                  orders=None, lambda_max=None, lambda_scale=1.0, device=0, coarse_planes=0,
-                 restart=30) -> SemOptions:
+                 restart=30, schwarz=None) -> SemOptions:
     lib = load()
     o = SemOptions()
     lib.sem_options_default(C.byref(o))
@@ -129,4 +131,5 @@ def make_options(N=7, smoother="cheb4opt", pre=4, post=0, precision="fp64", kryl
     o.device = int(device)
     o.coarse_planes = int(coarse_planes)
     o.gmres_restart = int(restart)
+    o.schwarz = SCHWARZ[schwarz] if (schwarz is None or isinstance(schwarz, str)) else int(schwarz)
     return o

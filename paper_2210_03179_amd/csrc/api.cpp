@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -53,7 +54,11 @@ sem_status dalloc(sem_ctx *c, T **p, size_t count) {
 template <typename T>
 sem_status upload(sem_ctx *c, T **p, const T *src, size_t count, hipStream_t s) {
   TRY(dalloc(c, p, count));
-  if (count) HIPCHK(c, hipMemcpyAsync(*p, src, count * sizeof(T), hipMemcpyHostToDevice, s));
+  if (count) {
+    // src is often a temporary host vector: the copy must be complete before it is freed
+    HIPCHK(c, hipMemcpyAsync(*p, src, count * sizeof(T), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
   return SEM_OK;
 }
 
@@ -104,8 +109,12 @@ sem_status validate_common(const sem_options *o, std::string &err) {
     return SEM_EINVAL;
   }
   if (o->precision != SEM_FP64 && o->precision != SEM_MIXED) { err = "unknown precision"; return SEM_EINVAL; }
-  if (o->krylov != SEM_PCG && o->krylov != SEM_FCG && o->krylov != SEM_GMRES) {
+  if (o->krylov != SEM_PCG && o->krylov != SEM_FCG && o->krylov != SEM_GMRES && o->krylov != SEM_MG) {
     err = "unknown Krylov method";
+    return SEM_EINVAL;
+  }
+  if (o->schwarz != SEM_JACOBI && o->schwarz != SEM_ASM && o->schwarz != SEM_RAS) {
+    err = "unknown Schwarz smoother";
     return SEM_EINVAL;
   }
   if (o->gmres_restart < 0 || o->gmres_restart > kMaxRestart) {
@@ -128,6 +137,10 @@ template <> struct V<double> {
   static const double *inv(const Level &L) { return L.invdiag64; }
   static const double *J(const Level &L) { return L.J64; }
   static const double *val(const DevCsr &A) { return A.val64; }
+  static const double *swS(const Level &L) { return L.swS64; }
+  static const double *swD(const Level &L) { return L.swD64; }
+  static double *swY(Level &L) { return L.swY64; }
+  static double *swT(Level &L) { return L.swT64; }
 };
 template <> struct V<float> {
   static float *&b(Level &L) { return L.b32; }
@@ -138,6 +151,10 @@ template <> struct V<float> {
   static const float *inv(const Level &L) { return L.invdiag32; }
   static const float *J(const Level &L) { return L.J32; }
   static const float *val(const DevCsr &A) { return A.val32; }
+  static const float *swS(const Level &L) { return L.swS32; }
+  static const float *swD(const Level &L) { return L.swD32; }
+  static float *swY(Level &L) { return L.swY32; }
+  static float *swT(Level &L) { return L.swT32; }
 };
 
 // operator on level L: SEM -> element-local result in w (length E (N+1)^3),
@@ -149,11 +166,76 @@ void apply_level(Level &L, const T *u, T *w, hipStream_t s) {
   else launch_csr(L.A, V<T>::val(L.A), u, (const T *)nullptr, w, 0, s);
 }
 
+// Chebyshev smoothing with a Schwarz smoother S in place of diag(A)^{-1} (Sec. 4.1: the
+// Schwarz smoothers enter Algorithms 1 and 2 unchanged). S needs the whole input vector,
+// so every step is: the residual (or A d) as a global vector, the subdomain solves, and
+// the weighted node sum fused with the recurrence of the algorithm.
+template <typename T>
+void smooth_schwarz(const sem_ctx *c, Level &L, int k, bool zero_guess, hipStream_t s) {
+  T *b = V<T>::b(L), *x = V<T>::x(L), *r = V<T>::r(L), *d = V<T>::d(L), *w = V<T>::w(L), *tv = V<T>::swT(L);
+  const T *inv = V<T>::inv(L);
+  auto applyS = [&](const T *v, int gmode, double a, double bc, double cc, int flags) {
+    launch_schwarz_local<T>(L, v, V<T>::swS(L), V<T>::swD(L), V<T>::swY(L), s);
+    launch_schwarz_gather<T>(L, L.sw_kind, V<T>::swY(L), gmode, (T *)nullptr, r, d, x, a, bc, cc, flags, s);
+  };
+  // out = src - DSS(w) (src = b or r), written as a plain global vector
+  auto residual = [&](bool from_b, T *out) {
+    launch_cheb<T>(L, w, b, r, out, d, x, inv, 0.0, 0.0, 0.0,
+                   CHEB_R_ONLY | CHEB_SUB_AD | CHEB_D_INIT | CHEB_X_INIT | (from_b ? CHEB_R_FROM_B : 0), 4, s);
+  };
+  const double lmax = L.lmax;
+  const int kind = c->opt.smoother;
+  if (kind == SEM_CHEB4 || kind == SEM_CHEB4_OPT) {
+    const double *beta = kind == SEM_CHEB4_OPT ? beta_row(k) : nullptr;
+    auto B = [&](int i) { return beta ? beta[i - 1] : 1.0; };
+    const double c0 = (4.0 / 3.0) * (1.0 / lmax);
+    if (zero_guess) {
+      applyS(b, SWG_CHEB4, 0.0, c0, B(1), CHEB_D_INIT | CHEB_X_INIT);
+    } else {
+      apply_level<T>(L, x, w, s);
+      residual(true, r);
+      applyS(r, SWG_CHEB4, 0.0, c0, B(1), CHEB_D_INIT);
+    }
+    for (int i = 1; i < k; ++i) {
+      apply_level<T>(L, d, w, s);
+      residual(zero_guess && i == 1, r);
+      const double a = (2.0 * i - 1.0) / (2.0 * i + 3.0);
+      const double bc = ((8.0 * i + 4.0) / (2.0 * i + 3.0)) * (1.0 / lmax);
+      applyS(r, SWG_CHEB4, a, bc, B(i + 1), 0);
+    }
+  } else {
+    const double frac = kind == SEM_CHEB1 ? 0.1 : 1.69 / (std::pow((double)k, 1.68) + 2.11 * k + 1.98);
+    const double lmin = frac * lmax;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    // r holds the smoothed residual S (b - A x) of Algorithm 1
+    if (zero_guess) {
+      applyS(b, SWG_CHEB1, 0.0, 1.0 / theta, 1.0, CHEB_D_INIT | CHEB_X_INIT);
+    } else {
+      apply_level<T>(L, x, w, s);
+      residual(true, tv);
+      applyS(tv, SWG_CHEB1, 0.0, 1.0 / theta, 1.0, CHEB_D_INIT);
+    }
+    for (int i = 1; i < k; ++i) {
+      apply_level<T>(L, d, w, s);
+      launch_dss<T>(L, w, tv, s);  // A d
+      const double rho_new = 1.0 / (2.0 * sigma - rho);
+      applyS(tv, SWG_CHEB1, rho_new * rho, 2.0 * rho_new / delta, 1.0, 0);
+      rho = rho_new;
+    }
+  }
+}
+
 // Order-k Chebyshev smoothing of A x = b on level L (Algorithms 1 and 2).
 // zero_guess: x starts at 0 (k-1 applies); otherwise from the current x (k applies).
 template <typename T>
 void smooth(const sem_ctx *c, Level &L, int k, bool zero_guess, hipStream_t s) {
   if (k <= 0) return;
+  if (L.sw_kind) {
+    smooth_schwarz<T>(c, L, k, zero_guess, s);
+    return;
+  }
   T *b = V<T>::b(L), *x = V<T>::x(L), *r = V<T>::r(L), *d = V<T>::d(L), *w = V<T>::w(L);
   const T *inv = V<T>::inv(L);
   const double lmax = L.lmax;
@@ -561,6 +643,140 @@ sem_status autotune_operator(sem_ctx *c, hipStream_t s) {
   return st;
 }
 
+// Eigenvalues of a small real upper Hessenberg matrix H (row-major, m x m) by the shifted
+// QR algorithm in complex arithmetic (Wilkinson shifts, deflation at the bottom).
+std::vector<std::complex<double>> hessenberg_eigenvalues(const std::vector<double> &Hr, int m) {
+  using cd = std::complex<double>;
+  std::vector<cd> H(Hr.begin(), Hr.end());
+  std::vector<cd> ev;
+  int n = m;
+  auto at = [&](int i, int j) -> cd & { return H[(size_t)i * m + j]; };
+  for (int iter = 0; n > 0 && iter < 100 * m; ++iter) {
+    if (n == 1) {
+      ev.push_back(at(0, 0));
+      n = 0;
+      break;
+    }
+    const double sub = std::abs(at(n - 1, n - 2));
+    if (sub <= 1e-14 * (std::abs(at(n - 1, n - 1)) + std::abs(at(n - 2, n - 2)))) {
+      ev.push_back(at(n - 1, n - 1));
+      --n;
+      continue;
+    }
+    // Wilkinson shift: eigenvalue of the trailing 2x2 closer to its last diagonal entry
+    const cd a = at(n - 2, n - 2), bq = at(n - 2, n - 1), cq = at(n - 1, n - 2), d = at(n - 1, n - 1);
+    const cd tr = a + d, det = a * d - bq * cq;
+    const cd disc = std::sqrt(tr * tr - 4.0 * det);
+    const cd l1 = 0.5 * (tr + disc), l2 = 0.5 * (tr - disc);
+    const cd mu = std::abs(l1 - d) < std::abs(l2 - d) ? l1 : l2;
+    for (int i = 0; i < n; ++i) at(i, i) -= mu;
+    // QR by Givens rotations on the leading n x n block, then RQ
+    std::vector<cd> cs(n), sn(n);
+    for (int k = 0; k + 1 < n; ++k) {
+      const cd x = at(k, k), y = at(k + 1, k);
+      const double r = std::sqrt(std::norm(x) + std::norm(y));
+      const cd c = r > 0 ? x / r : cd(1.0), s2 = r > 0 ? y / r : cd(0.0);
+      cs[k] = c;
+      sn[k] = s2;
+      for (int j = k; j < n; ++j) {
+        const cd u = at(k, j), v = at(k + 1, j);
+        at(k, j) = std::conj(c) * u + std::conj(s2) * v;
+        at(k + 1, j) = -s2 * u + c * v;
+      }
+    }
+    for (int k = 0; k + 1 < n; ++k) {
+      for (int i = 0; i <= std::min(k + 2, n - 1); ++i) {
+        const cd u = at(i, k), v = at(i, k + 1);
+        at(i, k) = u * cs[k] + v * sn[k];
+        at(i, k + 1) = -u * std::conj(sn[k]) + v * std::conj(cs[k]);
+      }
+    }
+    for (int i = 0; i < n; ++i) at(i, i) += mu;
+  }
+  return ev;
+}
+
+// lambda_max(S A) of a Schwarz smoother: S A is not symmetric (Sec. 4.1 notes small
+// imaginary parts of its spectrum), so Lanczos does not apply and the power iteration
+// does not settle on a complex pair. An Arnoldi process of kArn steps (classical
+// Gram-Schmidt applied twice, from a counter-based random start) gives the Hessenberg
+// matrix whose eigenvalue with the largest real part is the estimate.
+sem_status arnoldi_schwarz(sem_ctx *c, int j, double &out, hipStream_t s) {
+  Level &L = c->levels[j];
+  const int64_t n = L.n, ld = (n + 31) / 32 * 32;
+  const int m = (int)std::min<int64_t>(30, n - 1);
+  const int nb = kReduceBlocks;
+  double *Vb = nullptr, *dh = nullptr, *hh = nullptr;
+  HIPCHK(c, hipMalloc((void **)&Vb, (size_t)(m + 1) * ld * sizeof(double)));
+  HIPCHK(c, hipMalloc((void **)&dh, 2 * (kMaxRestart + 1) * sizeof(double)));
+  HIPCHK(c, hipHostMalloc((void **)&hh, 2 * (kMaxRestart + 1) * sizeof(double), hipHostMallocDefault));
+  sem_status st = SEM_OK;
+  std::vector<double> H((size_t)m * m, 0.0);
+  int mm = m;
+  {
+    std::vector<double> h(n);
+    double nrm = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      h[i] = splitmix_uniform(0x5C4A2Full + j, (uint64_t)i);
+      nrm += h[i] * h[i];
+    }
+    nrm = std::sqrt(nrm);
+    for (int64_t i = 0; i < n; ++i) h[i] /= nrm;
+    if (hipMemcpy(Vb, h.data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) st = SEM_EHIP;
+  }
+  double *w = c->kw, *av = c->kz, *dnrm = dh + kMaxRestart, *dh2 = dh + kMaxRestart + 1;
+  for (int k = 0; k < m && st == SEM_OK; ++k) {
+    const double *vk = Vb + (int64_t)k * ld;
+    launch_ax(L, vk, L.w64, s);
+    launch_dss<double>(L, L.w64, av, s);
+    launch_schwarz_local<double>(L, av, L.swS64, L.swD64, L.swY64, s);
+    launch_schwarz_gather<double>(L, L.sw_kind, L.swY64, SWG_PLAIN, w, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, 0,
+                                  s);
+    // classical Gram-Schmidt twice
+    launch_multi_dot(n, k + 1, Vb, ld, w, c->partials, nb, s);
+    launch_finalize_many(nb, k + 1, c->partials, dh, s);
+    launch_multi_axpy(n, k + 1, Vb, ld, dh, -1.0, w, nullptr, nb, s);
+    launch_multi_dot(n, k + 1, Vb, ld, w, c->partials, nb, s);
+    launch_finalize_many(nb, k + 1, c->partials, dh2, s);
+    launch_multi_axpy(n, k + 1, Vb, ld, dh2, -1.0, w, c->partials, nb, s);
+    launch_finalize_many(nb, 1, c->partials, dnrm, s);
+    if (hipMemcpyAsync(hh, dh, 2 * (kMaxRestart + 1) * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      st = SEM_EHIP;
+      break;
+    }
+    for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = hh[i] + hh[kMaxRestart + 1 + i];
+    const double hn = std::sqrt(hh[kMaxRestart]);
+    if (!std::isfinite(hn)) {
+      c->err = "Arnoldi process for lambda_max(S A) failed";
+      st = SEM_EINVAL;
+      break;
+    }
+    if (k + 1 < m) H[(size_t)(k + 1) * m + k] = hn;
+    if (hn <= 1e-14) {  // invariant subspace found
+      mm = k + 1;
+      break;
+    }
+    launch_scale_inv_sqrt(n, w, dnrm, Vb + (int64_t)(k + 1) * ld, s);
+  }
+  if (st == SEM_OK) {
+    std::vector<double> Hm((size_t)mm * mm);
+    for (int i = 0; i < mm; ++i)
+      for (int k = 0; k < mm; ++k) Hm[(size_t)i * mm + k] = H[(size_t)i * m + k];
+    double best = 0.0;
+    for (const auto &ev : hessenberg_eigenvalues(Hm, mm)) best = std::max(best, ev.real());
+    out = best;
+    if (!(best > 0.0)) {
+      c->err = "Arnoldi process for lambda_max(S A) found no positive eigenvalue";
+      st = SEM_EINVAL;
+    }
+  }
+  hipFree(Vb);
+  hipFree(dh);
+  hipHostFree(hh);
+  return st;
+}
+
 sem_status estimate_lambdas(sem_ctx *c, hipStream_t s) {
   const int ns = (int)c->levels.size() - 1;  // smoothed levels
   for (int j = 0; j < ns; ++j) {
@@ -572,7 +788,8 @@ sem_status estimate_lambdas(sem_ctx *c, hipStream_t s) {
       c->levels[j].lmax = c->opt.lambda_max[j];
     } else if (!c->host_only) {
       double lm = 0;
-      TRY(lanczos(c, j, lm, s));
+      if (c->levels[j].sw_kind) TRY(arnoldi_schwarz(c, j, lm, s));
+      else TRY(lanczos(c, j, lm, s));
       const double sc = c->opt.lambda_scale > 0 ? c->opt.lambda_scale : 1.0;
       c->levels[j].lmax = lm * sc;
     }
@@ -624,6 +841,12 @@ sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipS
       if (orders[j] >= orders[j - 1] || orders[j] < 1) { c->err = "orders must decrease"; return SEM_EINVAL; }
     if (orders.back() != 1) { c->err = "the coarsest order must be 1"; return SEM_EINVAL; }
   }
+  if (opt->schwarz != SEM_JACOBI)
+    for (size_t j = 0; j + 1 < orders.size(); ++j)
+      if (orders[j] < 3) {
+        c->err = "the Schwarz smoothers need order >= 3 on every smoothed level";
+        return SEM_EINVAL;
+      }
   TRY(init_device(c, s));
   const int nl = (int)orders.size();
   c->host_levels.resize(nl);
@@ -706,6 +929,24 @@ sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipS
       // FP64 work vectors for Lanczos on coarser levels
       TRY(dalloc(c, &L.w64, L.L));
     }
+    if (opt->schwarz != SEM_JACOBI && !coarse) {
+      // fast-diagonalisation data of the Schwarz smoother (FP64 always: lambda_max estimate)
+      SchwarzHost sh;
+      build_schwarz(*mesh, h, sh);
+      const int64_t nb3 = (int64_t)sh.nb * sh.nb * sh.nb;
+      L.sw_kind = opt->schwarz;
+      TRY(upload(c, &L.swS64, sh.S.data(), sh.S.size(), s));
+      TRY(upload(c, &L.swD64, sh.Dinv.data(), sh.Dinv.size(), s));
+      TRY(dalloc(c, &L.swY64, (size_t)L.E * nb3));
+      TRY(dalloc(c, &L.swT64, (size_t)L.n));
+      if (mixed) {
+        std::vector<float> S32(sh.S.begin(), sh.S.end()), D32(sh.Dinv.begin(), sh.Dinv.end());
+        TRY(upload(c, &L.swS32, S32.data(), S32.size(), s));
+        TRY(upload(c, &L.swD32, D32.data(), D32.size(), s));
+        TRY(dalloc(c, &L.swY32, (size_t)L.E * nb3));
+        TRY(dalloc(c, &L.swT32, (size_t)L.n));
+      }
+    }
     HIPCHK(c, hipStreamSynchronize(s));
   }
   // coarse factors
@@ -769,6 +1010,7 @@ sem_status setup_fd_impl(int n, double Lx, double Ly, int factor, int coarsest_n
   c->device = opt->device < 0 ? 0 : opt->device;
   TRY(validate_common(opt, c->err));
   if (opt->precision != SEM_FP64) { c->err = "the FD problem runs in FP64"; return SEM_EINVAL; }
+  if (opt->schwarz != SEM_JACOBI) { c->err = "the Schwarz smoothers exist for SEM levels only"; return SEM_EINVAL; }
   if (n < 2 || n > 8192 || !(Lx > 0) || !(Ly > 0) || (factor != 2 && factor != 4 && factor != 8) ||
       coarsest_n < 2) {
     c->err = "invalid FD problem parameters";
@@ -886,6 +1128,7 @@ void sem_options_default(sem_options *o) {
   o->device = 0;
   o->coarse_planes = 0;
   o->gmres_restart = 30;
+  o->schwarz = SEM_JACOBI;
 }
 
 sem_status sem_setup_box(const sem_box_mesh *mesh, const sem_options *opt, void *stream, sem_ctx **out) {
@@ -1067,6 +1310,39 @@ sem_status gmres_solve(sem_ctx *c, const double *b, double *u, double *r, double
   }
 }
 
+// Multigrid as the solver (Sec. 3, where it is compared with the bounds of Lemma
+// multilevel-poly-bound): u_i = u_{i-1} + V(b - A u_{i-1}), one V-cycle and one fine
+// operator application per iteration. The residual is recomputed from u (not carried
+// by a recurrence), so stopping and `history` use the true residual; with a
+// single-precision cycle this is iterative refinement. r holds b - A u_0 on entry.
+sem_status mg_solve(sem_ctx *c, const double *b, double *u, double *r, double bnorm, double rtol, int maxit,
+                    int32_t *iters, double *relres, double *history, hipStream_t s) {
+  const int64_t n = c->levels[0].n;
+  const bool mixed = c->opt.precision == SEM_MIXED && c->kind == LVL_SEM;
+  float *r32 = mixed ? c->levels[0].b32 : nullptr;
+  double *z = c->kz, *w = c->kw;
+  for (int it = 1; it <= maxit; ++it) {
+    TRY(vcycle_replay(c, r, z, s, mixed && it > 1));
+    launch_axpby(n, 1.0, u, 1.0, z, u, s);
+    fine_apply(c, u, w, nullptr, s);
+    launch_resid_norm(n, b, w, r, c->partials, kReduceBlocks, r32, s);
+    launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_RR, FIN_NONE, s);
+    TRY(read_scalars(c, s));
+    const double rr = c->pinned[S_RR];
+    if (!std::isfinite(rr)) {
+      c->err = "non-finite residual in the multigrid iteration";
+      return SEM_ENAN;
+    }
+    const double rn = std::sqrt(rr);
+    if (history) history[it] = rn;
+    if (iters) *iters = it;
+    if (relres) *relres = rn / bnorm;
+    if (rn <= rtol * bnorm) return SEM_OK;
+  }
+  c->err = "maximum number of iterations reached";
+  return SEM_ENOTCONV;
+}
+
 sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_t maxit, int32_t *iters,
                      double *relres, double *history, void *stream) {
   TRY(need_device(c));
@@ -1104,6 +1380,12 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
   if (rn <= rtol * bnorm) {
     if (relres) *relres = rn / bnorm;
     return SEM_OK;
+  }
+  if (c->opt.krylov == SEM_MG) {
+    const sem_status st = mg_solve(c, b, u, r, bnorm, rtol, maxit, iters, relres, history, s);
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipGetLastError());
+    return st;
   }
   if (c->opt.krylov == SEM_GMRES) {
     const sem_status st = gmres_solve(c, b, u, r, c->pinned[S_RR], bnorm, rtol, maxit, iters, relres, history, s);
@@ -1262,12 +1544,41 @@ sem_status sem_host_array(const sem_ctx *c, const char *what, int32_t j, double 
       for (int64_t r = 0; r < A.nrows; ++r)
         for (int64_t p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p) tmp[r * A.ncols + A.col[p]] = A.val[p];
       src = &tmp;
+    } else if (w.rfind("csr_", 0) == 0 || w.rfind("interp_", 0) == 0) {
+      // sparse A_j ("csr_*") or P_j ("interp_*", level j+1 -> j): rowptr, col, val
+      const bool interp = w[0] == 'i';
+      if (interp && j + 1 >= (int32_t)c->fd_host.size()) return SEM_EINVAL;
+      const Csr &A = interp ? c->fd_host[j].P : c->fd_host[j].A;
+      const std::string part = w.substr(interp ? 7 : 4);
+      if (part == "rowptr") tmp.assign(A.rowptr.begin(), A.rowptr.end());
+      else if (part == "col") tmp.assign(A.col.begin(), A.col.end());
+      else if (part == "val") tmp = A.val;
+      else return SEM_EINVAL;
+      src = &tmp;
     }
   }
   if (!src) return SEM_EINVAL;
   if (needed) *needed = (int64_t)src->size();
   if (n != (int64_t)src->size() || (!out && n > 0)) return SEM_EINVAL;
   if (n) std::memcpy(out, src->data(), n * sizeof(double));
+  return SEM_OK;
+}
+
+sem_status sem_set_smoothing(sem_ctx *c, int32_t smoother, int32_t pre_order, int32_t post_order) {
+  if (!c) return SEM_EINVAL;
+  if (c->batch) { c->err = "batched contexts keep their setup smoothing"; return SEM_EINVAL; }
+  sem_options o = c->opt;
+  o.smoother = smoother;
+  o.pre_order = pre_order;
+  o.post_order = post_order;
+  TRY(validate_common(&o, c->err));
+  if (!c->host_only) {
+    // captured cycles hold the old coefficients: wait for any replay, then drop them
+    HIPCHK(c, hipDeviceSynchronize());
+    for (auto &g : c->graphs) hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+  }
+  c->opt = o;
   return SEM_OK;
 }
 

@@ -456,6 +456,145 @@ bool block_tridiag_factor(const Csr &A, const std::vector<int64_t> &start, Block
   return true;
 }
 
+// ------------------------------------------------------------------ Schwarz / FDM
+namespace {
+// Symmetric eigen-decomposition C = V diag(lam) V^T by cyclic Jacobi rotations (n <= 16).
+void jacobi_eig(std::vector<double> &C, int n, std::vector<double> &V, std::vector<double> &lam) {
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+  double scale = 0.0;
+  for (double v : C) scale = std::max(scale, std::fabs(v));
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off = std::max(off, std::fabs(C[p * n + q]));
+    if (off <= 1e-15 * scale) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = C[p * n + q];
+        if (std::fabs(apq) <= 1e-300) continue;
+        const double theta = (C[q * n + q] - C[p * n + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double ckp = C[k * n + p], ckq = C[k * n + q];
+          C[k * n + p] = c * ckp - sn * ckq;
+          C[k * n + q] = sn * ckp + c * ckq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double cpk = C[p * n + k], cqk = C[q * n + k];
+          C[p * n + k] = c * cpk - sn * cqk;
+          C[q * n + k] = sn * cpk + c * cqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - sn * vkq;
+          V[k * n + q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  lam.resize(n);
+  for (int i = 0; i < n; ++i) lam[i] = C[i * n + i];
+}
+
+// 1D stiffness/mass of the three-element mesh (left, element, right) restricted to the
+// N+3 subdomain nodes [left N-1, 0..N, right 1]; absent unknowns become identity rows.
+void extended_1d(const Gll &g, double hl, double h, double hr, bool has_l, bool has_r, std::vector<double> &A,
+                 std::vector<double> &B) {
+  const int N = g.N, n1 = N + 1, n = 3 * N + 1, nb = N + 3;
+  std::vector<double> Ar((size_t)n1 * n1, 0.0);  // D^T W D
+  for (int i = 0; i < n1; ++i)
+    for (int j = 0; j < n1; ++j) {
+      double acc = 0.0;
+      for (int q = 0; q < n1; ++q) acc += g.D[q * n1 + i] * g.w[q] * g.D[q * n1 + j];
+      Ar[i * n1 + j] = acc;
+    }
+  std::vector<double> K((size_t)n * n, 0.0), M(n, 0.0);
+  const double hs[3] = {hl, h, hr};
+  for (int e = 0; e < 3; ++e)
+    for (int i = 0; i < n1; ++i) {
+      M[e * N + i] += 0.5 * hs[e] * g.w[i];
+      for (int j = 0; j < n1; ++j) K[(size_t)(e * N + i) * n + e * N + j] += (2.0 / hs[e]) * Ar[i * n1 + j];
+    }
+  A.assign((size_t)nb * nb, 0.0);
+  B.assign((size_t)nb * nb, 0.0);
+  for (int i = 0; i < nb; ++i) {
+    B[i * nb + i] = M[N - 1 + i];
+    for (int j = 0; j < nb; ++j) A[i * nb + j] = K[(size_t)(N - 1 + i) * n + N - 1 + j];
+  }
+  std::vector<int> absent;
+  if (!has_l) absent.insert(absent.end(), {0, 1});
+  if (!has_r) absent.insert(absent.end(), {N + 1, N + 2});
+  for (int i : absent) {
+    for (int j = 0; j < nb; ++j) A[i * nb + j] = A[j * nb + i] = B[i * nb + j] = B[j * nb + i] = 0.0;
+    A[i * nb + i] = B[i * nb + i] = 1.0;
+  }
+}
+}  // namespace
+
+void build_schwarz(const sem_box_mesh &mesh, const BoxLevelHost &lev, SchwarzHost &out) {
+  const int N = lev.N, nb = N + 3, nb3 = nb * nb * nb;
+  const int mx = mesh.nex, my = mesh.ney, mz = mesh.nez;
+  out.nb = nb;
+  out.S.assign((size_t)lev.E * 3 * nb * nb, 0.0);
+  out.Dinv.assign((size_t)lev.E * nb3, 0.0);
+  auto vtx = [&](int ix, int iy, int iz, int d) {
+    return mesh.vertex_xyz[(((size_t)iz * (my + 1) + iy) * (mx + 1) + ix) * 3 + d];
+  };
+  // mean edge length of every element along each axis (box approximation)
+  std::vector<double> len((size_t)lev.E * 3);
+  for (int64_t e = 0; e < lev.E; ++e) {
+    const int ex = (int)(e % mx), ey = (int)((e / mx) % my), ez = (int)(e / ((int64_t)mx * my));
+    for (int a = 0; a < 3; ++a) {
+      double acc = 0.0;
+      for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) {
+          int c0[3], c1[3];
+          // corner offsets: axis a goes 0 -> 1, the two other axes take (u, v)
+          const int o[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+          c0[a] = 0;
+          c1[a] = 1;
+          c0[o[a][0]] = c1[o[a][0]] = u;
+          c0[o[a][1]] = c1[o[a][1]] = v;
+          double d2 = 0.0;
+          for (int d = 0; d < 3; ++d) {
+            const double t = vtx(ex + c1[0], ey + c1[1], ez + c1[2], d) - vtx(ex + c0[0], ey + c0[1], ez + c0[2], d);
+            d2 += t * t;
+          }
+          acc += std::sqrt(d2);
+        }
+      len[e * 3 + a] = 0.25 * acc;
+    }
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < lev.E; ++e) {
+    const int idx[3] = {(int)(e % mx), (int)((e / mx) % my), (int)(e / ((int64_t)mx * my))};
+    const int cnt[3] = {mx, my, mz};
+    const int64_t stride[3] = {1, mx, (int64_t)mx * my};
+    std::vector<double> lam[3];
+    for (int a = 0; a < 3; ++a) {
+      const bool has_l = idx[a] > 0, has_r = idx[a] < cnt[a] - 1;
+      const double h = len[e * 3 + a];
+      const double hl = has_l ? len[(e - stride[a]) * 3 + a] : h;
+      const double hr = has_r ? len[(e + stride[a]) * 3 + a] : h;
+      std::vector<double> A, B, V;
+      extended_1d(lev.gll, hl, h, hr, has_l, has_r, A, B);
+      // A s = lambda B s with B diagonal: C = B^-1/2 A B^-1/2 = V Lam V^T, S = B^-1/2 V
+      std::vector<double> C((size_t)nb * nb);
+      for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < nb; ++j) C[i * nb + j] = A[i * nb + j] / std::sqrt(B[i * nb + i] * B[j * nb + j]);
+      jacobi_eig(C, nb, V, lam[a]);
+      double *S = &out.S[((size_t)e * 3 + a) * nb * nb];
+      for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < nb; ++j) S[i * nb + j] = V[i * nb + j] / std::sqrt(B[i * nb + i]);
+    }
+    double *Di = &out.Dinv[(size_t)e * nb3];
+    for (int k = 0; k < nb; ++k)
+      for (int j = 0; j < nb; ++j)
+        for (int i = 0; i < nb; ++i) Di[(k * nb + j) * nb + i] = 1.0 / (lam[0][i] + lam[1][j] + lam[2][k]);
+  }
+}
+
 // ------------------------------------------------------------------ FD hierarchy
 static Csr csr_from_map(int64_t nrows, int64_t ncols, std::vector<std::map<int32_t, double>> &rows) {
   Csr A;

@@ -45,6 +45,16 @@ struct Csr {
 };
 Csr assemble_q1(const BoxLevelHost &lev);
 
+// Schwarz smoothers with fast-diagonalisation local solves (Sec. 4.1): per element the
+// extended-box eigenvectors S_x, S_y, S_z ([e][axis][nb][nb], row-major, nb = N+3) and
+// 1/D ([e][k][j][i]) of Abar = Bz x By x Ax + Bz x Ay x Bx + Az x By x Bx.
+struct SchwarzHost {
+  int nb = 0;
+  std::vector<double> S;     // E * 3 * nb * nb
+  std::vector<double> Dinv;  // E * nb^3
+};
+void build_schwarz(const sem_box_mesh &mesh, const BoxLevelHost &lev, SchwarzHost &out);
+
 // Block-tridiagonal factorisation of an SPD matrix whose unknowns are grouped in
 // contiguous blocks with couplings only between neighbouring blocks.
 struct BlockTri {
@@ -110,6 +120,11 @@ struct Level {
   double *b64 = nullptr, *x64 = nullptr, *r64 = nullptr, *d64 = nullptr, *w64 = nullptr;
   float *b32 = nullptr, *x32 = nullptr, *r32 = nullptr, *d32 = nullptr, *w32 = nullptr;
   int64_t applies = 0;
+  // Schwarz smoother (0: Jacobi, SW_ASM, SW_RAS): FDM eigenvectors [e][3][nb][nb], 1/D
+  // [e][nb^3], subdomain results [e][nb^3] and a global work vector, per precision
+  int sw_kind = 0;
+  double *swS64 = nullptr, *swD64 = nullptr, *swY64 = nullptr, *swT64 = nullptr;
+  float *swS32 = nullptr, *swD32 = nullptr, *swY32 = nullptr, *swT32 = nullptr;
   // operator kernel variant per precision, chosen at setup by timing (kAxVariants)
   int ax_variant64 = 0, ax_variant32 = 0;
   float ax_time64_us[6] = {}, ax_time32_us[6] = {};  // kAxVariants

@@ -16,7 +16,16 @@ enum {
   CHEB_SUB_AD = 4,    // subtract A d (mode 1: diag^{-1} A d)
   CHEB_WRITE_R = 8,   // store the updated residual
   CHEB_D_INIT = 16,   // previous direction is zero
-  CHEB_X_INIT = 32    // previous iterate is zero
+  CHEB_X_INIT = 32,   // previous iterate is zero
+  CHEB_R_ONLY = 64    // only form and store the residual (a non-diagonal smoother follows)
+};
+// Schwarz smoother modes of the fused gather (Chebyshev recurrences of Algorithms 1 and 2
+// with z = S v in place of diag(A)^{-1} r)
+enum { SW_ASM = 1, SW_RAS = 2 };
+enum {
+  SWG_PLAIN = 0,  // out = z
+  SWG_CHEB4 = 1,  // d = a d + bc z, x += c d (Algorithm 2)
+  SWG_CHEB1 = 2   // r = r - z (or z with CHEB_D_INIT), d = a d + bc r, x += c d (Algorithm 1)
 };
 
 // device scalar slots of the Krylov method
@@ -67,6 +76,8 @@ void launch_dots(int64_t n, int nd, const T *x0, const T *y0, const T *x1, const
                  const T *y2, double *partials, int nblocks, hipStream_t s);
 void launch_finalize(int nblocks, int nd, const double *partials, double *scal, int slot, int op,
                      hipStream_t s);
+void launch_resid_norm(int64_t n, const double *b, const double *w, double *r, double *partials, int nblocks,
+                       float *r32, hipStream_t s);
 void launch_update_xr(int64_t n, const double *scal, double *x, const double *p, const double *r,
                       const double *w, double *rnew, double *partials, int nblocks, float *r32, hipStream_t s);
 void launch_update_p(int64_t n, const double *scal, const double *z, double *p, hipStream_t s);
@@ -88,6 +99,17 @@ void launch_multi_axpy(int64_t n, int k, const double *V, int64_t ldv, const dou
                        double *partials, int nblocks, hipStream_t s);
 // y = x / sqrt(*nrm2)
 void launch_scale_inv_sqrt(int64_t n, const double *x, const double *nrm2, double *y, hipStream_t s);
+
+// Schwarz smoother (Sec. 4.1) of a SEM level with element order N >= 3: y_e = Abar_e^{-1} R_e v
+// for every element (fast diagonalisation with Sm = [e][axis][nb][nb] eigenvectors and
+// Dinv = [e][nb^3], nb = N+3), then the node-wise weighted sum of the subdomain values
+// fused with the Chebyshev update selected by gmode (SWG_*) and flags (CHEB_D_INIT,
+// CHEB_X_INIT). z (optional) receives the smoothed value itself for SWG_PLAIN.
+template <typename T>
+void launch_schwarz_local(const Level &L, const T *v, const T *Sm, const T *Dinv, T *ye, hipStream_t s);
+template <typename T>
+void launch_schwarz_gather(const Level &L, int kind, const T *ye, int gmode, T *z, T *r, T *d, T *x, double a,
+                           double bc, double c, int flags, hipStream_t s);
 
 // out[0..n) = 0 with a kernel (no memset node when the caller captures a graph)
 template <typename T>

@@ -108,7 +108,7 @@ __device__ __forceinline__ void cheb_body(unsigned blk, const Box &b, int64_t n,
   for (int q = 0; q < VEC; ++q) {
     const int64_t g = g0 + 64 * q;
     const bool ok = g < n;
-    sv[q] = ok ? invdiag[g] : T(0);
+    sv[q] = (ok && !(flags & CHEB_R_ONLY)) ? invdiag[g] : T(0);
     rr[q] = ok ? rsrc[g] : T(0);
     dd[q] = (ok && !(flags & CHEB_D_INIT)) ? d[g] : T(0);
     xx[q] = (ok && !(flags & CHEB_X_INIT)) ? x[g] : T(0);
@@ -121,6 +121,14 @@ __device__ __forceinline__ void cheb_body(unsigned blk, const Box &b, int64_t n,
       if (g0 + 64 * q < n) ad[q] = dss_ijk(wsrc, b, cc);
       if (q + 1 < VEC) ijk_advance(b, cc, 64);
     }
+  }
+  if (flags & CHEB_R_ONLY) {  // residual only: r_out = rr - Ad
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      const int64_t g = g0 + 64 * q;
+      if (g < n) r_out[g] = (flags & CHEB_SUB_AD) ? rr[q] - ad[q] : rr[q];
+    }
+    return;
   }
 #pragma unroll
   for (int q = 0; q < VEC; ++q) {
@@ -421,6 +429,163 @@ prolong_rows_kernel(Box fb, Box cb, const T *__restrict__ xc, const T *__restric
   }
 }
 
+// ------------------------------------------------------------------ Schwarz smoother
+// One block per element; thread (j, i) owns the column (i, j, :) of the extended
+// (N+3)^3 tile. The x and y contractions pass through one LDS plane, the z contraction and
+// the 1/D scaling stay in registers (fixed indices), the element's three eigenvector
+// matrices are staged in LDS.
+template <int N>
+struct SwShape {
+  static constexpr int nb = N + 3, nb2 = nb * nb, nb3 = nb2 * nb;
+  static constexpr int block = (nb2 + 63) / 64 * 64;
+};
+
+template <int N, typename T>
+__global__ void __launch_bounds__(SwShape<N>::block)
+schwarz_local_kernel(Box b, int64_t E, const T *__restrict__ v, const T *__restrict__ Sm,
+                     const T *__restrict__ Dinv, T *__restrict__ ye) {
+  using S = SwShape<N>;
+  constexpr int nb = S::nb, nb2 = S::nb2, nb3 = S::nb3;
+  __shared__ T sS[3 * nb2];
+  __shared__ T pl[nb2];
+  const int64_t e = xcd_block(blockIdx.x, gridDim.x);
+  if (e >= E) return;  // whole block
+  const int t = threadIdx.x;
+  const bool act = t < nb2;
+  const int i = act ? t % nb : 0, j = act ? t / nb : 0;
+  for (int q = t; q < 3 * nb2; q += S::block) sS[q] = Sm[e * 3 * nb2 + q];
+  const Exyz ec = elem_xyz(b, e);
+  const int I = ec.x * N - 1 + i, J = ec.y * N - 1 + j;
+  const bool inIJ = act && I >= 1 && I <= b.nx && J >= 1 && J <= b.ny;
+  const int64_t gIJ = (int64_t)(I - 1) + (int64_t)b.nx * (J - 1), plane = (int64_t)b.nx * b.ny;
+  T col[nb];
+#pragma unroll
+  for (int k = 0; k < nb; ++k) {
+    const int K = ec.z * N - 1 + k;
+    const bool ok = inIJ && K >= 1 && K <= b.nz;
+    const T val = v[ok ? gIJ + plane * (K - 1) : 0];
+    col[k] = ok ? val : T(0);
+  }
+  __syncthreads();
+  const T *Sx = sS, *Sy = sS + nb2, *Sz = sS + 2 * nb2;
+  // forward: (S_y^T S_x^T) per plane
+#pragma unroll
+  for (int k = 0; k < nb; ++k) {
+    if (act) pl[j * nb + i] = col[k];
+    __syncthreads();
+    T tx = 0;
+#pragma unroll
+    for (int l = 0; l < nb; ++l) tx += Sx[l * nb + i] * pl[j * nb + l];
+    __syncthreads();
+    if (act) pl[j * nb + i] = tx;
+    __syncthreads();
+    T ty = 0;
+#pragma unroll
+    for (int l = 0; l < nb; ++l) ty += Sy[l * nb + j] * pl[l * nb + i];
+    col[k] = ty;
+    __syncthreads();
+  }
+  // S_z^T, 1/D, S_z along the column
+  T u[nb];
+#pragma unroll
+  for (int c = 0; c < nb; ++c) {
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < nb; ++k) acc += Sz[k * nb + c] * col[k];
+    u[c] = act ? acc * Dinv[e * nb3 + (c * nb + j) * nb + i] : T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < nb; ++k) {
+    T acc = 0;
+#pragma unroll
+    for (int c = 0; c < nb; ++c) acc += Sz[k * nb + c] * u[c];
+    col[k] = acc;
+  }
+  // backward: S_y then S_x per plane
+  T *out = ye + e * nb3;
+#pragma unroll
+  for (int k = 0; k < nb; ++k) {
+    if (act) pl[j * nb + i] = col[k];
+    __syncthreads();
+    T ty = 0;
+#pragma unroll
+    for (int l = 0; l < nb; ++l) ty += Sy[j * nb + l] * pl[l * nb + i];
+    __syncthreads();
+    if (act) pl[j * nb + i] = ty;
+    __syncthreads();
+    T tx = 0;
+#pragma unroll
+    for (int l = 0; l < nb; ++l) tx += Sx[i * nb + l] * pl[j * nb + l];
+    if (act) out[(k * nb + j) * nb + i] = tx;
+    __syncthreads();
+  }
+}
+
+// Subdomains containing lattice coordinate I along one axis (N >= 3): at most two, as
+// (element, subdomain-local index) pairs; ASM takes every subdomain, RAS only the
+// element's own nodes (local 1 .. N+1).
+__device__ __forceinline__ int sw_axis(int I, int N, const FastDiv &fN, int nelem, bool ras, int *el, int *loc) {
+  const int q = fdiv(fN, I), r = I - q * N;
+  int cnt = 0;
+  auto add = [&](int e, int l) {
+    if (e >= 0 && e < nelem) {
+      el[cnt] = e;
+      loc[cnt] = l;
+      ++cnt;
+    }
+  };
+  add(q, r + 1);  // the element whose own nodes hold I (for r == 0: its local node 0)
+  if (r == 0) add(q - 1, N + 1);
+  if (!ras) {
+    if (r == 1) add(q - 1, N + 2);
+    if (r == N - 1) add(q + 1, 0);
+  }
+  return cnt;
+}
+
+template <typename T, int VEC>
+__global__ void __launch_bounds__(256)
+schwarz_gather_kernel(Box b, int64_t n, int ras, const T *__restrict__ ye, int gmode, T *__restrict__ z,
+                      T *__restrict__ rv, T *__restrict__ d, T *__restrict__ x, T a, T bc, T c, int flags) {
+  const int nb = b.N + 3;
+  const int64_t nb3 = (int64_t)nb * nb * nb;
+  const int64_t g0 = strided_first<VEC>(blockIdx.x);
+  if (g0 >= n) return;
+  Ijk cc = ijk_of(b, g0);
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) {
+    const int64_t g = g0 + 64 * q;
+    if (g < n) {
+      int ex[2], lx[2], ey[2], ly[2], ez[2], lz[2];
+      const int cx = sw_axis(cc.I, b.N, b.fN, b.nex, ras, ex, lx);
+      const int cy = sw_axis(cc.J, b.N, b.fN, b.ney, ras, ey, ly);
+      const int cz = sw_axis(cc.K, b.N, b.fN, b.nez, ras, ez, lz);
+      T acc = 0;
+      for (int w = 0; w < cz; ++w)
+        for (int v2 = 0; v2 < cy; ++v2)
+          for (int u2 = 0; u2 < cx; ++u2) {
+            const int64_t e = ex[u2] + (int64_t)b.nex * (ey[v2] + (int64_t)b.ney * ez[w]);
+            acc += ye[e * nb3 + ((int64_t)lz[w] * nb + ly[v2]) * nb + lx[u2]];
+          }
+      const T zv = acc / (T)(cx * cy * cz);
+      if (gmode == SWG_PLAIN) {
+        z[g] = zv;
+      } else if (gmode == SWG_CHEB4) {
+        const T dn = ((flags & CHEB_D_INIT) ? T(0) : a * d[g]) + bc * zv;
+        d[g] = dn;
+        x[g] = ((flags & CHEB_X_INIT) ? T(0) : x[g]) + c * dn;
+      } else {
+        const T rn = (flags & CHEB_D_INIT) ? zv : rv[g] - zv;
+        rv[g] = rn;
+        const T dn = ((flags & CHEB_D_INIT) ? T(0) : a * d[g]) + bc * rn;
+        d[g] = dn;
+        x[g] = ((flags & CHEB_X_INIT) ? T(0) : x[g]) + c * dn;
+      }
+    }
+    if (q + 1 < VEC) ijk_advance(b, cc, 64);
+  }
+}
+
 // ------------------------------------------------------------------ sparse / dense
 // y = A x (mode 0), y = b - A x (mode 1), y += A x (mode 2); one thread per row.
 template <typename T>
@@ -661,6 +826,23 @@ update_xr_kernel(int64_t n, const double *__restrict__ scal, double *__restrict_
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// r = b - w with the partial ||r||^2 and (optional) the single-precision copy of r:
+// the residual of multigrid used as the solver, where w = A u.
+__global__ void __launch_bounds__(256)
+resid_norm_kernel(int64_t n, const double *__restrict__ b, const double *__restrict__ w, double *__restrict__ r,
+                  double *__restrict__ partials, float *__restrict__ r32) {
+  __shared__ double sm[4];
+  double acc = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+    const double rv = b[g] - w[g];
+    r[g] = rv;
+    if (r32) r32[g] = (float)rv;
+    acc += rv * rv;
+  }
+  const double t = block_sum(acc, sm);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
 // p = z + beta p, beta = scal[BETA]
 __global__ void update_p_kernel(int64_t n, const double *__restrict__ scal, const double *__restrict__ z,
                                 double *__restrict__ p) {
@@ -789,7 +971,8 @@ __global__ void __launch_bounds__(AxShape<N>::block)
 b_ax32_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, int level, int src) {
   SEMCHEB_BATCH_SYS
   const BatchLevelDev &L = S.lev[level];
-  ax_body<N, float, uint16_t>(blk, lbox(L), L.E, src == 0 ? L.d : L.x, L.G, L.D, L.w);
+  // BF16 factors staged in LDS by DMA (the variant the single-system autotuner prefers)
+  ax_body_dma<N>(blk, lbox(L), L.E, src == 0 ? L.d : L.x, L.G, L.D, L.w);
 }
 
 // FP64 operator on the finest level applied to the Krylov direction p
@@ -1197,6 +1380,11 @@ void launch_update_xr(int64_t n, const double *scal, double *x, const double *p,
   hipLaunchKernelGGL(update_xr_kernel, dim3(nblocks), dim3(256), 0, s, n, scal, x, p, r, w, rnew, partials, r32);
 }
 
+void launch_resid_norm(int64_t n, const double *b, const double *w, double *r, double *partials, int nblocks,
+                       float *r32, hipStream_t s) {
+  hipLaunchKernelGGL(resid_norm_kernel, dim3(nblocks), dim3(256), 0, s, n, b, w, r, partials, r32);
+}
+
 void launch_update_p(int64_t n, const double *scal, const double *z, double *p, hipStream_t s) {
   hipLaunchKernelGGL(update_p_kernel, dim3(nblk(n)), dim3(256), 0, s, n, scal, z, p);
 }
@@ -1226,6 +1414,39 @@ void launch_multi_axpy(int64_t n, int k, const double *V, int64_t ldv, const dou
 void launch_scale_inv_sqrt(int64_t n, const double *x, const double *nrm2, double *y, hipStream_t s) {
   hipLaunchKernelGGL(scale_inv_sqrt_kernel, dim3(nblk(n)), dim3(256), 0, s, n, x, nrm2, y);
 }
+
+template <int N, typename T>
+void launch_schwarz_local_n(const Level &L, const T *v, const T *Sm, const T *Dinv, T *ye, hipStream_t s) {
+  hipLaunchKernelGGL((schwarz_local_kernel<N, T>), dim3((unsigned)L.E), dim3(SwShape<N>::block), 0, s, mkbox(L),
+                     L.E, v, Sm, Dinv, ye);
+}
+template <typename T>
+void launch_schwarz_local(const Level &L, const T *v, const T *Sm, const T *Dinv, T *ye, hipStream_t s) {
+  switch (L.N) {
+#define SEMCHEB_SW_CASE(n) \
+  case n: launch_schwarz_local_n<n, T>(L, v, Sm, Dinv, ye, s); break;
+    SEMCHEB_SW_CASE(3) SEMCHEB_SW_CASE(4) SEMCHEB_SW_CASE(5) SEMCHEB_SW_CASE(6) SEMCHEB_SW_CASE(7)
+    SEMCHEB_SW_CASE(8) SEMCHEB_SW_CASE(9) SEMCHEB_SW_CASE(10) SEMCHEB_SW_CASE(11) SEMCHEB_SW_CASE(12)
+#undef SEMCHEB_SW_CASE
+    default: break;
+  }
+}
+template void launch_schwarz_local<double>(const Level &, const double *, const double *, const double *, double *,
+                                           hipStream_t);
+template void launch_schwarz_local<float>(const Level &, const float *, const float *, const float *, float *,
+                                          hipStream_t);
+
+template <typename T>
+void launch_schwarz_gather(const Level &L, int kind, const T *ye, int gmode, T *z, T *r, T *d, T *x, double a,
+                           double bc, double c, int flags, hipStream_t s) {
+  constexpr int VEC = 16 / sizeof(T);
+  hipLaunchKernelGGL((schwarz_gather_kernel<T, VEC>), dim3(nblk((L.n + VEC - 1) / VEC)), dim3(256), 0, s, mkbox(L),
+                     L.n, kind == SW_RAS ? 1 : 0, ye, gmode, z, r, d, x, (T)a, (T)bc, (T)c, flags);
+}
+template void launch_schwarz_gather<double>(const Level &, int, const double *, int, double *, double *, double *,
+                                            double *, double, double, double, int, hipStream_t);
+template void launch_schwarz_gather<float>(const Level &, int, const float *, int, float *, float *, float *,
+                                           float *, double, double, double, int, hipStream_t);
 
 template <typename T>
 void launch_zero(int64_t n, T *out, hipStream_t s) {

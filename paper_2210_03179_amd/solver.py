@@ -93,6 +93,11 @@ class _Base:
                                          out.ctypes.data_as(C.POINTER(C.c_double)), out.size, None), self._ctx)
         return out
 
+    def set_smoothing(self, smoother, pre: int, post: int):
+        """Change the Chebyshev kind and the (m, n) orders; hierarchy and lambda_max are kept."""
+        kind = L.SMOOTHERS[smoother] if isinstance(smoother, str) else int(smoother)
+        L.check(self._lib.sem_set_smoothing(self._ctx, kind, int(pre), int(post)), self._ctx)
+
     def apply_counts(self):
         nl = self.num_levels
         buf = (C.c_int64 * nl)()
@@ -132,11 +137,13 @@ class SemSolver(_Base):
     """Chebyshev-smoothed p-multigrid PCG for the SEM Poisson problem on a box mesh.
 
     verts: (nez+1, ney+1, nex+1, 3) float64 vertex coordinates (x fastest).
+    schwarz: None (Jacobi), "asm" or "ras": the basic smoother inside the Chebyshev algorithms.
+    krylov: "pcg", "fcg", "gmres" (GMRES(restart)) or "mg" (multigrid as the solver).
     """
 
     def __init__(self, verts, N=7, smoother="cheb4opt", pre=4, post=0, precision="fp64",
                  krylov="fcg", orders=None, lambda_max=None, lambda_scale=1.0, device=0,
-                 coarse_planes=0, restart=30):
+                 coarse_planes=0, restart=30, schwarz=None):
         super().__init__()
         verts = np.ascontiguousarray(np.asarray(verts, dtype=np.float64))
         if verts.ndim != 4 or verts.shape[3] != 3:
@@ -145,7 +152,7 @@ class SemSolver(_Base):
         mesh = L.SemBoxMesh(verts.shape[2] - 1, verts.shape[1] - 1, verts.shape[0] - 1,
                             verts.ctypes.data_as(C.POINTER(C.c_double)))
         opt = L.make_options(N, smoother, pre, post, precision, krylov, orders, lambda_max,
-                             lambda_scale, device, coarse_planes, restart)
+                             lambda_scale, device, coarse_planes, restart, schwarz)
         ctx = C.c_void_p()
         stream = _stream() if device >= 0 else C.c_void_p(0)
         L.check(self._lib.sem_setup_box(C.byref(mesh), C.byref(opt), stream, C.byref(ctx)))
@@ -205,7 +212,10 @@ class SemSolver(_Base):
 
 
 class FdSolver(_Base):
-    """2D finite-difference Poisson with Galerkin geometric multigrid (the paper's Sec. 3 problem)."""
+    """2D finite-difference Poisson with Galerkin geometric multigrid (the paper's Sec. 3 problem).
+
+    krylov: "pcg", "fcg", "gmres" (GMRES(restart)) or "mg" (multigrid as the solver).
+    """
 
     def __init__(self, n=64, Lx=1.0, Ly=1.0, factor=2, coarsest_n=8, smoother="cheb4", pre=4, post=0,
                  krylov="fcg", lambda_max=None, lambda_scale=1.0, device=0, restart=30):
@@ -217,6 +227,12 @@ class FdSolver(_Base):
         L.check(self._lib.sem_setup_fd2d(int(n), float(Lx), float(Ly), int(factor), int(coarsest_n),
                                          C.byref(opt), stream, C.byref(ctx)))
         self._ctx = ctx
+
+    def sparse(self, what: str, level: int):
+        """(rowptr, col, val) of A_j (what="csr") or of P_j, level j+1 -> j (what="interp")."""
+        rp = self.host_array(what + "_rowptr", level).astype(np.int64)
+        col = self.host_array(what + "_col", level).astype(np.int64)
+        return rp, col, self.host_array(what + "_val", level)
 
 
 class BatchedSolver(_Base):

@@ -1,0 +1,88 @@
+"""Chebyshev-accelerated Schwarz smoothers (paper, Sec. 4.1, eq. asm; FDM local solves) on
+the GPU against the oracle's definition (oracle/schwarz.py).
+
+Same lambda_max on both sides (the oracle's dense estimate): V-cycles to 1e-12, GMRES
+solves with identical iteration counts and recurrences to 1e-11 ||b||. The GPU's own
+lambda_max(S A) (Arnoldi, 30 steps) is compared with the oracle's dense value separately.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workload as wl
+from oracle import chebyshev as cheb
+from oracle import krylov, mg
+from paper_2210_03179_amd.solver import SemSolver
+
+pytestmark = pytest.mark.gpu
+
+ORDERS = [5, 3, 1]
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.fixture(scope="module")
+def mesh():
+    return wl.deformed_box((2, 2, 3), 0.05)
+
+
+@pytest.fixture(scope="module")
+def lmax_ref(mesh):
+    out = {}
+    for sw in ("asm", "ras"):
+        h = mg.sem_hierarchy(mesh, 5, cheb.CHEB4, 2, 2, orders=ORDERS, schwarz=sw)
+        out[sw] = [lev.lmax for lev in h.levels[:-1]]
+    return out
+
+
+@pytest.mark.parametrize("sw", ["asm", "ras"])
+@pytest.mark.parametrize("kind,pre,post", [("cheb4", 2, 2), ("cheb1", 3, 0), ("cheb4opt", 4, 0), ("cheb1opt", 1, 2)])
+def test_schwarz_vcycle_parity(mesh, lmax_ref, sw, kind, pre, post):
+    print(f"schwarz {sw} {kind} ({pre},{post})", flush=True)
+    lmax = lmax_ref[sw]
+    ref = mg.sem_hierarchy(mesh, 5, kind, pre, post, orders=ORDERS, lmax=lmax, schwarz=sw)
+    s = SemSolver(mesh, N=5, orders=ORDERS, smoother=kind, pre=pre, post=post, lambda_max=lmax, schwarz=sw)
+    r = wl.uniform_noise(ref.levels[0].n, 21)
+    z = s.vcycle(dev(r)).cpu().numpy()
+    zo = ref.vcycle(r)
+    assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+
+
+@pytest.mark.parametrize("sw", ["asm", "ras"])
+def test_schwarz_gmres_parity(mesh, lmax_ref, sw):
+    lmax = lmax_ref[sw]
+    ref = mg.sem_hierarchy(mesh, 5, cheb.CHEB4, 2, 0, orders=ORDERS, lmax=lmax, schwarz=sw)
+    box = ref.extra["boxes"][0]
+    b = box.mass() * wl.manufactured_load(box.coords()) + 1e-2 * wl.uniform_noise(box.n, 5)
+    res = krylov.fgmres(box.apply, b, ref.vcycle, 1e-10, restart=20, maxit=100)
+    s = SemSolver(mesh, N=5, orders=ORDERS, smoother="cheb4", pre=2, post=0, lambda_max=lmax, schwarz=sw,
+                  krylov="gmres", restart=20)
+    u, info = s.solve(dev(b), rtol=1e-10, maxit=100)
+    assert info.converged and res.converged and info.iterations == res.iterations
+    assert np.max(np.abs(info.history - np.array(res.history))) <= 1e-11 * np.linalg.norm(b)
+    assert np.linalg.norm(u.cpu().numpy() - res.x) <= 1e-10 * np.linalg.norm(res.x)
+
+
+@pytest.mark.parametrize("sw", ["asm", "ras"])
+def test_schwarz_lambda_estimate(mesh, lmax_ref, sw):
+    s = SemSolver(mesh, N=5, orders=ORDERS, smoother="cheb4", pre=2, post=2, schwarz=sw)
+    est = s.lambda_max()
+    for a, b in zip(est, lmax_ref[sw]):
+        assert abs(a - b) <= 1e-3 * b, (est, lmax_ref[sw])
+
+
+def test_schwarz_mixed_precision_true_residual():
+    V = wl.deformed_box(4, 0.05)
+    from oracle.sem import SemBox
+    box = SemBox(V, 7)
+    b = box.mass() * wl.manufactured_load(box.coords()) + 1e-3 * wl.uniform_noise(box.n, 0)
+    s = SemSolver(V, N=7, precision="mixed", smoother="cheb4", pre=2, post=0, schwarz="ras", krylov="gmres")
+    u, info = s.solve(dev(b), rtol=1e-8, maxit=100)
+    assert info.converged
+    assert np.linalg.norm(b - box.apply(u.cpu().numpy())) <= 1.01e-8 * np.linalg.norm(b)
+    sj = SemSolver(V, N=7, precision="mixed", smoother="cheb4", pre=2, post=0, krylov="gmres")
+    _, infoj = sj.solve(dev(b), rtol=1e-8, maxit=100)
+    print(f"schwarz-RAS iterations {info.iterations}, Jacobi {infoj.iterations}", flush=True)
+    assert info.iterations < infoj.iterations

@@ -127,3 +127,49 @@ def test_device_calls_on_host_context_fail_loudly(host_ctx):
     lib = L.load()
     st = lib.sem_apply_A(s._ctx, C.c_void_p(8), C.c_void_p(8), None)
     assert st == L.SEM_ENODEV
+
+
+def test_schwarz_option_validation():
+    import workload as wl
+    from paper_2210_03179_amd import _lib as L
+    from paper_2210_03179_amd.solver import SemSolver
+    V = wl.deformed_box(2, 0.05)
+    with pytest.raises(L.SemError) as ex:  # order 2 on a smoothed level
+        SemSolver(V, N=5, orders=[5, 2, 1], schwarz="asm", device=-1, lambda_max=[1.0, 1.0])
+    assert ex.value.status == L.SEM_EINVAL
+    with pytest.raises(L.SemError) as ex:  # default schedule 4 -> 2 -> 1
+        SemSolver(V, N=4, schwarz="ras", device=-1, lambda_max=[1.0, 1.0])
+    assert ex.value.status == L.SEM_EINVAL
+    with pytest.raises(L.SemError) as ex:  # unknown smoother code
+        SemSolver(V, N=5, schwarz=7, device=-1, lambda_max=[1.0, 1.0])
+    assert ex.value.status == L.SEM_EINVAL
+
+
+def test_fd_sparse_host_arrays_match_oracle():
+    s = FdSolver(n=32, Lx=4.0, factor=2, coarsest_n=2, device=-1, lambda_max=[1, 1, 1, 1])
+    As, Ps, _ = fd2d.hierarchy_matrices(32, 2, 4.0, 1.0, coarsest_n=2)
+    for j, A in enumerate(As):
+        rp, col, val = s.sparse("csr", j)
+        D = np.zeros(A.shape)
+        for r in range(A.shape[0]):
+            D[r, col[rp[r]:rp[r + 1]]] = val[rp[r]:rp[r + 1]]
+        assert np.max(np.abs(D - A.toarray())) < 1e-12 * abs(A).max()
+    for j, P in enumerate(Ps):
+        rp, col, val = s.sparse("interp", j)
+        D = np.zeros(P.shape)
+        for r in range(P.shape[0]):
+            D[r, col[rp[r]:rp[r + 1]]] = val[rp[r]:rp[r + 1]]
+        assert np.max(np.abs(D - P.toarray())) < 1e-15
+    with pytest.raises(L.SemError):
+        s.host_array("interp_val", len(As) - 1)   # no interpolation below the coarsest level
+
+
+def test_set_smoothing_validation_and_mg_option():
+    s = FdSolver(n=16, factor=2, coarsest_n=2, device=-1, lambda_max=[1, 1, 1], krylov="mg")
+    s.set_smoothing("cheb1opt", 3, 3)
+    for args in (("cheb4opt", 17, 0), ("cheb4", 0, 0), (9, 1, 1)):
+        with pytest.raises(L.SemError) as ex:
+            s.set_smoothing(*args)
+        assert ex.value.status == L.SEM_EINVAL
+    with pytest.raises(L.SemError):
+        FdSolver(n=16, factor=2, coarsest_n=2, device=-1, lambda_max=[1, 1, 1], krylov=7)
