@@ -61,6 +61,12 @@ def load() -> C.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2210_03179_amd.build")
+    try:
+        # torch ships its own HIP runtime; loading it first makes the library bind to that same
+        # runtime instance (one runtime per process), whichever module the caller imported first
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     P = C.POINTER

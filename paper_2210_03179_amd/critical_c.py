@@ -33,10 +33,34 @@ from .solver import FdSolver
 KINDS = ("cheb1", "cheb1opt", "cheb4", "cheb4opt")
 
 
+def _cheb_T_U(k: int, x: float):
+    """T_k(x) and U_{k-1}(x) by their three-term recurrences."""
+    t0, t1 = 1.0, x
+    u0, u1 = 0.0, 1.0          # U_{-1}, U_0
+    for _ in range(k - 1):
+        t0, t1 = t1, 2.0 * x * t1 - t0
+        u0, u1 = u1, 2.0 * x * u1 - u0
+    return (t1 if k >= 1 else t0), u1
+
+
+def gamma_inv_first_kind(k: int, lmin: float = 0.1, kstar: int = 3) -> float:
+    """gamma^{-1} of the 1st-kind smoother with fixed lambda_min (eq. gamma-1st-kind,
+    lambda_max = 1; its branch point is k* = 3 for lambda_min = 0.1)."""
+    x = (lmin + 1.0) / (lmin - 1.0)
+    T, U = _cheb_T_U(k, x)
+    if k <= kstar:
+        return T * T - 1.0
+    return 4.0 * k * U / ((lmin - 1.0) * T)
+
+
 def predicted_critical_C(kind: str, k: int) -> float:
-    """C* of the closed forms: (2k,0) has the smaller bound than (k,k) iff C > C*.
-    1st kind (lambda_min = lambda_max / 10): for k <= 3 the one-sided cycle wins for
-    every C (C* = 0); beyond, the asymptotic form 1.55 e^{1.45 k}."""
+    """C* above which (2k,0) has the smaller bound than (k,k): sqrt(V(C,2k)) < V(C,k)
+    (eq. optimal-mn with (m,n) = (2k,0) against (k,k)), that is
+    C > gamma^{-1}(k)^2 / (gamma^{-1}(2k) - 2 gamma^{-1}(k)).
+    4th and optimised 4th kind: eqs. 4th-kind-condition-C and opt-4th-kind-condition-C.
+    1st kind, lambda_min = 0.1: that construction with eq. gamma-1st-kind (its large-k
+    form is eq. 1st-kind-condition-C, 1.55 e^{1.45 k}); inf where (2k,0) never wins.
+    Optimised 1st kind: the fitted eq. opt-1st-kind-condition-C, 1.81 k^1.73."""
     if kind == "cheb4":
         return 2.0 * (k + 1) ** 2 / 3.0
     if kind == "cheb4opt":
@@ -44,7 +68,8 @@ def predicted_critical_C(kind: str, k: int) -> float:
         pi2 = math.pi ** 2
         return 2.0 * (6.0 * a - pi2) ** 2 / (3.0 * pi2 * (-12.0 * a + 6.0 * (4 * k + 1) ** 2 + pi2))
     if kind == "cheb1":
-        return 0.0 if k <= 3 else 1.55 * math.exp(1.45 * k)
+        gk, g2k = gamma_inv_first_kind(k), gamma_inv_first_kind(2 * k)
+        return gk * gk / (g2k - 2.0 * gk) if g2k > 2.0 * gk else math.inf
     if kind == "cheb1opt":
         return 1.81 * k ** 1.73
     raise ValueError(f"unknown smoother kind {kind!r}")
@@ -70,7 +95,8 @@ def approximation_constants(solver: FdSolver) -> list:
         # rho(D^{-1} A) from the symmetric form D^{-1/2} A D^{-1/2}
         s = 1.0 / np.sqrt(d)
         Ds = sla.LinearOperator(A.shape, matvec=lambda v: s * (A @ (s * v)), dtype=np.float64)
-        lmax = float(sla.eigsh(Ds, k=1, which="LA", return_eigenvectors=False, tol=1e-10)[0])
+        lmax = float(sla.eigsh(Ds, k=1, which="LA", return_eigenvectors=False, tol=1e-10,
+                               ncv=min(120, A.shape[0] - 1))[0]) if A.shape[0] > 1 else float(s[0] * A[0, 0] * s[0])
         # S = D^{-1} / lmax; C_j = lambda_max(S^{-1/2} K S^{-1/2}), K = A^{-1} - P Ac^{-1} P^T
         t = np.sqrt(d * lmax)
         luA, luC = sla.splu(A), sla.splu(Ac)
@@ -80,7 +106,24 @@ def approximation_constants(solver: FdSolver) -> list:
             return t * (luA.solve(w) - P @ luC.solve(P.T @ w))
 
         K = sla.LinearOperator(A.shape, matvec=kv, dtype=np.float64)
-        out.append(float(sla.eigsh(K, k=1, which="LA", return_eigenvectors=False, tol=1e-10)[0]))
+        if A.shape[0] <= 200:
+            Kd = np.column_stack([kv(e) for e in np.eye(A.shape[0])])
+            out.append(float(np.linalg.eigvalsh(0.5 * (Kd + Kd.T))[-1]))
+        else:
+            # the top of this spectrum is clustered; 6 digits are plenty for a critical-C table
+            out.append(float(sla.eigsh(K, k=1, which="LA", return_eigenvectors=False, tol=1e-6,
+                                       ncv=min(60, A.shape[0] - 1))[0]))
+    return out
+
+
+def study_constants(n=128, factors=(2, 8), Lxs=(1, 2, 4, 8, 16, 32, 64)) -> dict:
+    """C = max_j C_j per (factor, L_x), from host-only contexts (no GPU needed)."""
+    out = {}
+    for f in factors:
+        for Lx in Lxs:
+            probe = FdSolver(n=n, Lx=Lx, Ly=1.0, factor=f, coarsest_n=2, device=-1, lambda_max=[1.0] * 8)
+            out[f"{f}:{float(Lx)}"] = approximation_constants(probe)
+            probe.close()
     return out
 
 
@@ -105,15 +148,17 @@ def max_order(kind: str, kmax: int) -> int:
 
 
 def run_study(n=128, factors=(2, 8), Lxs=(1, 2, 4, 8, 16, 32, 64), kmax=10, rtol=1e-6, maxit=200,
-              gmres_factors=(2,), sweep_Lxs=(1, 8, 64), seed=0, log=print) -> dict:
-    """Average convergence rates of (k,k), (2k,0) and (optionally) every (m, 2k-m) cycle."""
+              gmres_factors=(2,), sweep_Lxs=(1, 8, 64), seed=0, constants=None, log=print) -> dict:
+    """Average convergence rates of (k,k), (2k,0) and (optionally) every (m, 2k-m) cycle.
+    constants: the study_constants() dict, computed here when None."""
     runs = []
     for f in factors:
         for Lx in Lxs:
             t0 = time.time()
             mgs = FdSolver(n=n, Lx=Lx, Ly=1.0, factor=f, coarsest_n=2, smoother="cheb4", pre=1, post=1,
                            krylov="mg")
-            Cs = approximation_constants(mgs)
+            key = f"{f}:{float(Lx)}"
+            Cs = constants[key] if constants and key in constants else approximation_constants(mgs)
             lmax = mgs.lambda_max()
             gm = None
             if f in gmres_factors:
@@ -157,14 +202,15 @@ def critical_table(study: dict, method: str = "solver") -> list:
     for (f, kind, k), d in sorted(by.items()):
         Cs = sorted(C for C in d if "sym" in d[C] and "one" in d[C])
         wins = [C for C in Cs if d[C]["one"] < d[C]["sym"]]
-        obs = None
+        obs, below = None, None
         for i, C in enumerate(Cs):
             if all(d[c]["one"] < d[c]["sym"] for c in Cs[i:]):
-                obs = C
+                obs, below = C, (Cs[i - 1] if i > 0 else None)
                 break
         ratios = [d[C]["one"] / d[C]["sym"] for C in Cs]
         rows.append({"factor": f, "kind": kind, "k": k, "C_tested": Cs, "one_sided_wins_at": wins,
-                     "observed_C_star": obs, "predicted_C_star": predicted_critical_C(kind, k),
+                     "observed_C_star": obs, "observed_C_star_above": below,
+                     "predicted_C_star": predicted_critical_C(kind, k),
                      "rate_ratio_min": min(ratios) if ratios else None,
                      "rate_ratio_max": max(ratios) if ratios else None})
     return rows
@@ -187,15 +233,23 @@ def best_split_table(study: dict) -> list:
     return rows
 
 
+def _interval(r) -> str:
+    """Observed C* as the interval between the tested C values around the switch."""
+    if r["observed_C_star"] is None:
+        return "never"
+    if r["observed_C_star_above"] is None:
+        return f"<= {r['observed_C_star']:.3g}"
+    return f"({r['observed_C_star_above']:.3g}, {r['observed_C_star']:.3g}]"
+
+
 def markdown(study: dict) -> str:
     lines = ["| factor | kind | k | predicted C* | observed C* (solver) | observed C* (GMRES(20)) |"
              " rho(2k,0)/rho(k,k) min..max |", "|---|---|---|---|---|---|---|"]
     gm = {(r["factor"], r["kind"], r["k"]): r for r in critical_table(study, "gmres20")}
     for r in critical_table(study, "solver"):
         g = gm.get((r["factor"], r["kind"], r["k"]))
-        fmt = lambda v: "never" if v is None else f"{v:.3g}"  # noqa: E731
         lines.append(f"| {r['factor']} | {r['kind']} | {r['k']} | {r['predicted_C_star']:.3g} | "
-                     f"{fmt(r['observed_C_star'])} | {fmt(g['observed_C_star']) if g else '-'} | "
+                     f"{_interval(r)} | {_interval(g) if g else '-'} | "
                      f"{r['rate_ratio_min']:.3f}..{r['rate_ratio_max']:.3f} |")
     sweep = best_split_table(study)
     if sweep:
@@ -214,9 +268,23 @@ def main(argv=None):
     ap.add_argument("--Lx", type=float, nargs="+", default=[1, 2, 4, 8, 16, 32, 64])
     ap.add_argument("--factors", type=int, nargs="+", default=[2, 8])
     ap.add_argument("--sweep-Lx", type=float, nargs="*", default=[1, 8, 64])
+    ap.add_argument("--gmres-factors", type=int, nargs="*", default=[2, 8],
+                    help="coarsening factors whose cycles are also timed as GMRES(20) preconditioners")
+    ap.add_argument("--constants-only", action="store_true",
+                    help="compute C_j on the host (no GPU) and write them to --out")
+    ap.add_argument("--constants", help="JSON written by --constants-only, to skip recomputing C_j")
     a = ap.parse_args(argv)
+    if a.constants_only:
+        with open(a.out, "w") as fh:
+            json.dump(study_constants(a.n, tuple(a.factors), tuple(a.Lx)), fh, indent=1)
+        return
+    constants = None
+    if a.constants:
+        with open(a.constants) as fh:
+            constants = json.load(fh)
     study = run_study(n=a.n, factors=tuple(a.factors), Lxs=tuple(a.Lx), kmax=a.kmax, maxit=a.maxit,
-                      sweep_Lxs=tuple(a.sweep_Lx), log=lambda s: print(s, flush=True))
+                      sweep_Lxs=tuple(a.sweep_Lx), gmres_factors=tuple(a.gmres_factors), constants=constants,
+                      log=lambda s: print(s, flush=True))
     with open(a.out, "w") as fh:
         json.dump(study, fh)
     print(markdown(study), flush=True)
