@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batched measurement")
     ap.add_argument("--no-schwarz", action="store_true", help="skip the Chebyshev-Schwarz measurement")
+    ap.add_argument("--no-trilinear", action="store_true",
+                    help="skip the measurement with factors formed in the operator")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the 64-system batched measurement (for profiler runs)")
     ap.add_argument("--kernel-reps", type=int, default=20)
@@ -362,6 +364,38 @@ def main():
                                         "setup_s": round(t_sw_setup, 2), "lambda_max": ssw.lambda_max()}
         log(f"schwarz RAS: {out['schwarz_ras_cheb4_2_0']}")
         del ssw
+    if not args.no_trilinear:
+        # the same solves with the geometric factors formed inside the operator from the
+        # trilinear element geometry (36 edge values per element) instead of read from HBM;
+        # not the headline: it holds for trilinear elements only
+        stm = SemSolver(V, N=N, smoother="cheb4opt", pre=4, post=0, precision="mixed", geometry="trilinear",
+                        lambda_max=smx.lambda_max())
+        st64 = SemSolver(V, N=N, smoother="cheb4opt", pre=4, post=0, precision="fp64", geometry="trilinear",
+                         lambda_max=s64.lambda_max())
+        utm, infotm, dttm, _, _ = time_solves(stm, b, max(1, args.steps // 2), 1)
+        ut64, infot64, dtt64, _, _ = time_solves(st64, b, max(1, args.steps // 2), 1)
+        t_tax64 = time_kernel(lambda: st64.apply_local(u_rand, w_loc), args.kernel_reps)
+        t_tax32 = time_kernel(lambda: stm.apply_local(u32, w32), args.kernel_reps)
+        E = nloc // (N + 1) ** 3
+        out["trilinear_geometry"] = {
+            "mixed": {"ms_per_solve": round(dttm * 1e3, 4), "iterations": infotm.iterations,
+                      "gdof_iter_per_s": round(n * infotm.iterations / dttm / 1e9, 4),
+                      "true_relres": true_rel(utm)},
+            "fp64": {"ms_per_solve": round(dtt64 * 1e3, 4), "iterations": infot64.iterations,
+                     "gdof_iter_per_s": round(n * infot64.iterations / dtt64 / 1e9, 4),
+                     "true_relres": true_rel(ut64)},
+            # algorithmic bytes: u gathered once per unknown, w stored per local node, 36 edge
+            # values per element
+            "ax_fp64_us": round(t_tax64 * 1e6, 2),
+            "ax_fp64_GBs": round((8.0 * n + 8.0 * nloc + 288.0 * E) / t_tax64 / 1e9, 1),
+            "ax_fp32_us": round(t_tax32 * 1e6, 2),
+            "ax_fp32_GBs": round((4.0 * n + 4.0 * nloc + 144.0 * E) / t_tax32 / 1e9, 1),
+            "variants_fp64_us": [round(x, 1) for x in st64.host_array("ax_tuning", 0)[1:3]],
+            "variants_fp32_us": [round(x, 1) for x in stm.host_array("ax_tuning", 0)[2 + nvar:4 + nvar]],
+        }
+        log(f"trilinear geometry: {out['trilinear_geometry']}")
+        stm.close()
+        st64.close()
     if not args.no_batched:
         log("batched systems ...")
         out["batched"] = bench_batched(max(1, args.steps // 2))

@@ -88,6 +88,14 @@ enum { SEM_JACOBI = 0, SEM_ASM = 1, SEM_RAS = 2 };
  * convergence rate, eq. avg-convergence-rate, is compared with Lemma
  * multilevel-poly-bound and the critical C of the one-sided cycle) */
 enum { SEM_PCG = 0, SEM_FCG = 1, SEM_GMRES = 2, SEM_MG = 3 };
+/* Geometric factors G = w_i w_j w_k |J| J^{-1} J^{-T} of the operator (eq. poisson with
+ * the SEM quadrature): SEM_GEOM_STORED reads the six factors per node from HBM (the
+ * general form, any element map); SEM_GEOM_TRILINEAR computes them inside the operator
+ * from 36 edge values per element, exact for the trilinear elements of a box mesh, so
+ * the operator streams only u and w. The trilinear form stores no factors on the
+ * device (sem_get_factors / sem_set_factors return SEM_EINVAL) and exists for single
+ * SEM contexts only. */
+enum { SEM_GEOM_STORED = 0, SEM_GEOM_TRILINEAR = 1 };
 
 #define SEM_MAX_LEVELS 8
 
@@ -107,6 +115,7 @@ typedef struct {
   int32_t coarse_planes;            /* planes per block of the coarse solve, 0 = auto */
   int32_t gmres_restart;            /* m of GMRES(m), 1..32; 0 = 30 */
   int32_t schwarz;                  /* smoother inside Chebyshev: SEM_JACOBI, SEM_ASM or SEM_RAS */
+  int32_t geometry;                 /* SEM_GEOM_STORED or SEM_GEOM_TRILINEAR */
 } sem_options;
 
 /* Structured hexahedral box mesh: (nex+1)(ney+1)(nez+1) vertices, x fastest.
@@ -119,7 +128,7 @@ typedef struct {
 
 /* Fills *opt with: N = 7, default schedule, SEM_CHEB4_OPT, (4,0), FP64,
  * SEM_FCG, estimated lambda_max, lambda_scale 1, device 0, GMRES restart 30,
- * Jacobi smoothing. */
+ * Jacobi smoothing, stored geometric factors. */
 void sem_options_default(sem_options *opt);
 
 /* Set up the SEM hierarchy on a box mesh: GLL data, geometric factors, Jacobi
@@ -200,7 +209,8 @@ sem_status sem_mass_apply(sem_ctx *ctx, const double *f, double *b, void *stream
 /* Copy the finest-level FP64 geometric factors out of / into the context.
  * G: device, E*6*(N+1)^3 doubles, layout [e][c][k][j][i]. Setting factors
  * changes A for apply_A, solve and the adjoint contraction; the
- * preconditioner (diagonals, lambda_max, coarse levels) keeps its setup data. */
+ * preconditioner (diagonals, lambda_max, coarse levels) keeps its setup data.
+ * SEM_EINVAL on contexts with SEM_GEOM_TRILINEAR (no factors are stored). */
 sem_status sem_get_factors(sem_ctx *ctx, double *G, void *stream);
 sem_status sem_set_factors(sem_ctx *ctx, const double *G, void *stream);
 

@@ -19,6 +19,7 @@ SMOOTHERS = {"cheb1": 1, "cheb1opt": 2, "cheb4": 4, "cheb4opt": 5}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 KRYLOV = {"pcg": 0, "fcg": 1, "gmres": 2, "mg": 3}
 SCHWARZ = {None: 0, "jacobi": 0, "asm": 1, "ras": 2}
+GEOMETRY = {"stored": 0, "trilinear": 1}
 MAX_LEVELS = 8
 
 # exported entry points, as declared in include/semcheb.h
@@ -38,6 +39,7 @@ class SemOptions(C.Structure):
         ("precision", C.c_int32), ("krylov", C.c_int32), ("num_lambda_max", C.c_int32),
         ("lambda_max", C.c_double * MAX_LEVELS), ("lambda_scale", C.c_double), ("device", C.c_int32),
         ("coarse_planes", C.c_int32), ("gmres_restart", C.c_int32), ("schwarz", C.c_int32),
+        ("geometry", C.c_int32),
     ]
 
 
@@ -116,7 +118,7 @@ def check(status: int, ctx=None) -> int:
 
 def make_options(N=7, smoother="cheb4opt", pre=4, post=0, precision="fp64", krylov="fcg",
                  orders=None, lambda_max=None, lambda_scale=1.0, device=0, coarse_planes=0,
-                 restart=30, schwarz=None) -> SemOptions:
+                 restart=30, schwarz=None, geometry="stored") -> SemOptions:
     lib = load()
     o = SemOptions()
     lib.sem_options_default(C.byref(o))
@@ -138,4 +140,5 @@ def make_options(N=7, smoother="cheb4opt", pre=4, post=0, precision="fp64", kryl
     o.coarse_planes = int(coarse_planes)
     o.gmres_restart = int(restart)
     o.schwarz = SCHWARZ[schwarz] if (schwarz is None or isinstance(schwarz, str)) else int(schwarz)
+    o.geometry = GEOMETRY[geometry] if isinstance(geometry, str) else int(geometry)
     return o

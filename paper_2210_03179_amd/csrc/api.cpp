@@ -117,6 +117,10 @@ sem_status validate_common(const sem_options *o, std::string &err) {
     err = "unknown Schwarz smoother";
     return SEM_EINVAL;
   }
+  if (o->geometry != SEM_GEOM_STORED && o->geometry != SEM_GEOM_TRILINEAR) {
+    err = "unknown geometry option";
+    return SEM_EINVAL;
+  }
   if (o->gmres_restart < 0 || o->gmres_restart > kMaxRestart) {
     err = "gmres_restart must lie in 0..32 (0 = 30)";
     return SEM_EINVAL;
@@ -284,11 +288,19 @@ void smooth(const sem_ctx *c, Level &L, int k, bool zero_guess, hipStream_t s) {
   }
 }
 
-void coarse_solve64(sem_ctx *c, const double *b, double *x, hipStream_t s) {
+// Exact solve of the order-1 coarse system (M_l^{-1} = A_l^{-1}, Sec. 2) with the
+// precomputed block factors; f32 reads their single-precision copies.
+void coarse_solve_blocks(sem_ctx *c, const double *b, double *x, bool f32, hipStream_t s) {
   CoarseSolver &C = c->coarse;
   if (C.n == 0) return;
+  // one dense factor block as a GEMV segment, in the requested storage precision
+  auto seg = [&](const double *M, const float *M32, const double *v, int64_t ncols, double sign) {
+    return f32 ? GemvSeg{nullptr, v, ncols, sign, M32} : GemvSeg{M, v, ncols, sign, nullptr};
+  };
+  auto at = [](const std::vector<float *> &v, int q) { return v.empty() ? (const float *)nullptr : v[q]; };
   if (C.dense) {
-    launch_gemv(C.n, C.n, C.Minv, b, nullptr, x, 0, s);
+    GemvJob jb{nullptr, x, C.n, 1, {seg(C.Minv, C.Minv32, b, C.n, 1.0)}};
+    launch_gemv_jobs(1, &jb, s);
     return;
   }
   // Block-tridiagonal substitution from both ends (blocks above `mid` top-down, below
@@ -301,32 +313,40 @@ void coarse_solve64(sem_ctx *c, const double *b, double *x, hipStream_t s) {
     GemvJob jobs[2];
     int nj = 0;
     const int top = step, bot = nb - 1 - step;
-    if (top < m) jobs[nj++] = GemvJob{b + C.start[top], C.y + C.start[top], rows(top), 1,
-                                      {{C.Lb[top], yb(top - 1), rows(top - 1), -1.0}}};
-    if (bot > m) jobs[nj++] = GemvJob{b + C.start[bot], C.y + C.start[bot], rows(bot), 1,
-                                      {{C.Lb[bot], yb(bot + 1), rows(bot + 1), -1.0}}};
+    if (top < m)
+      jobs[nj++] = GemvJob{b + C.start[top], C.y + C.start[top], rows(top), 1,
+                           {seg(C.Lb[top], at(C.Lb32, top), yb(top - 1), rows(top - 1), -1.0)}};
+    if (bot > m)
+      jobs[nj++] = GemvJob{b + C.start[bot], C.y + C.start[bot], rows(bot), 1,
+                           {seg(C.Lb[bot], at(C.Lb32, bot), yb(bot + 1), rows(bot + 1), -1.0)}};
     if (nj == 0) break;
     launch_gemv_jobs(nj, jobs, s);
   }
   {  // middle: x_m = Minv_m b_m - Xtop y_{m-1} - Xbot y_{m+1}
-    GemvJob jb{nullptr, x + C.start[m], rows(m), 1, {{C.Mb[m], b + C.start[m], rows(m), 1.0}}};
-    if (m > 0) jb.seg[jb.nseg++] = GemvSeg{C.Xtop, yb(m - 1), rows(m - 1), -1.0};
-    if (m < nb - 1) jb.seg[jb.nseg++] = GemvSeg{C.Xbot, yb(m + 1), rows(m + 1), -1.0};
+    GemvJob jb{nullptr, x + C.start[m], rows(m), 1, {seg(C.Mb[m], at(C.Mb32, m), b + C.start[m], rows(m), 1.0)}};
+    if (m > 0) jb.seg[jb.nseg++] = seg(C.Xtop, C.Xtop32, yb(m - 1), rows(m - 1), -1.0);
+    if (m < nb - 1) jb.seg[jb.nseg++] = seg(C.Xbot, C.Xbot32, yb(m + 1), rows(m + 1), -1.0);
     launch_gemv_jobs(1, &jb, s);
   }
   for (int step = 1;; ++step) {  // backward: x_q = Minv_q y_q - W_q x_n, n the neighbour towards mid
     GemvJob jobs[2];
     int nj = 0;
     const int top = m - step, bot = m + step;
-    if (top >= 0) jobs[nj++] = GemvJob{nullptr, x + C.start[top], rows(top), 2,
-                                       {{C.Mb[top], yb(top), rows(top), 1.0},
-                                        {C.Wb[top], x + C.start[top + 1], rows(top + 1), -1.0}}};
-    if (bot < nb) jobs[nj++] = GemvJob{nullptr, x + C.start[bot], rows(bot), 2,
-                                       {{C.Mb[bot], yb(bot), rows(bot), 1.0},
-                                        {C.Wb[bot], x + C.start[bot - 1], rows(bot - 1), -1.0}}};
+    if (top >= 0)
+      jobs[nj++] = GemvJob{nullptr, x + C.start[top], rows(top), 2,
+                           {seg(C.Mb[top], at(C.Mb32, top), yb(top), rows(top), 1.0),
+                            seg(C.Wb[top], at(C.Wb32, top), x + C.start[top + 1], rows(top + 1), -1.0)}};
+    if (bot < nb)
+      jobs[nj++] = GemvJob{nullptr, x + C.start[bot], rows(bot), 2,
+                           {seg(C.Mb[bot], at(C.Mb32, bot), yb(bot), rows(bot), 1.0),
+                            seg(C.Wb[bot], at(C.Wb32, bot), x + C.start[bot - 1], rows(bot - 1), -1.0)}};
     if (nj == 0) break;
     launch_gemv_jobs(nj, jobs, s);
   }
+}
+
+void coarse_solve64(sem_ctx *c, const double *b, double *x, hipStream_t s) {
+  coarse_solve_blocks(c, b, x, false, s);
 }
 
 template <typename T>
@@ -340,7 +360,7 @@ void coarse_solve<float>(sem_ctx *c, Level &L, hipStream_t s) {
   CoarseSolver &C = c->coarse;
   if (C.n == 0) return;
   launch_convert(C.n, L.b32, C.b, s);
-  coarse_solve64(c, C.b, C.x, s);
+  coarse_solve_blocks(c, C.b, C.x, C.has32, s);
   launch_convert(C.n, C.x, L.x32, s);
 }
 
@@ -583,8 +603,9 @@ sem_status autotune_operator(sem_ctx *c, hipStream_t s) {
       return SEM_EINVAL;
     }
     for (auto &L : c->levels) {
-      L.ax_variant64 = v < kAxVariants64 ? v : 0;
-      L.ax_variant32 = v;
+      // the trilinear operator has two variants (occupancy); other requests fall back to 0
+      L.ax_variant64 = v < (L.tri64 ? kAxTriVariants : kAxVariants64) ? v : 0;
+      L.ax_variant32 = v < (L.tri32 ? kAxTriVariants : kAxVariants) ? v : 0;
     }
     return SEM_OK;
   }
@@ -604,9 +625,10 @@ sem_status autotune_operator(sem_ctx *c, hipStream_t s) {
     Level &L = c->levels[j];
     for (int prec = 0; prec < 2; ++prec) {
       const bool fp64 = prec == 0;
-      if (!fp64 && !(mixed && L.Gbf && L.w32)) continue;
+      if (!fp64 && !(mixed && (L.Gbf || L.tri32) && L.w32)) continue;
       if (fp64 && !L.w64) continue;
-      const int nvar = fp64 ? kAxVariants64 : kAxVariants;
+      const bool trilinear = fp64 ? L.tri64 != nullptr : L.tri32 != nullptr;
+      const int nvar = trilinear ? kAxTriVariants : (fp64 ? kAxVariants64 : kAxVariants);
       float *times = fp64 ? L.ax_time64_us : L.ax_time32_us;
       for (int v = 0; v < kAxVariants; ++v) times[v] = v < nvar ? 1e30f : -1.0f;
       for (int round = 0; round < rounds && st == SEM_OK; ++round) {
@@ -891,11 +913,35 @@ sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipS
     return SEM_OK;
   }
   const bool mixed = opt->precision == SEM_MIXED;
+  // trilinear geometry: one edge table for all levels (the elements are the same), the
+  // factors are formed in the operator and never stored on the device
+  const bool tri = opt->geometry == SEM_GEOM_TRILINEAR;
+  double *tri64 = nullptr;
+  float *tri32 = nullptr;
+  if (tri) {
+    const std::vector<double> edges = trilinear_edges(*mesh);
+    TRY(upload(c, &tri64, edges.data(), edges.size(), s));
+    if (mixed) {
+      std::vector<float> e32(edges.begin(), edges.end());
+      TRY(upload(c, &tri32, e32.data(), e32.size(), s));
+    }
+  }
   for (int j = 0; j < nl; ++j) {
     const BoxLevelHost &h = c->host_levels[j];
     Level &L = c->levels[j];
     const bool coarse = j == nl - 1;
-    TRY(upload(c, &L.G64, h.G.data(), h.G.size(), s));
+    if (!tri) TRY(upload(c, &L.G64, h.G.data(), h.G.size(), s));
+    if (tri) {  // every level (a one-level hierarchy applies its coarse level's operator)
+      std::vector<double> xw(h.gll.x.begin(), h.gll.x.end());
+      xw.insert(xw.end(), h.gll.w.begin(), h.gll.w.end());
+      L.tri64 = tri64;
+      TRY(upload(c, &L.gxw64, xw.data(), xw.size(), s));
+      if (mixed) {
+        std::vector<float> xw32(xw.begin(), xw.end());
+        L.tri32 = tri32;
+        TRY(upload(c, &L.gxw32, xw32.data(), xw32.size(), s));
+      }
+    }
     TRY(upload(c, &L.D64, h.gll.D.data(), h.gll.D.size(), s));
     std::vector<float> D32(h.gll.D.begin(), h.gll.D.end());
     TRY(upload(c, &L.D32, D32.data(), D32.size(), s));
@@ -904,7 +950,7 @@ sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipS
     TRY(upload(c, &L.invdiag64, inv.data(), inv.size(), s));
     std::vector<float> inv32(inv.begin(), inv.end());
     TRY(upload(c, &L.invdiag32, inv32.data(), inv32.size(), s));
-    if (mixed && !coarse) {
+    if (mixed && !coarse && !tri) {
       std::vector<uint16_t> gb(h.G.size());
       for (size_t q = 0; q < gb.size(); ++q) gb[q] = to_bf16(h.G[q]);
       TRY(upload(c, &L.Gbf, gb.data(), gb.size(), s));
@@ -956,23 +1002,38 @@ sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipS
     TRY(dalloc(c, &C.x, C.n));
     TRY(dalloc(c, &C.y, C.n));
     TRY(dalloc(c, &C.t, C.n));
+    // the mixed-precision cycle reads single-precision copies of the factor blocks (half the
+    // bytes of this latency- and bandwidth-bound chain); products and sums stay FP64
+    C.has32 = mixed;
+    auto up32 = [&](float **dst, const std::vector<double> &src) -> sem_status {
+      if (!mixed || src.empty()) return SEM_OK;
+      std::vector<float> f(src.begin(), src.end());
+      return upload(c, dst, f.data(), f.size(), s);
+    };
     if (C.dense) {
       TRY(upload(c, &C.Minv, bt.Minv[0].data(), bt.Minv[0].size(), s));
+      TRY(up32(&C.Minv32, bt.Minv[0]));
     } else {
       const int nb = (int)start.size() - 1;
       C.mid = bt.mid;
       C.Mb.assign(nb, nullptr);
       C.Lb.assign(nb, nullptr);
       C.Wb.assign(nb, nullptr);
+      C.Mb32.assign(nb, nullptr);
+      C.Lb32.assign(nb, nullptr);
+      C.Wb32.assign(nb, nullptr);
       for (int q = 0; q < nb; ++q) {
         TRY(upload(c, &C.Mb[q], bt.Minv[q].data(), bt.Minv[q].size(), s));
         if (!bt.Lmat[q].empty()) TRY(upload(c, &C.Lb[q], bt.Lmat[q].data(), bt.Lmat[q].size(), s));
         if (!bt.Wmat[q].empty()) TRY(upload(c, &C.Wb[q], bt.Wmat[q].data(), bt.Wmat[q].size(), s));
-        HIPCHK(c, hipStreamSynchronize(s));
+        TRY(up32(&C.Mb32[q], bt.Minv[q]));
+        TRY(up32(&C.Lb32[q], bt.Lmat[q]));
+        TRY(up32(&C.Wb32[q], bt.Wmat[q]));
       }
       if (!bt.Xtop.empty()) TRY(upload(c, &C.Xtop, bt.Xtop.data(), bt.Xtop.size(), s));
       if (!bt.Xbot.empty()) TRY(upload(c, &C.Xbot, bt.Xbot.data(), bt.Xbot.size(), s));
-      HIPCHK(c, hipStreamSynchronize(s));
+      TRY(up32(&C.Xtop32, bt.Xtop));
+      TRY(up32(&C.Xbot32, bt.Xbot));
     }
   }
   TRY(alloc_krylov(c, c->levels[0].n));
@@ -1011,6 +1072,7 @@ sem_status setup_fd_impl(int n, double Lx, double Ly, int factor, int coarsest_n
   TRY(validate_common(opt, c->err));
   if (opt->precision != SEM_FP64) { c->err = "the FD problem runs in FP64"; return SEM_EINVAL; }
   if (opt->schwarz != SEM_JACOBI) { c->err = "the Schwarz smoothers exist for SEM levels only"; return SEM_EINVAL; }
+  if (opt->geometry != SEM_GEOM_STORED) { c->err = "the FD problem has no element geometry"; return SEM_EINVAL; }
   if (n < 2 || n > 8192 || !(Lx > 0) || !(Ly > 0) || (factor != 2 && factor != 4 && factor != 8) ||
       coarsest_n < 2) {
     c->err = "invalid FD problem parameters";
@@ -1129,6 +1191,7 @@ void sem_options_default(sem_options *o) {
   o->coarse_planes = 0;
   o->gmres_restart = 30;
   o->schwarz = SEM_JACOBI;
+  o->geometry = SEM_GEOM_STORED;
 }
 
 sem_status sem_setup_box(const sem_box_mesh *mesh, const sem_options *opt, void *stream, sem_ctx **out) {
@@ -1190,7 +1253,7 @@ sem_status sem_apply_local(sem_ctx *c, int32_t precision, const void *u, void *w
   const Level &L0 = c->levels[0];
   if (precision == SEM_FP64) {
     launch_ax(L0, (const double *)u, (double *)wL, (hipStream_t)stream);
-  } else if (precision == SEM_MIXED && L0.Gbf) {
+  } else if (precision == SEM_MIXED && (L0.Gbf || L0.tri32)) {
     launch_ax(L0, (const float *)u, (float *)wL, (hipStream_t)stream);
   } else {
     c->err = "precision not available on this context";
@@ -1462,6 +1525,7 @@ sem_status sem_get_factors(sem_ctx *c, double *G, void *stream) {
   TRY(need_device(c));
   if (c->kind != LVL_SEM || !G) { c->err = "factors exist for SEM problems only"; return SEM_EINVAL; }
   const Level &L = c->levels[0];
+  if (!L.G64) { c->err = "no factors are stored: the operator forms them from the trilinear geometry"; return SEM_EINVAL; }
   HIPCHK(c, hipMemcpyAsync(G, L.G64, L.L * 6 * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return SEM_OK;
 }
@@ -1470,6 +1534,7 @@ sem_status sem_set_factors(sem_ctx *c, const double *G, void *stream) {
   TRY(need_device(c));
   if (c->kind != LVL_SEM || !G) { c->err = "factors exist for SEM problems only"; return SEM_EINVAL; }
   const Level &L = c->levels[0];
+  if (!L.G64) { c->err = "no factors are stored: the operator forms them from the trilinear geometry"; return SEM_EINVAL; }
   HIPCHK(c, hipMemcpyAsync(L.G64, G, L.L * 6 * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return SEM_OK;
 }

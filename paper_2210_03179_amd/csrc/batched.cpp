@@ -181,6 +181,7 @@ sem_status setup_batched_impl(int nsys, const sem_box_mesh *meshes, const int32_
   if (opt->device < 0) { c->err = "batched contexts need a device"; return SEM_ENODEV; }
   if (opt->pre_order < 1) { c->err = "batched cycles need pre_order >= 1"; return SEM_EINVAL; }
   if (opt->schwarz != SEM_JACOBI) { c->err = "batched cycles use Jacobi smoothing"; return SEM_EINVAL; }
+  if (opt->geometry != SEM_GEOM_STORED) { c->err = "batched systems use stored factors"; return SEM_EINVAL; }
   if (opt->krylov != SEM_PCG && opt->krylov != SEM_FCG) {
     c->err = "batched systems are solved by PCG or flexible CG";
     return SEM_EINVAL;

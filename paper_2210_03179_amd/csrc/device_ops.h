@@ -307,6 +307,152 @@ __device__ __forceinline__ void ax_body(unsigned blk, const Box &b, int64_t E, c
 }
 
 
+// Geometric factors of a trilinear element computed where they are used instead of
+// read from HBM. tri holds per element 36 values: the half edge vectors
+//   Ar[c][b] = (X[c][b][1] - X[c][b][0]) / 2, As[c][a] = (X[c][1][a] - X[c][0][a]) / 2,
+//   At[b][a] = (X[1][b][a] - X[0][b][a]) / 2   (X[ck][cj][ci] the corner vertices),
+// so that at reference point (r, s, t), with h0(x) = (1-x)/2, h1(x) = (1+x)/2,
+//   dx/dr = sum_{b,c} Ar[c][b] h_b(s) h_c(t), dx/ds = sum_{a,c} As[c][a] h_a(r) h_c(t),
+//   dx/dt = sum_{a,b} At[b][a] h_a(r) h_b(s).
+// With those columns of J, the rows of J^{-1} are (js x jt, jt x jr, jr x js) / det and
+//   G_ab = w_i w_j w_k det (J^{-1} J^{-T})_ab = (w_i w_j w_k / det) (c_a . c_b),
+// c the cross products. gxw holds the GLL nodes x[0..N] then the weights w[0..N].
+template <typename T>
+struct TriColumn {
+  T rr[2][3], ss[2][3], tt[3];  // dx/dr at t-corner c, dx/ds at t-corner c, dx/dt
+  T wij;
+};
+
+template <int N, typename T>
+__device__ __forceinline__ TriColumn<T> tri_column(const T *__restrict__ te, const T *__restrict__ gxw, int i,
+                                                   int j) {
+  const T ri = gxw[i], sj = gxw[j];
+  const T ha[2] = {(T(1) - ri) * T(0.5), (T(1) + ri) * T(0.5)};
+  const T hb[2] = {(T(1) - sj) * T(0.5), (T(1) + sj) * T(0.5)};
+  TriColumn<T> c;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      c.rr[q][d] = te[(q * 2 + 0) * 3 + d] * hb[0] + te[(q * 2 + 1) * 3 + d] * hb[1];
+      c.ss[q][d] = te[12 + (q * 2 + 0) * 3 + d] * ha[0] + te[12 + (q * 2 + 1) * 3 + d] * ha[1];
+    }
+    c.tt[d] = (te[24 + 0 * 3 + d] * ha[0] + te[24 + 1 * 3 + d] * ha[1]) * hb[0] +
+              (te[24 + 2 * 3 + d] * ha[0] + te[24 + 3 * 3 + d] * ha[1]) * hb[1];
+  }
+  c.wij = gxw[N + 1 + i] * gxw[N + 1 + j];
+  return c;
+}
+
+// The six factors of plane k for the thread's column (tk, wk: node and weight of k).
+template <typename T>
+__device__ __forceinline__ void tri_factors(const TriColumn<T> &c, T tk, T wk, T &g0, T &g1, T &g2, T &g3, T &g4,
+                                            T &g5) {
+  const T f0 = (T(1) - tk) * T(0.5), f1 = (T(1) + tk) * T(0.5);
+  T jr[3], js[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    jr[d] = c.rr[0][d] * f0 + c.rr[1][d] * f1;
+    js[d] = c.ss[0][d] * f0 + c.ss[1][d] * f1;
+  }
+  const T *jt = c.tt;
+  const T cr[3] = {js[1] * jt[2] - js[2] * jt[1], js[2] * jt[0] - js[0] * jt[2], js[0] * jt[1] - js[1] * jt[0]};
+  const T cs[3] = {jt[1] * jr[2] - jt[2] * jr[1], jt[2] * jr[0] - jt[0] * jr[2], jt[0] * jr[1] - jt[1] * jr[0]};
+  const T ct[3] = {jr[1] * js[2] - jr[2] * js[1], jr[2] * js[0] - jr[0] * js[2], jr[0] * js[1] - jr[1] * js[0]};
+  const T det = jr[0] * cr[0] + jr[1] * cr[1] + jr[2] * cr[2];
+  const T sc = c.wij * wk / det;
+  g0 = sc * (cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+  g1 = sc * (cr[0] * cs[0] + cr[1] * cs[1] + cr[2] * cs[2]);
+  g2 = sc * (cr[0] * ct[0] + cr[1] * ct[1] + cr[2] * ct[2]);
+  g3 = sc * (cs[0] * cs[0] + cs[1] * cs[1] + cs[2] * cs[2]);
+  g4 = sc * (cs[0] * ct[0] + cs[1] * ct[1] + cs[2] * ct[2]);
+  g5 = sc * (ct[0] * ct[0] + ct[1] * ct[1] + ct[2] * ct[2]);
+}
+
+// The operator of ax_body with the factors of trilinear elements computed per plane
+// (tri_factors) instead of loaded: HBM traffic is the u gather and the w store only.
+template <int N, typename T>
+__device__ __forceinline__ void ax_body_tri(unsigned blk, const Box &b, int64_t E, const T *__restrict__ u,
+                                            const T *__restrict__ tri, const T *__restrict__ gxw,
+                                            const T *__restrict__ Dm, T *__restrict__ wL) {
+  using S = AxShape<N>;
+  constexpr int n1 = S::n1, n3 = n1 * n1 * n1;
+  __shared__ T sD[n1 * n1];
+  __shared__ T su[S::epb][n1][n1];
+  __shared__ T sr[S::epb][n1][n1];
+  __shared__ T ss[S::epb][n1][n1];
+  const int t = threadIdx.x;
+  const int le = t / S::tpe;
+  const int ij = t - le * S::tpe;
+  const int i = ij % n1, j = ij / n1;
+  const int64_t e = (int64_t)blk * S::epb + le;
+  const bool active = (le < S::epb) && (e < E);
+  for (int q = t; q < n1 * n1; q += S::block) sD[q] = Dm[q];
+
+  T ureg[n1], wreg[n1];
+  T Di[n1];
+  int ex = 0, ey = 0, ez = 0;
+  if (active) {
+    const Exyz ec = elem_xyz(b, e);
+    ex = ec.x;
+    ey = ec.y;
+    ez = ec.z;
+  }
+  const int I = ex * N + i, J = ey * N + j;
+  const bool inIJ = active && I >= 1 && I <= b.nx && J >= 1 && J <= b.ny;
+  const int64_t gIJ = (int64_t)(I - 1) + (int64_t)b.nx * (J - 1);
+  const int64_t plane = (int64_t)b.nx * b.ny;
+#pragma unroll
+  for (int k = 0; k < n1; ++k) {
+    const int K = ez * N + k;
+    const bool ok = inIJ && K >= 1 && K <= b.nz;
+    const T v = u[ok ? gIJ + plane * (K - 1) : 0];
+    ureg[k] = ok ? v : T(0);
+    wreg[k] = T(0);
+  }
+  const TriColumn<T> col = tri_column<N, T>(tri + (active ? e : 0) * 36, gxw, i, j);
+  __syncthreads();
+#pragma unroll
+  for (int l = 0; l < n1; ++l) Di[l] = sD[i * n1 + l];
+  const int lec = active ? le : 0;
+#pragma unroll 1
+  for (int k = 0; k < n1; ++k) {
+    T uk = ureg[0];
+#pragma unroll
+    for (int l = 1; l < n1; ++l) uk = (l == k) ? ureg[l] : uk;
+    if (active) su[lec][j][i] = uk;
+    T g0, g1, g2, g3, g4, g5;
+    tri_factors<T>(col, gxw[k], gxw[n1 + k], g0, g1, g2, g3, g4, g5);
+    __syncthreads();
+    T ur = 0, us = 0, ut = 0;
+#pragma unroll
+    for (int l = 0; l < n1; ++l) {
+      ur += Di[l] * su[lec][j][l];
+      us += sD[j * n1 + l] * su[lec][l][i];
+      ut += Dm[k * n1 + l] * ureg[l];  // wave-uniform: scalar loads
+    }
+    const T wr = g0 * ur + g1 * us + g2 * ut;
+    const T ws = g1 * ur + g3 * us + g4 * ut;
+    const T wt = g2 * ur + g4 * us + g5 * ut;
+    if (active) {
+      sr[lec][j][i] = wr;
+      ss[lec][j][i] = ws;
+    }
+    __syncthreads();
+    T acc = 0;
+#pragma unroll
+    for (int l = 0; l < n1; ++l) acc += sD[l * n1 + i] * sr[lec][j][l] + sD[l * n1 + j] * ss[lec][l][i];
+#pragma unroll
+    for (int l = 0; l < n1; ++l) wreg[l] += ((l == k) ? acc : T(0)) + Dm[k * n1 + l] * wt;
+    __syncthreads();
+  }
+  if (active) {
+    T *we = wL + e * n3;
+#pragma unroll
+    for (int k = 0; k < n1; ++k) we[(k * n1 + j) * n1 + i] = wreg[k];
+  }
+}
+
 // Same operator with the element's whole u tile resident in LDS: plane k of the tile
 // feeds the r and s derivatives and, once consumed, is overwritten by that plane's
 // r/s transpose contributions; the t-direction transpose accumulates in registers

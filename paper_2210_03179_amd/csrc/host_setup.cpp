@@ -595,6 +595,32 @@ void build_schwarz(const sem_box_mesh &mesh, const BoxLevelHost &lev, SchwarzHos
   }
 }
 
+// ------------------------------------------------------------------ trilinear edges
+// Per element the 36 half edge vectors the operator needs to form the factors of a
+// trilinear element itself: [Ar[c][b][d]] [As[c][a][d]] [At[b][a][d]], with
+// Ar[c][b] = (X[c][b][1] - X[c][b][0]) / 2 along r at s-corner b and t-corner c,
+// As[c][a] = (X[c][1][a] - X[c][0][a]) / 2, At[b][a] = (X[1][b][a] - X[0][b][a]) / 2.
+std::vector<double> trilinear_edges(const sem_box_mesh &mesh) {
+  const int64_t E = (int64_t)mesh.nex * mesh.ney * mesh.nez;
+  std::vector<double> out((size_t)E * 36);
+  for (int64_t e = 0; e < E; ++e) {
+    const int ex = (int)(e % mesh.nex), ey = (int)((e / mesh.nex) % mesh.ney),
+              ez = (int)(e / ((int64_t)mesh.nex * mesh.ney));
+    auto X = [&](int ck, int cj, int ci, int d) {
+      return mesh.vertex_xyz[3 * vidx(mesh, ex + ci, ey + cj, ez + ck) + d];
+    };
+    double *o = &out[(size_t)e * 36];
+    for (int p = 0; p < 2; ++p)
+      for (int q = 0; q < 2; ++q)
+        for (int d = 0; d < 3; ++d) {
+          o[(p * 2 + q) * 3 + d] = 0.5 * (X(p, q, 1, d) - X(p, q, 0, d));       // Ar[c=p][b=q]
+          o[12 + (p * 2 + q) * 3 + d] = 0.5 * (X(p, 1, q, d) - X(p, 0, q, d));  // As[c=p][a=q]
+          o[24 + (p * 2 + q) * 3 + d] = 0.5 * (X(1, p, q, d) - X(0, p, q, d));  // At[b=p][a=q]
+        }
+  }
+  return out;
+}
+
 // ------------------------------------------------------------------ FD hierarchy
 static Csr csr_from_map(int64_t nrows, int64_t ncols, std::vector<std::map<int32_t, double>> &rows) {
   Csr A;

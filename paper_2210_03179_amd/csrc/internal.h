@@ -36,6 +36,7 @@ struct BoxLevelHost {
 };
 // Returns SEM_EMESH on a non-positive Jacobian.
 sem_status build_box_level(const sem_box_mesh &mesh, int N, BoxLevelHost &out, std::string &err);
+std::vector<double> trilinear_edges(const sem_box_mesh &mesh);
 // Assembled order-1 operator in CSR (rows = n).
 struct Csr {
   int64_t nrows = 0, ncols = 0;
@@ -105,6 +106,10 @@ struct Level {
   // SEM
   double *G64 = nullptr;      // [E][6][n1^3]
   uint16_t *Gbf = nullptr;    // bf16 copy (mixed precision)
+  // trilinear geometry computed in the operator instead of G: per element 36 half edge
+  // vectors, and the GLL nodes then weights of this order (both precisions as needed)
+  double *tri64 = nullptr, *gxw64 = nullptr;
+  float *tri32 = nullptr, *gxw32 = nullptr;
   double *D64 = nullptr;      // (N+1)^2
   float *D32 = nullptr;
   double *J64 = nullptr;      // interpolation from the next level, (N+1) x (Nc+1)
@@ -134,6 +139,7 @@ constexpr int kGmresScalars = 2 * 32 + 2;  // projections (<= 32), ||w||^2, y (<
 // planes for FP64 factors at N = 7 (other FP64 orders launch variant 0 for it)
 constexpr int kAxVariants = 6;
 constexpr int kAxVariants64 = 6;
+constexpr int kAxTriVariants = 2;  // trilinear operator: AxShape::min_waves or 1 wave per SIMD
 
 struct CoarseSolver {
   bool dense = true;
@@ -145,6 +151,11 @@ struct CoarseSolver {
   int mid = 0;
   std::vector<double *> Mb, Lb, Wb;
   double *Xtop = nullptr, *Xbot = nullptr;
+  // single-precision copies of the same blocks, read by the mixed-precision cycle
+  bool has32 = false;
+  float *Minv32 = nullptr;
+  std::vector<float *> Mb32, Lb32, Wb32;
+  float *Xtop32 = nullptr, *Xbot32 = nullptr;
   double *b = nullptr, *y = nullptr, *x = nullptr, *t = nullptr;
   std::vector<double> host_dense;  // small problems: assembled matrix for inspection
 };

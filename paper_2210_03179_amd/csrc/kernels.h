@@ -58,10 +58,11 @@ void launch_gemv(int64_t nrows, int64_t ncols, const double *M, const double *x,
 // Up to two independent products in one launch, one 256-thread block per output row:
 // y[r] = (b ? b[r] : 0) + sum_s sign_s * (M_s[r, :] . x_s), M_s dense row-major with ncols columns.
 struct GemvSeg {
-  const double *M;
+  const double *M;  // row-major nrows x ncols, or
   const double *x;
   int64_t ncols;
   double sign;
+  const float *M32 = nullptr;  // the same matrix stored in single precision (M unused)
 };
 struct GemvJob {
   const double *b;

@@ -33,6 +33,15 @@ ax_local_kernel(Box b, int64_t E, const T *__restrict__ u, const GT *__restrict_
   else ax_body<N, T, GT, PF>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
 }
 
+// Operator of trilinear elements with factors computed in the kernel (ax_body_tri);
+// OCC as above (variant 0: AxShape::min_waves, variant 1: 1).
+template <int N, typename T, int OCC>
+__global__ void __launch_bounds__(AxShape<N>::block, OCC)
+ax_tri_kernel(Box b, int64_t E, const T *__restrict__ u, const T *__restrict__ tri, const T *__restrict__ gxw,
+              const T *__restrict__ Dm, T *__restrict__ wL) {
+  ax_body_tri<N, T>(xcd_block(blockIdx.x, gridDim.x), b, E, u, tri, gxw, Dm, wL);
+}
+
 // ------------------------------------------------------------------ summation / vector kernels
 template <typename T>
 __global__ void dss_kernel(Box b, int64_t n, const T *__restrict__ wL, T *__restrict__ out) {
@@ -665,18 +674,40 @@ __global__ void __launch_bounds__(256) gemv_jobs_kernel(const GemvJobs J) {
   for (int q = 0; q < 3; ++q) {
     if (q >= jb.nseg) break;
     const GemvSeg g = jb.seg[q];
-    const double *Mr = g.M + row * g.ncols;
+    const int64_t last = g.ncols - 1;
     double part = 0.0;
-    for (int64_t c0 = 0; c0 < g.ncols; c0 += 64 * kRowUnroll) {
-      double mv[kRowUnroll], xv[kRowUnroll];
+    // loads are unconditional (past the end: the row's last entry, weighted by 0 when
+    // summed) so a whole chunk of the row is in flight without a branch or wait per load
+    if (g.M32) {  // wave-uniform: single-precision storage, double products and sums
+      const float *Mr = g.M32 + row * g.ncols;
+      for (int64_t c0 = 0; c0 < g.ncols; c0 += 64 * kRowUnroll) {
+        float mv[kRowUnroll];
+        double xv[kRowUnroll];
 #pragma unroll
-      for (int u = 0; u < kRowUnroll; ++u) {
-        const int64_t c = c0 + lane + 64 * u;
-        mv[u] = c < g.ncols ? Mr[c] : 0.0;
-        xv[u] = c < g.ncols ? g.x[c] : 0.0;
+        for (int u = 0; u < kRowUnroll; ++u) {
+          const int64_t c = c0 + lane + 64 * u;
+          const int64_t cc = c < last ? c : last;
+          mv[u] = Mr[cc];
+          xv[u] = g.x[cc];
+        }
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u)
+          part += (c0 + lane + 64 * u <= last ? 1.0 : 0.0) * ((double)mv[u] * xv[u]);
       }
+    } else {
+      const double *Mr = g.M + row * g.ncols;
+      for (int64_t c0 = 0; c0 < g.ncols; c0 += 64 * kRowUnroll) {
+        double mv[kRowUnroll], xv[kRowUnroll];
 #pragma unroll
-      for (int u = 0; u < kRowUnroll; ++u) part += mv[u] * xv[u];
+        for (int u = 0; u < kRowUnroll; ++u) {
+          const int64_t c = c0 + lane + 64 * u;
+          const int64_t cc = c < last ? c : last;
+          mv[u] = Mr[cc];
+          xv[u] = g.x[cc];
+        }
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) part += (c0 + lane + 64 * u <= last ? 1.0 : 0.0) * (mv[u] * xv[u]);
+      }
     }
     acc += g.sign * part;
   }
@@ -1189,6 +1220,33 @@ void launch_ax_n(const Level &L, const T *u, const GT *G, const T *D, T *wL, int
                        D, wL);
 }
 
+template <int N, typename T>
+void launch_ax_tri_n(const Level &L, const T *u, const T *tri, const T *gxw, const T *D, T *wL, int variant,
+                     hipStream_t s) {
+  using S = AxShape<N>;
+  const unsigned grid = (unsigned)((L.E + S::epb - 1) / S::epb);
+  if (variant == 1)
+    hipLaunchKernelGGL((ax_tri_kernel<N, T, 1>), dim3(grid), dim3(S::block), 0, s, mkbox(L), L.E, u, tri, gxw, D,
+                       wL);
+  else
+    hipLaunchKernelGGL((ax_tri_kernel<N, T, S::min_waves>), dim3(grid), dim3(S::block), 0, s, mkbox(L), L.E, u, tri,
+                       gxw, D, wL);
+}
+
+template <typename T>
+bool launch_ax_tri(const Level &L, const T *u, const T *tri, const T *gxw, const T *D, T *wL, hipStream_t s) {
+  const int variant = sizeof(T) == 8 ? L.ax_variant64 : L.ax_variant32;
+  switch (L.N) {
+#define SEMCHEB_AXT_CASE(n) \
+  case n: launch_ax_tri_n<n, T>(L, u, tri, gxw, D, wL, variant, s); return true;
+    SEMCHEB_AXT_CASE(1) SEMCHEB_AXT_CASE(2) SEMCHEB_AXT_CASE(3) SEMCHEB_AXT_CASE(4)
+    SEMCHEB_AXT_CASE(5) SEMCHEB_AXT_CASE(6) SEMCHEB_AXT_CASE(7) SEMCHEB_AXT_CASE(8)
+    SEMCHEB_AXT_CASE(9) SEMCHEB_AXT_CASE(10) SEMCHEB_AXT_CASE(11) SEMCHEB_AXT_CASE(12)
+#undef SEMCHEB_AXT_CASE
+    default: return false;
+  }
+}
+
 template <typename T, typename GT>
 bool launch_ax_t(const Level &L, const T *u, const GT *G, const T *D, T *wL, hipStream_t s) {
   const int variant = sizeof(T) == 8 ? L.ax_variant64 : L.ax_variant32;
@@ -1214,9 +1272,11 @@ void launch_adj_n(const Level &L, const double *lam, const double *u, double *dG
 
 // ------------------------------------------------------------------ launchers
 bool launch_ax(const Level &L, const double *u, double *wL, hipStream_t s) {
+  if (L.tri64) return launch_ax_tri<double>(L, u, L.tri64, L.gxw64, L.D64, wL, s);
   return launch_ax_t<double, double>(L, u, L.G64, L.D64, wL, s);
 }
 bool launch_ax(const Level &L, const float *u, float *wL, hipStream_t s) {
+  if (L.tri32) return launch_ax_tri<float>(L, u, L.tri32, L.gxw32, L.D32, wL, s);
   return launch_ax_t<float, uint16_t>(L, u, L.Gbf, L.D32, wL, s);
 }
 

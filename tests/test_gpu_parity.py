@@ -297,6 +297,26 @@ def test_blocked_coarse_solve_parity(small_case, planes):
     assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
 
 
+def test_mixed_cycle_single_precision_coarse_factors(small_case, monkeypatch):
+    # the mixed cycle reads single-precision copies of the coarse factor blocks: the dense inverse
+    # (planes = 0 on this small mesh) and the two-ended block elimination (1 or 2 planes per block)
+    # are different factorizations of one matrix, so their cycles differ only by the rounding of
+    # the stored factors; all three stay within the mixed cycle's BF16 accuracy of the FP64 oracle
+    monkeypatch.setenv("SEMCHEB_AX_VARIANT", "0")  # the same operator kernel in all three
+    V, N, lmax = small_case
+    ref = mg.sem_hierarchy(V, N, cheb.CHEB4, 2, 2, lmax=lmax)
+    r = wl.uniform_noise(ref.levels[0].n, 6)
+    zo = ref.vcycle(r)
+    zs = []
+    for planes in (0, 1, 2):
+        s = SemSolver(V, N=N, smoother="cheb4", pre=2, post=2, lambda_max=lmax, coarse_planes=planes,
+                      precision="mixed")
+        zs.append(host(s.vcycle(dev(r))))
+        assert np.linalg.norm(zs[-1] - zo) <= 1e-2 * np.linalg.norm(zo), planes
+    for z in zs[1:]:
+        assert np.linalg.norm(z - zs[0]) <= 1e-5 * np.linalg.norm(zs[0])
+
+
 @pytest.mark.parametrize("nz,planes", [(9, 1), (8, 1), (9, 3), (6, 2)])
 def test_blocked_coarse_solve_block_counts(nz, planes):
     # two-ended block elimination with an even (8) and odd (7, 3) number of blocks and a

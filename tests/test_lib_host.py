@@ -173,3 +173,14 @@ def test_set_smoothing_validation_and_mg_option():
         assert ex.value.status == L.SEM_EINVAL
     with pytest.raises(L.SemError):
         FdSolver(n=16, factor=2, coarsest_n=2, device=-1, lambda_max=[1, 1, 1], krylov=7)
+
+
+def test_geometry_option_validation():
+    V = wl.deformed_box(2, 0.05)
+    s = SemSolver(V, N=4, geometry="trilinear", device=-1, lambda_max=[1.0, 1.0])
+    assert s.num_levels == 3
+    with pytest.raises(L.SemError) as ex:
+        SemSolver(V, N=4, geometry=5, device=-1, lambda_max=[1.0, 1.0])
+    assert ex.value.status == L.SEM_EINVAL
+    o = L.make_options(device=-1)
+    assert o.geometry == 0  # stored factors by default
