@@ -396,6 +396,17 @@ def main():
         log(f"trilinear geometry: {out['trilinear_geometry']}")
         stm.close()
         st64.close()
+    if not args.no_trilinear:
+        # option: the mixed cycle's coarse solve reads FP32 copies of its factor blocks (FP64
+        # vectors, products and sums); the headline keeps FP64 factors
+        scs = SemSolver(V, N=N, smoother="cheb4opt", pre=4, post=0, precision="mixed", coarse_storage="mixed",
+                        lambda_max=smx.lambda_max())
+        ucs, infocs, dtcs, _, _ = time_solves(scs, b, max(1, args.steps // 2), 1)
+        out["mixed_fp32_coarse_factors"] = {"ms_per_solve": round(dtcs * 1e3, 4), "iterations": infocs.iterations,
+                                            "gdof_iter_per_s": round(n * infocs.iterations / dtcs / 1e9, 4),
+                                            "true_relres": true_rel(ucs)}
+        log(f"mixed, FP32 coarse factors: {out['mixed_fp32_coarse_factors']}")
+        scs.close()
     if not args.no_batched:
         log("batched systems ...")
         out["batched"] = bench_batched(max(1, args.steps // 2))

@@ -116,6 +116,9 @@ typedef struct {
   int32_t gmres_restart;            /* m of GMRES(m), 1..32; 0 = 30 */
   int32_t schwarz;                  /* smoother inside Chebyshev: SEM_JACOBI, SEM_ASM or SEM_RAS */
   int32_t geometry;                 /* SEM_GEOM_STORED or SEM_GEOM_TRILINEAR */
+  int32_t coarse_storage;           /* coarse factor blocks read by a SEM_MIXED cycle: SEM_FP64
+                                       (default) or SEM_MIXED (FP32 copies; FP64 vectors, products
+                                       and sums); FP64 contexts accept SEM_FP64 only */
 } sem_options;
 
 /* Structured hexahedral box mesh: (nex+1)(ney+1)(nez+1) vertices, x fastest.
@@ -128,7 +131,7 @@ typedef struct {
 
 /* Fills *opt with: N = 7, default schedule, SEM_CHEB4_OPT, (4,0), FP64,
  * SEM_FCG, estimated lambda_max, lambda_scale 1, device 0, GMRES restart 30,
- * Jacobi smoothing, stored geometric factors. */
+ * Jacobi smoothing, stored geometric factors, FP64 coarse factors. */
 void sem_options_default(sem_options *opt);
 
 /* Set up the SEM hierarchy on a box mesh: GLL data, geometric factors, Jacobi

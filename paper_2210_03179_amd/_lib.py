@@ -39,7 +39,7 @@ class SemOptions(C.Structure):
         ("precision", C.c_int32), ("krylov", C.c_int32), ("num_lambda_max", C.c_int32),
         ("lambda_max", C.c_double * MAX_LEVELS), ("lambda_scale", C.c_double), ("device", C.c_int32),
         ("coarse_planes", C.c_int32), ("gmres_restart", C.c_int32), ("schwarz", C.c_int32),
-        ("geometry", C.c_int32),
+        ("geometry", C.c_int32), ("coarse_storage", C.c_int32),
     ]
 
 
@@ -118,7 +118,7 @@ def check(status: int, ctx=None) -> int:
 
 def make_options(N=7, smoother="cheb4opt", pre=4, post=0, precision="fp64", krylov="fcg",
                  orders=None, lambda_max=None, lambda_scale=1.0, device=0, coarse_planes=0,
-                 restart=30, schwarz=None, geometry="stored") -> SemOptions:
+                 restart=30, schwarz=None, geometry="stored", coarse_storage="fp64") -> SemOptions:
     lib = load()
     o = SemOptions()
     lib.sem_options_default(C.byref(o))
@@ -141,4 +141,5 @@ def make_options(N=7, smoother="cheb4opt", pre=4, post=0, precision="fp64", kryl
     o.gmres_restart = int(restart)
     o.schwarz = SCHWARZ[schwarz] if (schwarz is None or isinstance(schwarz, str)) else int(schwarz)
     o.geometry = GEOMETRY[geometry] if isinstance(geometry, str) else int(geometry)
+    o.coarse_storage = PRECISIONS[coarse_storage] if isinstance(coarse_storage, str) else int(coarse_storage)
     return o

@@ -121,6 +121,10 @@ sem_status validate_common(const sem_options *o, std::string &err) {
     err = "unknown geometry option";
     return SEM_EINVAL;
   }
+  if (o->coarse_storage != SEM_FP64 && !(o->coarse_storage == SEM_MIXED && o->precision == SEM_MIXED)) {
+    err = "coarse_storage must be SEM_FP64, or SEM_MIXED with a mixed-precision cycle";
+    return SEM_EINVAL;
+  }
   if (o->gmres_restart < 0 || o->gmres_restart > kMaxRestart) {
     err = "gmres_restart must lie in 0..32 (0 = 30)";
     return SEM_EINVAL;
@@ -1002,11 +1006,11 @@ sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipS
     TRY(dalloc(c, &C.x, C.n));
     TRY(dalloc(c, &C.y, C.n));
     TRY(dalloc(c, &C.t, C.n));
-    // the mixed-precision cycle reads single-precision copies of the factor blocks (half the
-    // bytes of this latency- and bandwidth-bound chain); products and sums stay FP64
-    C.has32 = mixed;
+    // on request the mixed-precision cycle reads single-precision copies of the factor blocks
+    // (half the bytes of this latency- and bandwidth-bound chain); products and sums stay FP64
+    C.has32 = mixed && opt->coarse_storage == SEM_MIXED;
     auto up32 = [&](float **dst, const std::vector<double> &src) -> sem_status {
-      if (!mixed || src.empty()) return SEM_OK;
+      if (!C.has32 || src.empty()) return SEM_OK;
       std::vector<float> f(src.begin(), src.end());
       return upload(c, dst, f.data(), f.size(), s);
     };
@@ -1192,6 +1196,7 @@ void sem_options_default(sem_options *o) {
   o->gmres_restart = 30;
   o->schwarz = SEM_JACOBI;
   o->geometry = SEM_GEOM_STORED;
+  o->coarse_storage = SEM_FP64;
 }
 
 sem_status sem_setup_box(const sem_box_mesh *mesh, const sem_options *opt, void *stream, sem_ctx **out) {

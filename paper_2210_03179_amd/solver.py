@@ -140,11 +140,13 @@ class SemSolver(_Base):
     schwarz: None (Jacobi), "asm" or "ras": the basic smoother inside the Chebyshev algorithms.
     krylov: "pcg", "fcg", "gmres" (GMRES(restart)) or "mg" (multigrid as the solver).
     geometry: "stored" (factors read from HBM) or "trilinear" (formed in the operator).
+    coarse_storage: "fp64" or, with precision="mixed", "mixed" (the cycle reads FP32 copies of the
+    coarse factor blocks).
     """
 
     def __init__(self, verts, N=7, smoother="cheb4opt", pre=4, post=0, precision="fp64",
                  krylov="fcg", orders=None, lambda_max=None, lambda_scale=1.0, device=0,
-                 coarse_planes=0, restart=30, schwarz=None, geometry="stored"):
+                 coarse_planes=0, restart=30, schwarz=None, geometry="stored", coarse_storage="fp64"):
         super().__init__()
         verts = np.ascontiguousarray(np.asarray(verts, dtype=np.float64))
         if verts.ndim != 4 or verts.shape[3] != 3:
@@ -153,7 +155,7 @@ class SemSolver(_Base):
         mesh = L.SemBoxMesh(verts.shape[2] - 1, verts.shape[1] - 1, verts.shape[0] - 1,
                             verts.ctypes.data_as(C.POINTER(C.c_double)))
         opt = L.make_options(N, smoother, pre, post, precision, krylov, orders, lambda_max,
-                             lambda_scale, device, coarse_planes, restart, schwarz, geometry)
+                             lambda_scale, device, coarse_planes, restart, schwarz, geometry, coarse_storage)
         ctx = C.c_void_p()
         stream = _stream() if device >= 0 else C.c_void_p(0)
         L.check(self._lib.sem_setup_box(C.byref(mesh), C.byref(opt), stream, C.byref(ctx)))

@@ -298,7 +298,8 @@ def test_blocked_coarse_solve_parity(small_case, planes):
 
 
 def test_mixed_cycle_single_precision_coarse_factors(small_case, monkeypatch):
-    # the mixed cycle reads single-precision copies of the coarse factor blocks: the dense inverse
+    # with coarse_storage="mixed" the mixed cycle reads single-precision copies of the coarse
+    # factor blocks: the dense inverse
     # (planes = 0 on this small mesh) and the two-ended block elimination (1 or 2 planes per block)
     # are different factorizations of one matrix, so their cycles differ only by the rounding of
     # the stored factors; all three stay within the mixed cycle's BF16 accuracy of the FP64 oracle
@@ -310,7 +311,7 @@ def test_mixed_cycle_single_precision_coarse_factors(small_case, monkeypatch):
     zs = []
     for planes in (0, 1, 2):
         s = SemSolver(V, N=N, smoother="cheb4", pre=2, post=2, lambda_max=lmax, coarse_planes=planes,
-                      precision="mixed")
+                      precision="mixed", coarse_storage="mixed")
         zs.append(host(s.vcycle(dev(r))))
         assert np.linalg.norm(zs[-1] - zo) <= 1e-2 * np.linalg.norm(zo), planes
     for z in zs[1:]:

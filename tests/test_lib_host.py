@@ -183,4 +183,8 @@ def test_geometry_option_validation():
         SemSolver(V, N=4, geometry=5, device=-1, lambda_max=[1.0, 1.0])
     assert ex.value.status == L.SEM_EINVAL
     o = L.make_options(device=-1)
-    assert o.geometry == 0  # stored factors by default
+    assert o.geometry == 0 and o.coarse_storage == 0  # stored factors, FP64 coarse factors by default
+    with pytest.raises(L.SemError) as ex:   # FP32 coarse factors belong to a mixed cycle
+        SemSolver(V, N=4, coarse_storage="mixed", device=-1, lambda_max=[1.0, 1.0])
+    assert ex.value.status == L.SEM_EINVAL
+    SemSolver(V, N=4, precision="mixed", coarse_storage="mixed", device=-1, lambda_max=[1.0, 1.0])
