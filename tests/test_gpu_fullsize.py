@@ -1,0 +1,108 @@
+"""Parity at the full sizes of the measured workloads, in the launch configuration bench.py
+times (32^3 elements, N = 7, opt. 4th-kind (4,0) one-sided cycle; the 64 uneven batched
+systems).
+
+At these sizes the oracle applies the operator (full vectors) but does not run cycles or
+solves, so the cycle and the solvers are checked through properties that hold at any size:
+- operator: the GPU A u equals the oracle's, element by element, stored and trilinear
+  factors;
+- solves: the true FP64 residual b - A u of the FP64 and the mixed solutions, evaluated with
+  the oracle's operator, meets 1e-8; the mixed solve needs at most one iteration more and
+  agrees with the FP64 solution to single-precision level;
+- the symmetric (2,2) FP64 cycle is a symmetric operator (r2 . M r1 = r1 . M r2);
+- batched: every system's true residual (GPU FP64 operator of its own context, and the
+  oracle's operator on sampled systems) meets 1e-8.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workload as wl
+from oracle.sem import SemBox
+from paper_2210_03179_amd import _lib as L
+from paper_2210_03179_amd.solver import BatchedSolver, SemSolver
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.fixture(scope="module")
+def cfg3():
+    print("building the 32^3, N = 7 oracle box", flush=True)
+    V = wl.deformed_box(32, 0.05)
+    box = SemBox(V, 7)
+    b0 = box.mass() * wl.manufactured_load(box.coords())
+    b = b0 + 1e-3 * np.max(np.abs(b0)) * wl.uniform_noise(box.n, 0)
+    return V, box, b
+
+
+def test_cfg3_operator_full_size(cfg3):
+    V, box, _ = cfg3
+    u = wl.uniform_noise(box.n, 11)
+    ref = box.apply(u)
+    s = SemSolver(V, N=7)
+    w = s.apply_A(dev(u)).cpu().numpy()
+    assert np.max(np.abs(w - ref)) <= 1e-14 * 64 * np.max(np.abs(ref))
+    del s
+    st = SemSolver(V, N=7, geometry="trilinear", lambda_max=[2.0, 2.0])
+    wt = st.apply_A(dev(u)).cpu().numpy()
+    assert np.max(np.abs(wt - ref)) <= 1e-13 * 64 * np.max(np.abs(ref))
+
+
+def test_cfg3_solves_full_size(cfg3):
+    V, box, b = cfg3
+    bn = np.linalg.norm(b)
+    s64 = SemSolver(V, N=7, smoother="cheb4opt", pre=4, post=0, precision="fp64", krylov="fcg")
+    u64, info64 = s64.solve(dev(b), rtol=1e-8, maxit=100)
+    smx = SemSolver(V, N=7, smoother="cheb4opt", pre=4, post=0, precision="mixed", krylov="fcg",
+                    lambda_max=s64.lambda_max())
+    umx, infomx = smx.solve(dev(b), rtol=1e-8, maxit=100)
+    assert info64.converged and infomx.converged
+    x64, xmx = u64.cpu().numpy(), umx.cpu().numpy()
+    r64 = np.linalg.norm(b - box.apply(x64)) / bn
+    rmx = np.linalg.norm(b - box.apply(xmx)) / bn
+    print(f"32^3 N=7: fp64 {info64.iterations} its true {r64:.2e}; mixed {infomx.iterations} its true {rmx:.2e}",
+          flush=True)
+    assert r64 <= 1.01e-8 and rmx <= 1.01e-8
+    assert abs(r64 - info64.relres) <= 1e-11     # recurrence residual tracks the true one
+    assert infomx.iterations <= info64.iterations + 1
+    assert np.linalg.norm(xmx - x64) <= 1e-7 * np.linalg.norm(x64)
+
+
+def test_cfg3_symmetric_cycle_full_size(cfg3):
+    V, box, _ = cfg3
+    s = SemSolver(V, N=7, smoother="cheb4", pre=2, post=2, lambda_max=[2.46, 2.23])
+    r1, r2 = dev(wl.uniform_noise(box.n, 21)), dev(wl.uniform_noise(box.n, 22))
+    a = float(torch.dot(r2, s.vcycle(r1)))
+    c = float(torch.dot(r1, s.vcycle(r2)))
+    assert abs(a - c) <= 1e-12 * max(abs(a), abs(c))
+    assert float(torch.dot(r1, s.vcycle(r1))) > 0.0
+
+
+def test_cfg4_batched_full_size():
+    specs = wl.batched_specs(64, 1000)
+    verts = [wl.batched_box(sp.m, sp.mesh_seed) for sp in specs]
+    singles = [SemSolver(V, N=sp.N, smoother="cheb4opt", pre=4, post=0, precision="fp64")
+               for V, sp in zip(verts, specs)]
+    rhs = []
+    for s, sp in zip(singles, specs):
+        f = wl.manufactured_load(s.coords().cpu().numpy())
+        b0 = s.mass_apply(dev(f)).cpu().numpy()
+        rhs.append(b0 + 1e-3 * np.max(np.abs(b0)) * wl.uniform_noise(s.n, sp.rhs_seed))
+    bs = BatchedSolver(verts, [sp.N for sp in specs], smoother="cheb4opt", pre=4, post=0, krylov="fcg")
+    u, st, its, rel = bs.solve(dev(np.concatenate(rhs)), rtol=1e-8, maxit=200)
+    assert st == L.SEM_OK
+    worst = 0.0
+    for q, (s, bq) in enumerate(zip(singles, rhs)):
+        uq = u[bs.offsets[q]:bs.offsets[q + 1]].contiguous()
+        bqd = dev(bq)
+        worst = max(worst, float(torch.linalg.vector_norm(bqd - s.apply_A(uq)) / torch.linalg.vector_norm(bqd)))
+    print(f"64 batched systems: iterations {min(its)}..{max(its)}, worst true residual {worst:.2e}", flush=True)
+    assert worst <= 1.01e-8
+    for q in (0, 17, 42):   # the oracle's operator on sampled systems
+        bx = SemBox(verts[q], specs[q].N)
+        uq = u[bs.offsets[q]:bs.offsets[q + 1]].cpu().numpy()
+        assert np.linalg.norm(rhs[q] - bx.apply(uq)) <= 1.01e-8 * np.linalg.norm(rhs[q]), q
