@@ -16,14 +16,22 @@ namespace dev {
 __device__ __forceinline__ float bf16_to_float(uint16_t h) {
   return __uint_as_float(((uint32_t)h) << 16);
 }
+// Geometric factors are streamed exactly once per operator launch: non-temporal loads
+// keep them from displacing the vectors (u, w) that other kernels reuse from cache.
 template <typename GT, typename T>
 __device__ __forceinline__ T load_factor(const GT *p);
 template <>
-__device__ __forceinline__ double load_factor<double, double>(const double *p) { return *p; }
+__device__ __forceinline__ double load_factor<double, double>(const double *p) {
+  return __builtin_nontemporal_load(p);
+}
 template <>
-__device__ __forceinline__ float load_factor<uint16_t, float>(const uint16_t *p) { return bf16_to_float(*p); }
+__device__ __forceinline__ float load_factor<uint16_t, float>(const uint16_t *p) {
+  return bf16_to_float(__builtin_nontemporal_load(p));
+}
 template <>
-__device__ __forceinline__ float load_factor<float, float>(const float *p) { return *p; }
+__device__ __forceinline__ float load_factor<float, float>(const float *p) { return __builtin_nontemporal_load(p); }
+// cache-policy operand of the global-to-LDS loads for the same streams (non-temporal)
+constexpr int kFactorCpol = 2;
 
 // ------------------------------------------------------------------ box geometry helpers
 // Division by the (small) element order with a precomputed multiply-high reciprocal
@@ -635,8 +643,8 @@ __device__ __forceinline__ void ax_body_dma(unsigned blk, const Box &b, int64_t 
       if (c0 + lane < nchunks) {
         const void *gp = src + (int64_t)(c0 + lane) * kChunk;
         auto *lp = (__attribute__((address_space(3))) void *)(reinterpret_cast<char *>(sG) + c0 * kChunk);
-        if constexpr (kChunk == 16) __builtin_amdgcn_global_load_lds(gp, lp, 16, 0, 0);
-        else __builtin_amdgcn_global_load_lds(gp, lp, 4, 0, 0);
+        if constexpr (kChunk == 16) __builtin_amdgcn_global_load_lds(gp, lp, 16, 0, kFactorCpol);
+        else __builtin_amdgcn_global_load_lds(gp, lp, 4, 0, kFactorCpol);
       }
     }
   }
@@ -739,7 +747,8 @@ __device__ __forceinline__ void ax_body_ring64(unsigned blk, const Box &b, int64
 #pragma unroll
     for (int p = 0; p < 3; ++p)
       __builtin_amdgcn_global_load_lds(gsrc + (int64_t)(2 * p) * (n3 * 8) + (int64_t)k * (n2 * 8),
-                                       (__attribute__((address_space(3))) void *)(dst + p * 1024), 16, 0, 0);
+                                       (__attribute__((address_space(3))) void *)(dst + p * 1024), 16, 0,
+                                       kFactorCpol);
   };
 #pragma unroll
   for (int k = 0; k < kRing; ++k) issue(k);
