@@ -620,10 +620,11 @@ sem_status autotune_operator(sem_ctx *c, hipStream_t s) {
   HIPCHK(c, hipEventCreate(&e1));
   const bool mixed = c->opt.precision == SEM_MIXED;
   HIPCHK(c, hipMemsetAsync(c->kr, 0, c->levels[0].n * sizeof(double), s));
-  // three interleaved rounds of (one warm-up + three timed launches) per variant; a
-  // variant's time is its best round, so clock ramps and other transients during setup
-  // do not decide the choice
-  const int reps = 3, rounds = 3;
+  // five interleaved rounds of (one warm-up + a timed batch) per variant; a variant's time
+  // is its best round, so clock ramps and other transients during setup do not decide the
+  // choice. A batch is three launches, or as many as make it last about 300 us (small
+  // levels: a 10 us kernel is otherwise timed at the resolution of the events)
+  const int rounds = 5;
   sem_status st = SEM_OK;
   for (size_t j = 0; j + 1 < c->levels.size() && st == SEM_OK; ++j) {
     Level &L = c->levels[j];
@@ -635,6 +636,7 @@ sem_status autotune_operator(sem_ctx *c, hipStream_t s) {
       const int nvar = trilinear ? kAxTriVariants : (fp64 ? kAxVariants64 : kAxVariants);
       float *times = fp64 ? L.ax_time64_us : L.ax_time32_us;
       for (int v = 0; v < kAxVariants; ++v) times[v] = v < nvar ? 1e30f : -1.0f;
+      int reps = 3;
       for (int round = 0; round < rounds && st == SEM_OK; ++round) {
         for (int v = 0; v < nvar; ++v) {
           int &var = fp64 ? L.ax_variant64 : L.ax_variant32;
@@ -653,7 +655,9 @@ sem_status autotune_operator(sem_ctx *c, hipStream_t s) {
           }
           float ms = 0;
           hipEventElapsedTime(&ms, e0, e1);
-          times[v] = std::min(times[v], ms * 1000.0f / reps);
+          const float us = ms * 1000.0f / reps;
+          times[v] = std::min(times[v], us);
+          if (round == 0 && v == 0) reps = std::max(3, std::min(200, (int)std::ceil(300.0f / std::max(us, 0.5f))));
         }
       }
       const float *tt = fp64 ? L.ax_time64_us : L.ax_time32_us;

@@ -677,7 +677,8 @@ __global__ void __launch_bounds__(256) gemv_jobs_kernel(const GemvJobs J) {
     const int64_t last = g.ncols - 1;
     double part = 0.0;
     // loads are unconditional (past the end: the row's last entry, weighted by 0 when
-    // summed) so a whole chunk of the row is in flight without a branch or wait per load
+    // summed) so a whole chunk of the row is in flight without a branch or wait per load;
+    // the factor blocks are streamed once per solve (non-temporal), x is shared by all rows
     if (g.M32) {  // wave-uniform: single-precision storage, double products and sums
       const float *Mr = g.M32 + row * g.ncols;
       for (int64_t c0 = 0; c0 < g.ncols; c0 += 64 * kRowUnroll) {
@@ -687,7 +688,7 @@ __global__ void __launch_bounds__(256) gemv_jobs_kernel(const GemvJobs J) {
         for (int u = 0; u < kRowUnroll; ++u) {
           const int64_t c = c0 + lane + 64 * u;
           const int64_t cc = c < last ? c : last;
-          mv[u] = Mr[cc];
+          mv[u] = __builtin_nontemporal_load(Mr + cc);
           xv[u] = g.x[cc];
         }
 #pragma unroll
@@ -702,7 +703,7 @@ __global__ void __launch_bounds__(256) gemv_jobs_kernel(const GemvJobs J) {
         for (int u = 0; u < kRowUnroll; ++u) {
           const int64_t c = c0 + lane + 64 * u;
           const int64_t cc = c < last ? c : last;
-          mv[u] = Mr[cc];
+          mv[u] = __builtin_nontemporal_load(Mr + cc);
           xv[u] = g.x[cc];
         }
 #pragma unroll
