@@ -69,6 +69,11 @@ def kernel_only(args):
     u32, w32 = u.float(), torch.empty(nloc, dtype=torch.float32, device="cuda")
     t64 = time_kernel(lambda: s64.apply_local(u, w), args.kernel_reps)
     tmx = time_kernel(lambda: smx.apply_local(u32, w32), args.kernel_reps)
+    # the same operator with factors formed in the kernel (trilinear geometry option)
+    st64 = SemSolver(V, N=args.order, precision="fp64", lambda_max=lam, geometry="trilinear")
+    stmx = SemSolver(V, N=args.order, precision="mixed", lambda_max=lam, geometry="trilinear")
+    tt64 = time_kernel(lambda: st64.apply_local(u, w), args.kernel_reps)
+    ttmx = time_kernel(lambda: stmx.apply_local(u32, w32), args.kernel_reps)
     # plain device copy of a known size (1 GiB read + 1 GiB written per launch): the reference
     # against which the profiler's FETCH_SIZE / WRITE_SIZE counters are scaled
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -78,7 +83,8 @@ def kernel_only(args):
                       "copy_bytes": 2 * src.numel() * 8, "copy_us": tcp * 1e6,
                       "copy_GBs": 2 * src.numel() * 8 / tcp / 1e9,
                       "ax_fp64_us": t64 * 1e6, "ax_fp64_GBs": (56.0 * nloc + 8.0 * n) / t64 / 1e9,
-                      "ax_bf16_us": tmx * 1e6, "ax_bf16_GBs": (16.0 * nloc + 4.0 * n) / tmx / 1e9}), flush=True)
+                      "ax_bf16_us": tmx * 1e6, "ax_bf16_GBs": (16.0 * nloc + 4.0 * n) / tmx / 1e9,
+                      "ax_trilinear_fp64_us": tt64 * 1e6, "ax_trilinear_fp32_us": ttmx * 1e6}), flush=True)
 
 
 def log(msg):
