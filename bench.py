@@ -396,8 +396,8 @@ def main():
             "ax_fp64_GBs": round((8.0 * n + 8.0 * nloc + 288.0 * E) / t_tax64 / 1e9, 1),
             "ax_fp32_us": round(t_tax32 * 1e6, 2),
             "ax_fp32_GBs": round((4.0 * n + 4.0 * nloc + 144.0 * E) / t_tax32 / 1e9, 1),
-            "variants_fp64_us": [round(x, 1) for x in st64.host_array("ax_tuning", 0)[1:3]],
-            "variants_fp32_us": [round(x, 1) for x in stm.host_array("ax_tuning", 0)[2 + nvar:4 + nvar]],
+            "variants_fp64_us": [round(x, 1) for x in st64.host_array("ax_tuning", 0)[1:4]],
+            "variants_fp32_us": [round(x, 1) for x in stm.host_array("ax_tuning", 0)[2 + nvar:5 + nvar]],
         }
         log(f"trilinear geometry: {out['trilinear_geometry']}")
         stm.close()

@@ -461,6 +461,90 @@ __device__ __forceinline__ void ax_body_tri(unsigned blk, const Box &b, int64_t 
   }
 }
 
+// ax_body_tri with the element's u tile in LDS (the structure of ax_body_tile): no
+// select-indexed register arrays, fewer VALU instructions per plane.
+template <int N, typename T>
+__device__ __forceinline__ void ax_body_tri_tile(unsigned blk, const Box &b, int64_t E, const T *__restrict__ u,
+                                                 const T *__restrict__ tri, const T *__restrict__ gxw,
+                                                 const T *__restrict__ Dm, T *__restrict__ wL) {
+  using S = AxShape<N>;
+  constexpr int n1 = S::n1, n3 = n1 * n1 * n1;
+  __shared__ T sD[n1 * n1];
+  __shared__ T su[S::epb][n1][n1][n1];
+  __shared__ T sr[S::epb][n1][n1];
+  __shared__ T ss[S::epb][n1][n1];
+  const int t = threadIdx.x;
+  const int le = t / S::tpe;
+  const int ij = t - le * S::tpe;
+  const int i = ij % n1, j = ij / n1;
+  const int64_t e = (int64_t)blk * S::epb + le;
+  const bool active = (le < S::epb) && (e < E);
+  const int lec = active ? le : 0;
+  for (int q = t; q < n1 * n1; q += S::block) sD[q] = Dm[q];
+
+  T ureg[n1], tt[n1];
+  int ex = 0, ey = 0, ez = 0;
+  if (active) {
+    const Exyz ec = elem_xyz(b, e);
+    ex = ec.x;
+    ey = ec.y;
+    ez = ec.z;
+  }
+  const int I = ex * N + i, J = ey * N + j;
+  const bool inIJ = active && I >= 1 && I <= b.nx && J >= 1 && J <= b.ny;
+  const int64_t gIJ = (int64_t)(I - 1) + (int64_t)b.nx * (J - 1);
+  const int64_t plane = (int64_t)b.nx * b.ny;
+#pragma unroll
+  for (int k = 0; k < n1; ++k) {
+    const int K = ez * N + k;
+    const bool ok = inIJ && K >= 1 && K <= b.nz;
+    const T v = u[ok ? gIJ + plane * (K - 1) : 0];
+    ureg[k] = ok ? v : T(0);
+    tt[k] = T(0);
+  }
+  const TriColumn<T> col = tri_column<N, T>(tri + (active ? e : 0) * 36, gxw, i, j);
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < n1; ++k) su[lec][k][j][i] = ureg[k];
+  }
+  __syncthreads();
+  T Di[n1];
+#pragma unroll
+  for (int l = 0; l < n1; ++l) Di[l] = sD[i * n1 + l];
+#pragma unroll 1
+  for (int k = 0; k < n1; ++k) {
+    T g0, g1, g2, g3, g4, g5;
+    tri_factors<T>(col, gxw[k], gxw[n1 + k], g0, g1, g2, g3, g4, g5);
+    T ur = 0, us = 0, ut = 0;
+#pragma unroll
+    for (int l = 0; l < n1; ++l) {
+      ur += Di[l] * su[lec][k][j][l];
+      us += sD[j * n1 + l] * su[lec][k][l][i];
+      ut += Dm[k * n1 + l] * ureg[l];  // wave-uniform: scalar loads
+    }
+    const T wr = g0 * ur + g1 * us + g2 * ut;
+    const T ws = g1 * ur + g3 * us + g4 * ut;
+    const T wt = g2 * ur + g4 * us + g5 * ut;
+    if (active) {
+      sr[lec][j][i] = wr;
+      ss[lec][j][i] = ws;
+    }
+    __syncthreads();
+    T acc = 0;
+#pragma unroll
+    for (int l = 0; l < n1; ++l) acc += sD[l * n1 + i] * sr[lec][j][l] + sD[l * n1 + j] * ss[lec][l][i];
+    if (active) su[lec][k][j][i] = acc;  // every read of plane k happened before the barrier
+#pragma unroll
+    for (int l = 0; l < n1; ++l) tt[l] += Dm[k * n1 + l] * wt;
+    __syncthreads();
+  }
+  if (active) {
+    T *we = wL + e * n3;
+#pragma unroll
+    for (int k = 0; k < n1; ++k) we[(k * n1 + j) * n1 + i] = su[lec][k][j][i] + tt[k];
+  }
+}
+
 // Same operator with the element's whole u tile resident in LDS: plane k of the tile
 // feeds the r and s derivatives and, once consumed, is overwritten by that plane's
 // r/s transpose contributions; the t-direction transpose accumulates in registers

@@ -139,7 +139,7 @@ constexpr int kGmresScalars = 2 * 32 + 2;  // projections (<= 32), ||w||^2, y (<
 // planes for FP64 factors at N = 7 (other FP64 orders launch variant 0 for it)
 constexpr int kAxVariants = 6;
 constexpr int kAxVariants64 = 6;
-constexpr int kAxTriVariants = 2;  // trilinear operator: AxShape::min_waves or 1 wave per SIMD
+constexpr int kAxTriVariants = 3;  // trilinear operator: (min_waves | 1 wave per SIMD) x register column, LDS tile
 
 struct CoarseSolver {
   bool dense = true;

@@ -33,13 +33,15 @@ ax_local_kernel(Box b, int64_t E, const T *__restrict__ u, const GT *__restrict_
   else ax_body<N, T, GT, PF>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
 }
 
-// Operator of trilinear elements with factors computed in the kernel (ax_body_tri);
-// OCC as above (variant 0: AxShape::min_waves, variant 1: 1).
-template <int N, typename T, int OCC>
+// Operator of trilinear elements with factors computed in the kernel; OCC as above and
+// TILE 0 (ax_body_tri, u column in registers) or 1 (ax_body_tri_tile, u tile in LDS).
+// Variants: 0 = (min_waves, 0), 1 = (1, 0), 2 = (min_waves, 1; FP64: 2 waves per SIMD).
+template <int N, typename T, int OCC, int TILE = 0>
 __global__ void __launch_bounds__(AxShape<N>::block, OCC)
 ax_tri_kernel(Box b, int64_t E, const T *__restrict__ u, const T *__restrict__ tri, const T *__restrict__ gxw,
               const T *__restrict__ Dm, T *__restrict__ wL) {
-  ax_body_tri<N, T>(xcd_block(blockIdx.x, gridDim.x), b, E, u, tri, gxw, Dm, wL);
+  if constexpr (TILE == 1) ax_body_tri_tile<N, T>(xcd_block(blockIdx.x, gridDim.x), b, E, u, tri, gxw, Dm, wL);
+  else ax_body_tri<N, T>(xcd_block(blockIdx.x, gridDim.x), b, E, u, tri, gxw, Dm, wL);
 }
 
 // ------------------------------------------------------------------ summation / vector kernels
@@ -1226,7 +1228,13 @@ void launch_ax_tri_n(const Level &L, const T *u, const T *tri, const T *gxw, con
                      hipStream_t s) {
   using S = AxShape<N>;
   const unsigned grid = (unsigned)((L.E + S::epb - 1) / S::epb);
-  if (variant == 1)
+  // the LDS-tile form keeps the u column and the t-transpose sums in registers: FP64 asks
+  // for 2 waves per SIMD so they fit without spilling
+  constexpr int kTileOcc = sizeof(T) == 8 ? 2 : S::min_waves;
+  if (variant == 2)
+    hipLaunchKernelGGL((ax_tri_kernel<N, T, kTileOcc, 1>), dim3(grid), dim3(S::block), 0, s, mkbox(L), L.E, u,
+                       tri, gxw, D, wL);
+  else if (variant == 1)
     hipLaunchKernelGGL((ax_tri_kernel<N, T, 1>), dim3(grid), dim3(S::block), 0, s, mkbox(L), L.E, u, tri, gxw, D,
                        wL);
   else

@@ -22,7 +22,7 @@ def dev(x):
 
 
 @pytest.mark.parametrize("N", list(range(1, 13)))
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_trilinear_operator_parity(N, variant, monkeypatch):
     print(f"trilinear operator N={N} variant {variant}", flush=True)
     monkeypatch.setenv("SEMCHEB_AX_VARIANT", str(variant))
@@ -77,6 +77,6 @@ def test_trilinear_has_no_stored_factors():
     assert ex.value.status == L.SEM_EINVAL
     tune = s.host_array("ax_tuning")
     per = 2 * (1 + 6)
-    for j in range(s.num_levels - 1):   # two variants timed, the others marked -1
+    for j in range(s.num_levels - 1):   # three variants timed, the others marked -1
         t64 = tune[j * per + 1: j * per + 7]
-        assert np.all(t64[:2] > 0) and np.all(t64[2:] == -1)
+        assert np.all(t64[:3] > 0) and np.all(t64[3:] == -1)
