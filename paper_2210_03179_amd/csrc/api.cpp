@@ -1471,10 +1471,12 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
   HIPCHK(c, hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   sem_status status = SEM_ENOTCONV;
   int it = 0;
+  bool x_pending = false;  // x += alpha p of the last residual update not yet applied
   for (it = 1; it <= maxit; ++it) {
     fine_apply(c, p, w, p, s);
     launch_finalize(c->npartials, 1, c->partials, c->scal, S_PW, FIN_NONE, s);
-    launch_update_xr(n, c->scal, u, p, r, w, r2, c->partials, kReduceBlocks, mixed ? c->levels[0].b32 : nullptr, s);
+    launch_update_r(n, c->scal, r, w, r2, c->partials, kReduceBlocks, mixed ? c->levels[0].b32 : nullptr, s);
+    x_pending = true;
     launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_RR, FIN_NONE, s);
     TRY(read_scalars(c, s));
     const double rz = c->pinned[S_RZ], pw = c->pinned[S_PW], rr = c->pinned[S_RR];
@@ -1506,8 +1508,10 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
       launch_dots<double>(n, 1, z, r, nullptr, nullptr, nullptr, nullptr, c->partials, kReduceBlocks, s);
       launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_ZR, FIN_BETA_PCG, s);
     }
-    launch_update_p(n, c->scal, z, p, s);
+    launch_update_xp(n, c->scal, u, z, p, s);  // x += alpha p, p = z + beta p
+    x_pending = false;
   }
+  if (x_pending) launch_update_x(n, c->scal, u, p, s);
   HIPCHK(c, hipStreamSynchronize(s));
   HIPCHK(c, hipGetLastError());
   if (status == SEM_ENOTCONV) c->err = "maximum number of iterations reached";

@@ -29,7 +29,7 @@ enum {
 };
 
 // device scalar slots of the Krylov method
-enum { S_RZ = 0, S_PW = 1, S_RR = 2, S_ZR = 3, S_ZRO = 4, S_BB = 5, S_BETA = 6, S_TMP = 8, S_COUNT = 16 };
+enum { S_RZ = 0, S_PW = 1, S_RR = 2, S_ZR = 3, S_ZRO = 4, S_BB = 5, S_BETA = 6, S_ALPHA = 7, S_TMP = 8, S_COUNT = 16 };
 // scalar operations done by the finalize kernel after the reduction
 enum { FIN_NONE = 0, FIN_INIT_RZ = 1, FIN_BETA_PCG = 2, FIN_BETA_FCG = 3 };
 
@@ -79,9 +79,10 @@ void launch_finalize(int nblocks, int nd, const double *partials, double *scal, 
                      hipStream_t s);
 void launch_resid_norm(int64_t n, const double *b, const double *w, double *r, double *partials, int nblocks,
                        float *r32, hipStream_t s);
-void launch_update_xr(int64_t n, const double *scal, double *x, const double *p, const double *r,
-                      const double *w, double *rnew, double *partials, int nblocks, float *r32, hipStream_t s);
-void launch_update_p(int64_t n, const double *scal, const double *z, double *p, hipStream_t s);
+void launch_update_r(int64_t n, double *scal, const double *r, const double *w, double *rnew, double *partials,
+                     int nblocks, float *r32, hipStream_t s);
+void launch_update_xp(int64_t n, const double *scal, double *x, const double *z, double *p, hipStream_t s);
+void launch_update_x(int64_t n, const double *scal, double *x, const double *p, hipStream_t s);
 void launch_convert(int64_t n, const double *in, float *out, hipStream_t s);
 void launch_convert(int64_t n, const float *in, double *out, hipStream_t s);
 void launch_axpby(int64_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s);

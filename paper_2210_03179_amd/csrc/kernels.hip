@@ -838,28 +838,6 @@ __global__ void scale_inv_sqrt_kernel(int64_t n, const double *__restrict__ x, c
   if (g < n) y[g] = x[g] / d;
 }
 
-// x += alpha p; r_new = r - alpha w; partial ||r_new||^2. alpha = scal[RZ] / scal[PW].
-// r32 (optional): single-precision copy of r_new, the input of a mixed-precision cycle.
-__global__ void __launch_bounds__(256)
-update_xr_kernel(int64_t n, const double *__restrict__ scal, double *__restrict__ x,
-                 const double *__restrict__ p, const double *__restrict__ r,
-                 const double *__restrict__ w, double *__restrict__ rnew, double *__restrict__ partials,
-                 float *__restrict__ r32) {
-  __shared__ double sm[4];
-  const double alpha = scal[S_RZ] / scal[S_PW];
-  double acc = 0.0;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    x[g] = x[g] + alpha * p[g];
-    const double rv = r[g] - alpha * w[g];
-    rnew[g] = rv;
-    if (r32) r32[g] = (float)rv;
-    acc += rv * rv;
-  }
-  const double s = block_sum(acc, sm);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
 // r = b - w with the partial ||r||^2 and (optional) the single-precision copy of r:
 // the residual of multigrid used as the solver, where w = A u.
 __global__ void __launch_bounds__(256)
@@ -877,12 +855,41 @@ resid_norm_kernel(int64_t n, const double *__restrict__ b, const double *__restr
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-// p = z + beta p, beta = scal[BETA]
-__global__ void update_p_kernel(int64_t n, const double *__restrict__ scal, const double *__restrict__ z,
-                                double *__restrict__ p) {
+// The CG iterate update x += alpha p is deferred to the pass that updates p, which reads
+// p anyway: r_new = r - alpha w with its norm (alpha = r.z / p.w, kept in scal[S_ALPHA]),
+// then x += alpha p and p = z + beta p in one pass, and x += alpha p alone when the
+// iteration stops.
+__global__ void __launch_bounds__(256)
+update_r_kernel(int64_t n, double *__restrict__ scal, const double *__restrict__ r, const double *__restrict__ w,
+                double *__restrict__ rnew, double *__restrict__ partials, float *__restrict__ r32) {
+  __shared__ double sm[4];
+  const double alpha = scal[S_RZ] / scal[S_PW];
+  double acc = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+    const double rv = r[g] - alpha * w[g];
+    rnew[g] = rv;
+    if (r32) r32[g] = (float)rv;
+    acc += rv * rv;
+  }
+  const double s = block_sum(acc, sm);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA] = alpha;
+}
+
+__global__ void update_xp_kernel(int64_t n, const double *__restrict__ scal, double *__restrict__ x,
+                                 const double *__restrict__ z, double *__restrict__ p) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
-  p[g] = z[g] + scal[S_BETA] * p[g];
+  const double pg = p[g];
+  x[g] = x[g] + scal[S_ALPHA] * pg;
+  p[g] = z[g] + scal[S_BETA] * pg;
+}
+
+__global__ void update_x_kernel(int64_t n, const double *__restrict__ scal, double *__restrict__ x,
+                                const double *__restrict__ p) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  x[g] = x[g] + scal[S_ALPHA] * p[g];
 }
 
 template <typename TO, typename TI>
@@ -1444,18 +1451,21 @@ void launch_finalize(int nblocks, int nd, const double *partials, double *scal, 
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, nblocks, nd, partials, scal, slot, op);
 }
 
-void launch_update_xr(int64_t n, const double *scal, double *x, const double *p, const double *r,
-                      const double *w, double *rnew, double *partials, int nblocks, float *r32, hipStream_t s) {
-  hipLaunchKernelGGL(update_xr_kernel, dim3(nblocks), dim3(256), 0, s, n, scal, x, p, r, w, rnew, partials, r32);
-}
 
 void launch_resid_norm(int64_t n, const double *b, const double *w, double *r, double *partials, int nblocks,
                        float *r32, hipStream_t s) {
   hipLaunchKernelGGL(resid_norm_kernel, dim3(nblocks), dim3(256), 0, s, n, b, w, r, partials, r32);
 }
 
-void launch_update_p(int64_t n, const double *scal, const double *z, double *p, hipStream_t s) {
-  hipLaunchKernelGGL(update_p_kernel, dim3(nblk(n)), dim3(256), 0, s, n, scal, z, p);
+void launch_update_r(int64_t n, double *scal, const double *r, const double *w, double *rnew, double *partials,
+                     int nblocks, float *r32, hipStream_t s) {
+  hipLaunchKernelGGL(update_r_kernel, dim3(nblocks), dim3(256), 0, s, n, scal, r, w, rnew, partials, r32);
+}
+void launch_update_xp(int64_t n, const double *scal, double *x, const double *z, double *p, hipStream_t s) {
+  hipLaunchKernelGGL(update_xp_kernel, dim3(nblk(n)), dim3(256), 0, s, n, scal, x, z, p);
+}
+void launch_update_x(int64_t n, const double *scal, double *x, const double *p, hipStream_t s) {
+  hipLaunchKernelGGL(update_x_kernel, dim3(nblk(n)), dim3(256), 0, s, n, scal, x, p);
 }
 
 void launch_convert(int64_t n, const double *in, float *out, hipStream_t s) {
