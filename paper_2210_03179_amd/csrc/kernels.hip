@@ -745,6 +745,26 @@ dots_kernel(int64_t n, int nd, const T *__restrict__ x0, const T *__restrict__ y
   }
 }
 
+// Sum over b = threadIdx.x, +blockDim.x, ... < nblocks of partials[b*nd + q], in that order,
+// with eight loads in flight per round instead of one (reductions with tens of thousands of
+// partials are otherwise a chain of dependent memory latencies).
+__device__ __forceinline__ double strided_partial_sum(const double *__restrict__ partials, int nblocks, int nd,
+                                                      int q) {
+  constexpr int kRound = 8;
+  double a = 0.0;
+  for (int b0 = threadIdx.x; b0 < nblocks; b0 += kRound * blockDim.x) {
+    double v[kRound];
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const int bq = b0 + u * blockDim.x;
+      v[u] = bq < nblocks ? partials[(int64_t)bq * nd + q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) a += v[u];
+  }
+  return a;
+}
+
 // out[slot + q] = sum_b partials[b*nd + q], fixed order; then an optional scalar
 // step for the Krylov recurrences (see finalize_op).
 __global__ void __launch_bounds__(256)
@@ -753,8 +773,7 @@ finalize_kernel(int nblocks, int nd, const double *__restrict__ partials, double
   __shared__ double sm[4];
   __shared__ double res[3];
   for (int q = 0; q < nd; ++q) {
-    double a = 0.0;
-    for (int bq = threadIdx.x; bq < nblocks; bq += blockDim.x) a += partials[bq * nd + q];
+    const double a = strided_partial_sum(partials, nblocks, nd, q);
     const double s = block_sum(a, sm);
     if (threadIdx.x == 0) res[q] = s;
   }
@@ -802,8 +821,7 @@ __global__ void __launch_bounds__(256)
 finalize_many_kernel(int nblocks, int nd, const double *__restrict__ partials, double *__restrict__ out) {
   __shared__ double sm[4];
   const int q = blockIdx.x;
-  double a = 0.0;
-  for (int bq = threadIdx.x; bq < nblocks; bq += blockDim.x) a += partials[(int64_t)bq * nd + q];
+  const double a = strided_partial_sum(partials, nblocks, nd, q);
   const double t = block_sum(a, sm);
   if (threadIdx.x == 0) out[q] = t;
 }
