@@ -1166,7 +1166,6 @@ void release(sem_ctx *c) {
     for (auto &g : c->graphs) hipGraphExecDestroy(g.exec);
     c->graphs.clear();
     if (c->capture_stream) hipStreamDestroy(c->capture_stream);
-    if (c->scal_event) hipEventDestroy(c->scal_event);
     for (void *p : c->allocations) hipFree(p);
     if (c->pinned) hipHostFree(c->pinned);
     if (c->gpinned) hipHostFree(c->gpinned);
@@ -1473,44 +1472,22 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
   sem_status status = SEM_ENOTCONV;
   int it = 0;
   bool x_pending = false;  // x += alpha p of the last residual update not yet applied
-  if (!c->scal_event) HIPCHK(c, hipEventCreateWithFlags(&c->scal_event, hipEventDisableTiming));
-  double rn_prev = rn, rn_prev2 = 0.0;
   for (it = 1; it <= maxit; ++it) {
     fine_apply(c, p, w, p, s);
     launch_finalize(c->npartials, 1, c->partials, c->scal, S_PW, FIN_NONE, s);
     launch_update_r(n, c->scal, r, w, r2, c->partials, kReduceBlocks, mixed ? c->levels[0].b32 : nullptr, s);
     x_pending = true;
     launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_RR, FIN_NONE, s);
-    HIPCHK(c, hipMemcpyAsync(c->pinned, c->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipEventRecord(c->scal_event, s));
-    // The next V-cycle reads only the new residual, so it is queued before the host has the
-    // scalars and runs while they travel, unless this iteration is likely the last one
-    // (||r|| extrapolated geometrically from the two previous iterations within 4x of the
-    // tolerance). A cycle queued on an iteration that turns out to stop is discarded: its
-    // result is unused and its operator applications are not counted.
-    const double pred = rn_prev2 > 0.0 ? rn_prev * rn_prev / rn_prev2 : rn_prev;
-    const bool spec = it < maxit && pred > 4.0 * rtol * bnorm;
-    std::vector<int64_t> counts_before;
-    if (spec) {
-      for (auto &L : c->levels) counts_before.push_back(L.applies);
-      TRY(vcycle_replay(c, r2, z, s, mixed));
-    }
-    auto discard = [&]() {
-      if (spec)
-        for (size_t j = 0; j < c->levels.size(); ++j) c->levels[j].applies = counts_before[j];
-    };
-    HIPCHK(c, hipEventSynchronize(c->scal_event));
+    TRY(read_scalars(c, s));
     const double rz = c->pinned[S_RZ], pw = c->pinned[S_PW], rr = c->pinned[S_RR];
     if (!std::isfinite(rr) || !std::isfinite(pw) || !std::isfinite(rz)) {
       c->err = "non-finite value in the Krylov iteration";
       status = SEM_ENAN;
-      discard();
       break;
     }
     if (!(rz > 0.0) || !(pw > 0.0)) {
       c->err = "Krylov breakdown (r.z <= 0 or p.Ap <= 0)";
       status = SEM_EBREAKDOWN;
-      discard();
       break;
     }
     std::swap(r, r2);  // r: new residual, r2: previous residual
@@ -1520,13 +1497,10 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
     if (relres) *relres = rn / bnorm;
     if (rn <= rtol * bnorm) {
       status = SEM_OK;
-      discard();
       break;
     }
     if (it == maxit) break;
-    rn_prev2 = rn_prev;
-    rn_prev = rn;
-    if (!spec) TRY(vcycle_replay(c, r, z, s, mixed));
+    TRY(vcycle_replay(c, r, z, s, mixed));
     if (flexible) {
       launch_dots<double>(n, 2, z, r, z, r2, nullptr, nullptr, c->partials, kReduceBlocks, s);
       launch_finalize(kReduceBlocks, 2, c->partials, c->scal, S_ZR, FIN_BETA_FCG, s);

@@ -232,7 +232,6 @@ struct sem_ctx {
   std::vector<CycleGraph> graphs;
   bool use_graphs = true;
   hipStream_t capture_stream = nullptr;
-  hipEvent_t scal_event = nullptr;  // marks the Krylov scalars' arrival in host memory
   std::string err;
   std::vector<void *> allocations;
   sem_batch *batch = nullptr;  // set for batched contexts (kind == 2)

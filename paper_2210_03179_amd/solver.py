@@ -120,10 +120,14 @@ class _Base:
         L.check(self._lib.sem_vcycle(self._ctx, _ptr(r), _ptr(out), _stream()), self._ctx)
         return out
 
-    def solve(self, b, x0=None, rtol: float = 1e-8, maxit: int = 500, raise_on_fail: bool = False):
-        """Returns (u, SolveInfo). u starts from x0 (zero when None)."""
+    def solve(self, b, x0=None, rtol: float = 1e-8, maxit: int = 500, raise_on_fail: bool = False, out=None):
+        """Returns (u, SolveInfo). u starts from x0 (zero when None). out: optional preallocated
+        tensor like b that receives u (no allocation inside the call)."""
         torch = _torch()
-        u = torch.zeros_like(b) if x0 is None else x0.clone()
+        if out is not None:
+            u = out.zero_() if x0 is None else out.copy_(x0)
+        else:
+            u = torch.zeros_like(b) if x0 is None else x0.clone()
         its, rel = C.c_int32(), C.c_double()
         hist = np.zeros(maxit + 1)
         st = self._lib.sem_solve(self._ctx, _ptr(b), _ptr(u), float(rtol), int(maxit), C.byref(its),

@@ -225,10 +225,13 @@ def test_solve_edge_cases(small_case):
     with pytest.raises(L.SemError) as e:
         s.solve(bad)
     assert e.value.status == L.SEM_ENAN
-    # deterministic: two solves are bitwise identical
+    # deterministic: two solves are bitwise identical, also into a preallocated output
     u1, _ = s.solve(b)
     u2, _ = s.solve(b)
     assert torch.equal(u1, u2)
+    out = torch.full_like(b, 7.0)
+    u3, _ = s.solve(b, out=out)
+    assert u3.data_ptr() == out.data_ptr() and torch.equal(u3, u1)
 
 
 # ------------------------------------------------------------------ finite differences (config 1)
