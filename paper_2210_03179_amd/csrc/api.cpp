@@ -396,23 +396,37 @@ void vcycle(sem_ctx *c, int j, hipStream_t s) {
   }
   vcycle<T>(c, j + 1, s);
   // a one-sided mixed cycle ends with this prolongation on the finest level: it
-  // writes the widened result z directly (c->zout) instead of updating x
+  // writes the widened result z directly (c->zout) instead of updating x, and can
+  // reduce the Krylov dot products of z on the way
   double *zout = (j == 0 && post == 0) ? c->zout : nullptr;
-  if (L.type == LVL_SEM) launch_prolong<T>(L, C, V<T>::x(C), V<T>::J(L), x, zout, s);
-  else launch_csr<T>(L.P, V<T>::val(L.P), V<T>::x(C), (const T *)nullptr, x, 2, s);
+  if (L.type == LVL_SEM) {
+    const int nb = launch_prolong<T>(L, C, V<T>::x(C), V<T>::J(L), x, zout, s, zout ? c->zdot_r1 : nullptr,
+                                     c->zdot_r2, c->partials, c->partials_cap);
+    if (zout) c->zdot_blocks = nb;
+  } else launch_csr<T>(L.P, V<T>::val(L.P), V<T>::x(C), (const T *)nullptr, x, 2, s);
   if (post > 0) smooth<T>(c, L, post, false, s);
 }
 
 // z = M^{-1} r through the context's precision. In mixed precision the single-
 // precision copy of r may already be in place (r32_ready, written by the Krylov update).
-void vcycle_top(sem_ctx *c, const double *r, double *z, hipStream_t s, bool r32_ready = false) {
+// d1 (and d2) ask for z . d1 (z . d2) in partials; the return value is the number of
+// blocks that wrote them, 0 when this cycle cannot fuse them (the caller reduces instead).
+int vcycle_top(sem_ctx *c, const double *r, double *z, hipStream_t s, bool r32_ready = false,
+               const double *d1 = nullptr, const double *d2 = nullptr) {
   Level &L0 = c->levels[0];
+  int dot_blocks = 0;
   if (c->opt.precision == SEM_MIXED) {
     if (!r32_ready) launch_convert(L0.n, r, L0.b32, s);
     const bool fused_out = c->opt.post_order == 0 && L0.type == LVL_SEM && c->levels.size() > 1;
     c->zout = fused_out ? z : nullptr;
+    c->zdot_r1 = d1;
+    c->zdot_r2 = d1 ? d2 : nullptr;
+    c->zdot_blocks = 0;
     vcycle<float>(c, 0, s);
+    if (fused_out && d1) dot_blocks = c->zdot_blocks;
     c->zout = nullptr;
+    c->zdot_r1 = c->zdot_r2 = nullptr;
+    c->zdot_blocks = 0;
     if (!fused_out) launch_convert(L0.n, L0.x32, z, s);
   } else {
     double *sb = L0.b64, *sx = L0.x64;
@@ -422,6 +436,7 @@ void vcycle_top(sem_ctx *c, const double *r, double *z, hipStream_t s, bool r32_
     L0.b64 = sb;
     L0.x64 = sx;
   }
+  return dot_blocks;
 }
 
 // The V-cycle of the Krylov solve as a replayed HIP graph. A cycle chains dozens of
@@ -431,17 +446,25 @@ void vcycle_top(sem_ctx *c, const double *r, double *z, hipStream_t s, bool r32_
 // buffers, Chebyshev coefficients, operator variants) are fixed after setup, and
 // the cycle records no memset or host copy. Operator-application counters advance
 // by the captured cycle's counts at every replay.
-sem_status vcycle_replay(sem_ctx *c, const double *r, double *z, hipStream_t s, bool r32_ready) {
+//
+// d1, d2 and dot_blocks: optional dot products of z fused into the cycle (see vcycle_top);
+// *dot_blocks receives the number of partials blocks written, 0 when none were.
+sem_status vcycle_replay(sem_ctx *c, const double *r, double *z, hipStream_t s, bool r32_ready,
+                         const double *d1 = nullptr, const double *d2 = nullptr, int *dot_blocks = nullptr) {
+  if (dot_blocks) *dot_blocks = 0;
+  if (!dot_blocks) d1 = d2 = nullptr;
   if (!c->use_graphs) {
-    vcycle_top(c, r, z, s, r32_ready);
+    const int nb = vcycle_top(c, r, z, s, r32_ready, d1, d2);
+    if (dot_blocks) *dot_blocks = nb;
     return SEM_OK;
   }
   // a mixed cycle whose single-precision input is already in place does not read r
   const double *key = (c->opt.precision == SEM_MIXED && r32_ready) ? nullptr : r;
   for (auto &g : c->graphs) {
-    if (g.r == key && g.z == z && g.r32 == r32_ready) {
+    if (g.r == key && g.z == z && g.r32 == r32_ready && g.d1 == d1 && g.d2 == d2) {
       HIPCHK(c, hipGraphLaunch(g.exec, s));
       for (size_t j = 0; j < c->levels.size(); ++j) c->levels[j].applies += g.applies[j];
+      if (dot_blocks) *dot_blocks = g.dot_blocks;
       return SEM_OK;
     }
   }
@@ -449,10 +472,10 @@ sem_status vcycle_replay(sem_ctx *c, const double *r, double *z, hipStream_t s, 
   std::vector<int64_t> before;
   for (auto &L : c->levels) before.push_back(L.applies);
   HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeRelaxed));
-  vcycle_top(c, r, z, c->capture_stream, r32_ready);
+  const int nb = vcycle_top(c, r, z, c->capture_stream, r32_ready, d1, d2);
   hipGraph_t graph = nullptr;
   HIPCHK(c, hipStreamEndCapture(c->capture_stream, &graph));
-  sem_ctx::CycleGraph g{key, z, r32_ready, nullptr, {}};
+  sem_ctx::CycleGraph g{key, z, r32_ready, d1, d2, nb, nullptr, {}};
   const hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
   hipGraphDestroy(graph);
   if (e != hipSuccess) {
@@ -464,7 +487,7 @@ sem_status vcycle_replay(sem_ctx *c, const double *r, double *z, hipStream_t s, 
     c->levels[j].applies = before[j];
   }
   c->graphs.push_back(g);
-  return vcycle_replay(c, r, z, s, r32_ready);
+  return vcycle_replay(c, r, z, s, r32_ready, d1, d2, dot_blocks);
 }
 
 // w = A u on the finest level with a reduction partial of p . w when p is given.
@@ -581,7 +604,8 @@ sem_status alloc_krylov(sem_ctx *c, int64_t n) {
   TRY(dalloc(c, &c->kp, n));
   TRY(dalloc(c, &c->kw, n));
   TRY(dalloc(c, &c->scal, S_COUNT));
-  TRY(dalloc(c, &c->partials, std::max<size_t>((size_t)kReduceBlocks * kMaxRestart, (size_t)(n / 256 + 2))));
+  c->partials_cap = (int64_t)std::max<size_t>((size_t)kReduceBlocks * kMaxRestart, (size_t)(n / 256 + 2));
+  TRY(dalloc(c, &c->partials, (size_t)c->partials_cap));
   HIPCHK(c, hipHostMalloc((void **)&c->pinned, S_COUNT * sizeof(double), hipHostMallocDefault));
   if (c->opt.krylov == SEM_GMRES) {
     const int m = c->opt.gmres_restart > 0 ? c->opt.gmres_restart : 30;
@@ -1500,14 +1524,15 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
       break;
     }
     if (it == maxit) break;
-    TRY(vcycle_replay(c, r, z, s, mixed));
-    if (flexible) {
-      launch_dots<double>(n, 2, z, r, z, r2, nullptr, nullptr, c->partials, kReduceBlocks, s);
-      launch_finalize(kReduceBlocks, 2, c->partials, c->scal, S_ZR, FIN_BETA_FCG, s);
-    } else {
-      launch_dots<double>(n, 1, z, r, nullptr, nullptr, nullptr, nullptr, c->partials, kReduceBlocks, s);
-      launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_ZR, FIN_BETA_PCG, s);
+    // z . r (and z . r_old for the flexible beta), reduced inside the cycle when it can
+    int zb = 0;
+    TRY(vcycle_replay(c, r, z, s, mixed, r, flexible ? r2 : nullptr, &zb));
+    if (zb == 0) {
+      if (flexible) launch_dots<double>(n, 2, z, r, z, r2, nullptr, nullptr, c->partials, kReduceBlocks, s);
+      else launch_dots<double>(n, 1, z, r, nullptr, nullptr, nullptr, nullptr, c->partials, kReduceBlocks, s);
+      zb = kReduceBlocks;
     }
+    launch_finalize(zb, flexible ? 2 : 1, c->partials, c->scal, S_ZR, flexible ? FIN_BETA_FCG : FIN_BETA_PCG, s);
     launch_update_xp(n, c->scal, u, z, p, s);  // x += alpha p, p = z + beta p
     x_pending = false;
   }

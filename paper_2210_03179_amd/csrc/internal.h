@@ -216,16 +216,24 @@ struct sem_ctx {
   double *partials = nullptr;  // reduction partials
   int npartials = 0;           // partials written by the last fused apply
   double *pinned = nullptr;    // host-pinned scalar mirror
+  int64_t partials_cap = 0;    // doubles in partials
   double *zout = nullptr;      // set during a mixed one-sided cycle: widened output target
+  // optional Krylov reductions fused into that cycle's last kernel: z . zdot_r1 (and z . zdot_r2)
+  // reduced over zdot_blocks partials (0 when the cycle could not fuse them)
+  const double *zdot_r1 = nullptr, *zdot_r2 = nullptr;
+  int zdot_blocks = 0;
   // GMRES(m) work: basis V (m+1 vectors) and preconditioned directions Z (m vectors), leading
   // dimension gld; device scalars gH (projections, ||w||^2, y) and their pinned host mirror
   double *gV = nullptr, *gZ = nullptr, *gH = nullptr, *gpinned = nullptr;
   int64_t gld = 0;
-  // V-cycles of the Krylov solve replayed as captured HIP graphs, one per (r, z, r32) triple
+  // V-cycles of the Krylov solve replayed as captured HIP graphs, one per (r, z, r32, dot
+  // operands) key
   struct CycleGraph {
     const double *r;
     double *z;
     bool r32;
+    const double *d1, *d2;  // fused dot operands (nullptr: none)
+    int dot_blocks;         // partials the replay writes (0: the dots were not fused)
     hipGraphExec_t exec;
     std::vector<int64_t> applies;  // operator applications per level of one cycle
   };

@@ -50,7 +50,13 @@ void launch_resid_weight(const Level &L, const T *wL, const T *b, T *rw, hipStre
 template <typename T>
 void launch_restrict(const Level &F, const Level &C, const T *rw, const T *J, T *rcL, hipStream_t s);
 template <typename T>
-void launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *xf, double *zout, hipStream_t s);
+// zout (one-sided mixed cycle): write the widened z instead of updating xf; with dr1 (and dr2)
+// also the partial sums of z . dr1 (z . dr2) into partials[block * nd + q], nd = 1 (2). Returns
+// the number of blocks that wrote partials, 0 when none did (orders without the row-blocked
+// kernel, or more blocks than partials_cap / nd).
+int launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *xf, double *zout, hipStream_t s,
+                   const double *dr1 = nullptr, const double *dr2 = nullptr, double *partials = nullptr,
+                   int64_t partials_cap = 0);
 template <typename T>
 void launch_csr(const DevCsr &A, const T *val, const T *x, const T *b, T *y, int mode, hipStream_t s);
 void launch_gemv(int64_t nrows, int64_t ncols, const double *M, const double *x, const double *b, double *y,

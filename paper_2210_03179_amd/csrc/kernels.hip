@@ -389,7 +389,8 @@ restrict_rows_kernel(Box fb, Box cb, const T *__restrict__ rw, const T *__restri
 template <typename T, int NF, int NC>
 __global__ void __launch_bounds__(256)
 prolong_rows_kernel(Box fb, Box cb, const T *__restrict__ xc, const T *__restrict__ Jm, T *__restrict__ xf,
-                    double *__restrict__ zout) {
+                    double *__restrict__ zout, const double *__restrict__ dr1, const double *__restrict__ dr2,
+                    double *__restrict__ partials) {
   constexpr int nf = NF + 1, nc = NC + 1, EX = rows_ex<NF, NC, T>();
   __shared__ T sJ[nf * nc];
   __shared__ T sc[EX * nc * nc * nc];      // [el][c][b][a]
@@ -427,6 +428,7 @@ prolong_rows_kernel(Box fb, Box cb, const T *__restrict__ xc, const T *__restric
   __syncthreads();
   // owned fine nodes (local i, j, k < NF) of the run: rows of nel*NF contiguous unknowns
   const int RL = nel * NF;
+  double d1 = 0.0, d2 = 0.0;
   for (int q = t; q < NF * NF * RL; q += 256) {
     const int ig = q % RL, j = (q / RL) % NF, k = q / (RL * NF);
     const int el = ig / NF, i = ig - el * NF;
@@ -435,8 +437,25 @@ prolong_rows_kernel(Box fb, Box cb, const T *__restrict__ xc, const T *__restric
     T acc = 0;
 #pragma unroll
     for (int c = 0; c < nc; ++c) acc += sJ[k * nc + c] * t2[((el * nc + c) * nf + j) * nf + i];
-    if (zout) zout[g] = (double)(xf[g] + acc);
-    else xf[g] += acc;
+    if (zout) {
+      const double zv = (double)(xf[g] + acc);
+      zout[g] = zv;
+      if (dr1) d1 += zv * dr1[g];
+      if (dr2) d2 += zv * dr2[g];
+    } else {
+      xf[g] += acc;
+    }
+  }
+  // optional Krylov reductions over the written z (z . r1, z . r2): one partial per block
+  if (dr1) {
+    __shared__ double sm[4];
+    const int nd = dr2 ? 2 : 1;
+    double s = block_sum(d1, sm);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * nd] = s;
+    if (dr2) {
+      s = block_sum(d2, sm);
+      if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * nd + 1] = s;
+    }
   }
 }
 
@@ -1406,26 +1425,29 @@ template void launch_restrict<float>(const Level &, const Level &, const float *
                                      hipStream_t);
 
 template <typename T>
-void launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *xf, double *zout, hipStream_t s) {
+int launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *xf, double *zout, hipStream_t s,
+                   const double *dr1, const double *dr2, double *partials, int64_t partials_cap) {
   const int nf = F.N + 1, nc = C.N + 1;
   const size_t lds = sizeof(T) * (size_t)(nf * nc + nc * nc * nc + nc * nc * nf + nc * nf * nf);
 #define SEMCHEB_PICK(A, B)                                                                              \
   if (F.N == A && C.N == B) {                                                                           \
     constexpr int ex = rows_ex<A, B, T>();                                                              \
     const unsigned grid = (unsigned)(((F.nex + ex - 1) / ex) * (int64_t)F.ney * F.nez);                \
+    const bool dots = zout && dr1 && partials && (int64_t)grid * (dr2 ? 2 : 1) <= partials_cap;         \
     hipLaunchKernelGGL((prolong_rows_kernel<T, A, B>), dim3(grid), dim3(256), 0, s, mkbox(F), mkbox(C), xc, J, \
-                       xf, zout);                                                                       \
-    return;                                                                                             \
+                       xf, zout, dots ? dr1 : nullptr, dots ? dr2 : nullptr, dots ? partials : nullptr); \
+    return dots ? (int)grid : 0;                                                                        \
   }
   SEMCHEB_TRANSFER_PAIRS(SEMCHEB_PICK)
 #undef SEMCHEB_PICK
   hipLaunchKernelGGL((prolong_kernel<T, 0, 0>), dim3((unsigned)F.E), dim3(128), lds, s, mkbox(F), mkbox(C), F.E, xc,
                      J, xf, zout);
+  return 0;
 }
-template void launch_prolong<double>(const Level &, const Level &, const double *, const double *, double *,
-                                     double *, hipStream_t);
-template void launch_prolong<float>(const Level &, const Level &, const float *, const float *, float *,
-                                    double *, hipStream_t);
+template int launch_prolong<double>(const Level &, const Level &, const double *, const double *, double *,
+                                    double *, hipStream_t, const double *, const double *, double *, int64_t);
+template int launch_prolong<float>(const Level &, const Level &, const float *, const float *, float *,
+                                   double *, hipStream_t, const double *, const double *, double *, int64_t);
 
 template <typename T>
 void launch_csr(const DevCsr &A, const T *val, const T *x, const T *b, T *y, int mode, hipStream_t s) {
