@@ -307,6 +307,11 @@ def main():
     kmx = "ax_local_kernel<%d, float, bf16, %d, %d, %d>" % ((N,) + _variant_args(vmx, N))
     log(f"operator variants (us) fp64 {[round(x, 1) for x in tune64[1:1 + nvar]]} -> {v64}, "
         f"bf16 {[round(x, 1) for x in tunemx[2 + nvar:2 + 2 * nvar]]} -> {vmx}")
+    per = 2 * (1 + nvar)
+    for j in range(1, s64.num_levels - 1):  # the smoothed lower levels
+        t64, tmx = tune64[j * per:(j + 1) * per], tunemx[j * per:(j + 1) * per]
+        log(f"level {j} operator variants (us) fp64 {[round(x, 1) for x in t64[1:1 + nvar]]} -> {int(t64[0])}, "
+            f"bf16 {[round(x, 1) for x in tmx[2 + nvar:2 + 2 * nvar]]} -> {int(tmx[1 + nvar])}")
     tr64 = measured_traffic(k64) if N == 7 and m == 32 else None
     trmx = measured_traffic(kmx) if N == 7 and m == 32 else None
     out = {

@@ -619,8 +619,9 @@ sem_status alloc_krylov(sem_ctx *c, int64_t n) {
 }
 
 // Autotuner: time every operator-kernel variant on the level's own data (events on the
-// setup stream) and keep the fastest per precision. Variants differ only in load
-// scheduling and register allocation, not in arithmetic, so results are identical.
+// setup stream) and keep the fastest per precision. Variants compute the same sums and
+// differ in load scheduling, register allocation and where the compiler contracts
+// multiply-adds, so their results agree to rounding.
 sem_status autotune_operator(sem_ctx *c, hipStream_t s) {
   // SEMCHEB_AX_VARIANT=v fixes variant v on every level (tests cover each variant this
   // way); SEMCHEB_AUTOTUNE=0 keeps variant 0.
