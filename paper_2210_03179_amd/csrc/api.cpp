@@ -395,14 +395,17 @@ void vcycle(sem_ctx *c, int j, hipStream_t s) {
     launch_csr<T>(L.R, V<T>::val(L.R), r, (const T *)nullptr, V<T>::b(C), 0, s);
   }
   vcycle<T>(c, j + 1, s);
-  // a one-sided mixed cycle ends with this prolongation on the finest level: it
-  // writes the widened result z directly (c->zout) instead of updating x, and can
-  // reduce the Krylov dot products of z on the way
-  double *zout = (j == 0 && post == 0) ? c->zout : nullptr;
+  // a one-sided cycle ends with this prolongation on the finest level. In mixed
+  // precision it writes the widened result z directly (c->zout) instead of updating x.
+  // Its result is then the cycle's z (FP64: x is z), and the Krylov dot products of z
+  // can be reduced on the way
+  const bool last = j == 0 && post == 0;
+  double *zout = last ? c->zout : nullptr;
+  const bool zdots = last && (zout || sizeof(T) == sizeof(double));
   if (L.type == LVL_SEM) {
-    const int nb = launch_prolong<T>(L, C, V<T>::x(C), V<T>::J(L), x, zout, s, zout ? c->zdot_r1 : nullptr,
-                                     c->zdot_r2, c->partials, c->partials_cap);
-    if (zout) c->zdot_blocks = nb;
+    const int nb = launch_prolong<T>(L, C, V<T>::x(C), V<T>::J(L), x, zout, s, zdots ? c->zdot_r1 : nullptr,
+                                     zdots ? c->zdot_r2 : nullptr, c->partials, c->partials_cap);
+    if (zdots) c->zdot_blocks = nb;
   } else launch_csr<T>(L.P, V<T>::val(L.P), V<T>::x(C), (const T *)nullptr, x, 2, s);
   if (post > 0) smooth<T>(c, L, post, false, s);
 }
@@ -414,19 +417,16 @@ void vcycle(sem_ctx *c, int j, hipStream_t s) {
 int vcycle_top(sem_ctx *c, const double *r, double *z, hipStream_t s, bool r32_ready = false,
                const double *d1 = nullptr, const double *d2 = nullptr) {
   Level &L0 = c->levels[0];
-  int dot_blocks = 0;
+  c->zdot_r1 = d1;
+  c->zdot_r2 = d1 ? d2 : nullptr;
+  c->zdot_blocks = 0;
+  bool fused_out = false;
   if (c->opt.precision == SEM_MIXED) {
     if (!r32_ready) launch_convert(L0.n, r, L0.b32, s);
-    const bool fused_out = c->opt.post_order == 0 && L0.type == LVL_SEM && c->levels.size() > 1;
+    fused_out = c->opt.post_order == 0 && L0.type == LVL_SEM && c->levels.size() > 1;
     c->zout = fused_out ? z : nullptr;
-    c->zdot_r1 = d1;
-    c->zdot_r2 = d1 ? d2 : nullptr;
-    c->zdot_blocks = 0;
     vcycle<float>(c, 0, s);
-    if (fused_out && d1) dot_blocks = c->zdot_blocks;
     c->zout = nullptr;
-    c->zdot_r1 = c->zdot_r2 = nullptr;
-    c->zdot_blocks = 0;
     if (!fused_out) launch_convert(L0.n, L0.x32, z, s);
   } else {
     double *sb = L0.b64, *sx = L0.x64;
@@ -436,6 +436,12 @@ int vcycle_top(sem_ctx *c, const double *r, double *z, hipStream_t s, bool r32_r
     L0.b64 = sb;
     L0.x64 = sx;
   }
+  // the partials count only when the prolongation that wrote them produced z itself
+  const bool z_last = c->opt.post_order == 0 && L0.type == LVL_SEM && c->levels.size() > 1 &&
+                      (fused_out || c->opt.precision != SEM_MIXED);
+  const int dot_blocks = (d1 && z_last) ? c->zdot_blocks : 0;
+  c->zdot_r1 = c->zdot_r2 = nullptr;
+  c->zdot_blocks = 0;
   return dot_blocks;
 }
 

@@ -50,10 +50,11 @@ void launch_resid_weight(const Level &L, const T *wL, const T *b, T *rw, hipStre
 template <typename T>
 void launch_restrict(const Level &F, const Level &C, const T *rw, const T *J, T *rcL, hipStream_t s);
 template <typename T>
-// zout (one-sided mixed cycle): write the widened z instead of updating xf; with dr1 (and dr2)
-// also the partial sums of z . dr1 (z . dr2) into partials[block * nd + q], nd = 1 (2). Returns
-// the number of blocks that wrote partials, 0 when none did (orders without the row-blocked
-// kernel, or more blocks than partials_cap / nd).
+// zout (one-sided mixed cycle): write the widened result z instead of updating xf; with dr1
+// (and dr2) also the partial sums of z . dr1 (z . dr2) into partials[block * nd + q], nd = 1
+// (2), z being the result written (zout, else the updated xf). Returns the number of blocks
+// that wrote them, 0 when none did (orders without the row-blocked kernel, or more blocks
+// than partials_cap / nd).
 int launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *xf, double *zout, hipStream_t s,
                    const double *dr1 = nullptr, const double *dr2 = nullptr, double *partials = nullptr,
                    int64_t partials_cap = 0);

@@ -337,6 +337,20 @@ constexpr int rows_ex() {
   return (sizeof(T) == 4 ? 64 : 32) / NF < 1 ? 1 : ((sizeof(T) == 4 ? 64 : 32) / NF > 8 ? 8 : (sizeof(T) == 4 ? 64 : 32) / NF);
 }
 
+// Elements per block of the prolongation: row runs of about 450-500 bytes (the partial
+// cache lines at the run ends cost less the longer the run), within 32 KB of LDS per block.
+// FP64 runs stop at 56 unknowns so that a thread's share of the owned nodes (at order 7)
+// still fits the register preload.
+template <int NF, int NC, typename T>
+constexpr int prolong_ex() {
+  constexpr int nf = NF + 1, nc = NC + 1;
+  constexpr int per = (int)sizeof(T) * (nc * nc * nc + nc * nc * nf + nc * nf * nf);
+  int ex = (sizeof(T) == 4 ? 128 : 56) / NF;
+  if (ex > 16) ex = 16;
+  while (ex > 1 && (int)sizeof(T) * nf * nc + ex * per > 32768) --ex;
+  return ex < 1 ? 1 : ex;
+}
+
 template <typename T, int NF, int NC>
 __global__ void __launch_bounds__(256)
 restrict_rows_kernel(Box fb, Box cb, const T *__restrict__ rw, const T *__restrict__ Jm, T *__restrict__ rcL) {
@@ -391,7 +405,7 @@ __global__ void __launch_bounds__(256)
 prolong_rows_kernel(Box fb, Box cb, const T *__restrict__ xc, const T *__restrict__ Jm, T *__restrict__ xf,
                     double *__restrict__ zout, const double *__restrict__ dr1, const double *__restrict__ dr2,
                     double *__restrict__ partials) {
-  constexpr int nf = NF + 1, nc = NC + 1, EX = rows_ex<NF, NC, T>();
+  constexpr int nf = NF + 1, nc = NC + 1, EX = prolong_ex<NF, NC, T>();
   __shared__ T sJ[nf * nc];
   __shared__ T sc[EX * nc * nc * nc];      // [el][c][b][a]
   __shared__ T t1[EX * nc * nc * nf];      // [el][c][b][i]
@@ -402,6 +416,31 @@ prolong_rows_kernel(Box fb, Box cb, const T *__restrict__ xc, const T *__restric
   const int ex0 = gx * EX;
   const int nel = fb.nex - ex0 < EX ? fb.nex - ex0 : EX;
   const int t = threadIdx.x;
+  // owned fine nodes (local i, j, k < NF) of the run: rows of nel*NF contiguous unknowns.
+  // When a thread's share is small (kIt nodes) their operands are loaded first, before
+  // the contractions, so that all of the thread's loads are in flight together
+  const int RL = nel * NF, nown = NF * NF * RL;
+  constexpr int kIt = (NF * NF * EX * NF + 255) / 256;
+  constexpr bool kPre = kIt <= 12;
+  int64_t gq[kPre ? kIt : 1];
+  T xq[kPre ? kIt : 1];
+  double r1q[kPre ? kIt : 1], r2q[kPre ? kIt : 1];
+  if constexpr (kPre) {
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      const int q = t + 256 * it;
+      int64_t g = -1;
+      if (q < nown) {
+        const int ig = q % RL, j = (q / RL) % NF, k = q / (RL * NF);
+        g = lattice_index(fb, ex0 * NF + ig, ey * NF + j, ez * NF + k);
+      }
+      gq[it] = g;
+      const int64_t gs = g >= 0 ? g : 0;  // in bounds; the value is not used
+      xq[it] = xf[gs];
+      r1q[it] = dr1 ? dr1[gs] : 0.0;
+      r2q[it] = dr2 ? dr2[gs] : 0.0;
+    }
+  }
   for (int q = t; q < nf * nc; q += 256) sJ[q] = Jm[q];
   for (int q = t; q < EX * nc * nc * nc; q += 256) {
     const int a = q % nc, bq = (q / nc) % nc, c = (q / (nc * nc)) % nc, el = q / (nc * nc * nc);
@@ -426,27 +465,31 @@ prolong_rows_kernel(Box fb, Box cb, const T *__restrict__ xc, const T *__restric
     t2[q] = acc;
   }
   __syncthreads();
-  // owned fine nodes (local i, j, k < NF) of the run: rows of nel*NF contiguous unknowns
-  const int RL = nel * NF;
   double d1 = 0.0, d2 = 0.0;
-  for (int q = t; q < NF * NF * RL; q += 256) {
+  auto finish = [&](int q, int64_t g, T xl, double r1, double r2) {
     const int ig = q % RL, j = (q / RL) % NF, k = q / (RL * NF);
     const int el = ig / NF, i = ig - el * NF;
-    const int64_t g = lattice_index(fb, ex0 * NF + ig, ey * NF + j, ez * NF + k);
-    if (g < 0) continue;
     T acc = 0;
 #pragma unroll
     for (int c = 0; c < nc; ++c) acc += sJ[k * nc + c] * t2[((el * nc + c) * nf + j) * nf + i];
-    if (zout) {
-      const double zv = (double)(xf[g] + acc);
-      zout[g] = zv;
-      if (dr1) d1 += zv * dr1[g];
-      if (dr2) d2 += zv * dr2[g];
-    } else {
-      xf[g] += acc;
+    const T xv = xl + acc;
+    if (zout) zout[g] = (double)xv;
+    else xf[g] = xv;
+    d1 += (double)xv * r1;
+    d2 += (double)xv * r2;
+  };
+  if constexpr (kPre) {
+#pragma unroll
+    for (int it = 0; it < kIt; ++it)
+      if (gq[it] >= 0) finish(t + 256 * it, gq[it], xq[it], r1q[it], r2q[it]);
+  } else {
+    for (int q = t; q < nown; q += 256) {
+      const int ig = q % RL, j = (q / RL) % NF, k = q / (RL * NF);
+      const int64_t g = lattice_index(fb, ex0 * NF + ig, ey * NF + j, ez * NF + k);
+      if (g >= 0) finish(q, g, xf[g], dr1 ? dr1[g] : 0.0, dr2 ? dr2[g] : 0.0);
     }
   }
-  // optional Krylov reductions over the written z (z . r1, z . r2): one partial per block
+  // optional Krylov reductions over the written result z (z . r1, z . r2): one partial per block
   if (dr1) {
     __shared__ double sm[4];
     const int nd = dr2 ? 2 : 1;
@@ -1431,9 +1474,9 @@ int launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *x
   const size_t lds = sizeof(T) * (size_t)(nf * nc + nc * nc * nc + nc * nc * nf + nc * nf * nf);
 #define SEMCHEB_PICK(A, B)                                                                              \
   if (F.N == A && C.N == B) {                                                                           \
-    constexpr int ex = rows_ex<A, B, T>();                                                              \
+    constexpr int ex = prolong_ex<A, B, T>();                                                           \
     const unsigned grid = (unsigned)(((F.nex + ex - 1) / ex) * (int64_t)F.ney * F.nez);                \
-    const bool dots = zout && dr1 && partials && (int64_t)grid * (dr2 ? 2 : 1) <= partials_cap;         \
+    const bool dots = dr1 && partials && (int64_t)grid * (dr2 ? 2 : 1) <= partials_cap;                 \
     hipLaunchKernelGGL((prolong_rows_kernel<T, A, B>), dim3(grid), dim3(256), 0, s, mkbox(F), mkbox(C), xc, J, \
                        xf, zout, dots ? dr1 : nullptr, dots ? dr2 : nullptr, dots ? partials : nullptr); \
     return dots ? (int)grid : 0;                                                                        \
