@@ -365,13 +365,34 @@ restrict_rows_kernel(Box fb, Box cb, const T *__restrict__ rw, const T *__restri
   const int ex0 = gx * EX;
   const int nel = fb.nex - ex0 < EX ? fb.nex - ex0 : EX;
   const int t = threadIdx.x;
-  for (int q = t; q < nf * nc; q += 256) sJ[q] = Jm[q];
-  for (int q = t; q < nf * nf * RW; q += 256) {
-    const int ig = q % RW, j = (q / RW) % nf, k = q / (RW * nf);
-    const int64_t g = lattice_index(fb, ex0 * NF + ig, ey * NF + j, ez * NF + k);
-    const T v = rw[g >= 0 ? g : 0];
-    srow[q] = g >= 0 ? v : T(0);
+  // stage the fine rows: when a thread's share is small (kL values) all of its loads are
+  // issued before the first LDS store, so they are in flight together
+  constexpr int kL = (nf * nf * RW + 255) / 256;
+  if constexpr (kL <= 24) {
+    T v[kL];
+#pragma unroll
+    for (int it = 0; it < kL; ++it) {
+      const int q = t + 256 * it;
+      int64_t g = -1;
+      if (q < nf * nf * RW) {
+        const int ig = q % RW, j = (q / RW) % nf, k = q / (RW * nf);
+        g = lattice_index(fb, ex0 * NF + ig, ey * NF + j, ez * NF + k);
+      }
+      const T x = rw[g >= 0 ? g : 0];
+      v[it] = g >= 0 ? x : T(0);
+    }
+#pragma unroll
+    for (int it = 0; it < kL; ++it)
+      if (t + 256 * it < nf * nf * RW) srow[t + 256 * it] = v[it];
+  } else {
+    for (int q = t; q < nf * nf * RW; q += 256) {
+      const int ig = q % RW, j = (q / RW) % nf, k = q / (RW * nf);
+      const int64_t g = lattice_index(fb, ex0 * NF + ig, ey * NF + j, ez * NF + k);
+      const T x = rw[g >= 0 ? g : 0];
+      srow[q] = g >= 0 ? x : T(0);
+    }
   }
+  for (int q = t; q < nf * nc; q += 256) sJ[q] = Jm[q];
   __syncthreads();
   for (int q = t; q < EX * nf * nf * nc; q += 256) {  // t1[el][k][j][a] = sum_i J[i][a] f[k][j][i]
     const int a = q % nc, j = (q / nc) % nf, k = (q / (nc * nf)) % nf, el = q / (nc * nf * nf);
