@@ -142,6 +142,31 @@ def _solve_parity(s, ref, Aop, b, flexible, tol=1e-8, maxit=200):
     return u, info, res
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pcg_one_sided_history_parity(small_case, precision):
+    # plain CG with a one-sided cycle (a non-symmetric preconditioner) stagnates, here and in
+    # the oracle; its first iterations still agree, which covers the single z.r reduction the
+    # cycle's last prolongation computes for CG (flexible CG takes two)
+    V, N, lmax = small_case
+    print(f"pcg one-sided history {precision}", flush=True)
+    ref = mg.sem_hierarchy(V, N, "cheb4opt", 4, 0, lmax=lmax)
+    box = ref.extra["boxes"][0]
+    b = box.mass() * wl.manufactured_load(box.coords()) + 1e-2 * wl.uniform_noise(box.n, 1)
+    s = SemSolver(V, N=N, smoother="cheb4opt", pre=4, post=0, krylov="pcg", lambda_max=lmax,
+                  precision=precision)
+    its = 12
+    res = krylov.pcg(box.apply, b, ref.vcycle, 1e-8, its, flexible=False)
+    u, info = s.solve(dev(b), rtol=1e-8, maxit=its)
+    assert not res.converged and not info.converged
+    assert info.iterations == res.iterations == its
+    h_o = np.array(res.history)
+    if precision == "fp64":
+        assert np.max(np.abs(info.history - h_o)) <= 1e-10 * h_o[0]
+        assert np.linalg.norm(host(u) - res.x) <= 1e-10 * np.linalg.norm(res.x)
+    else:  # single-precision cycle: the same descent, within the BF16 factors' rounding
+        assert np.max(np.abs(info.history - h_o) / h_o) <= 0.2
+
+
 def test_cfg2_rhs_parity(cfg2):
     V, ref, box, b, lmax = cfg2
     s = SemSolver(V, N=7, lambda_max=lmax)
