@@ -178,12 +178,32 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
 // One (N+1)^2 thread slab per element, looping over the k planes:
 //   u column (i,j,:) held in registers, plane k of u staged in LDS for the r and s
 //   derivatives; the t derivative and its transpose stay in registers.
+// Elements per operator block for orders whose (N+1)^2 columns fit a wave poorly: N = 4
+// fills 50 of 64 lanes with two elements, 125 of 128 with five; N = 5 fills 36 of 64 with
+// one, 252 of 256 with seven (measured: FP64 operator 182 -> 169 us, BF16 64 -> 50 us on
+// 13.8 M local nodes). Orders whose element spans several waves keep one element per block:
+// three order-9 elements in 320 lanes ran 50 % slower than one in 128.
+template <int N>
+struct AxPack {
+  static constexpr int k = 0;
+};
+template <>
+struct AxPack<4> {
+  static constexpr int k = 5;
+};
+template <>
+struct AxPack<5> {
+  static constexpr int k = 7;
+};
+
 template <int N>
 struct AxShape {
   static constexpr int n1 = N + 1;
   static constexpr int tpe = n1 * n1;
-  static constexpr int block = tpe <= 64 ? 64 : ((tpe + 63) / 64) * 64;
-  static constexpr int epb = tpe <= 64 ? 64 / tpe : 1;
+  // elements per block: as many as fill one wave, one when an element needs more lanes, or
+  // AxPack's count where that rule leaves many lanes idle
+  static constexpr int epb = AxPack<N>::k > 0 ? AxPack<N>::k : (tpe <= 64 ? 64 / tpe : 1);
+  static constexpr int block = ((epb * tpe + 63) / 64) * 64;
   // occupancy requested from the register allocator (waves per SIMD): 4 keeps enough
   // factor loads in flight to stream HBM; larger orders get what their registers allow
   static constexpr int min_waves = N <= 7 ? 4 : 2;

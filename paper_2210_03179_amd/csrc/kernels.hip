@@ -1671,8 +1671,14 @@ void b_ax64_n(const LaunchTable &t, const BatchSysDev *sys, hipStream_t s) {
 }  // namespace
 
 int batch_ax_elements_per_block(int N) {
-  const int tpe = (N + 1) * (N + 1);
-  return tpe <= 64 ? 64 / tpe : 1;
+  switch (N) {
+#define SEMCHEB_EPB(n) \
+  case n: return AxShape<n>::epb;
+    SEMCHEB_EPB(1) SEMCHEB_EPB(2) SEMCHEB_EPB(3) SEMCHEB_EPB(4) SEMCHEB_EPB(5) SEMCHEB_EPB(6)
+    SEMCHEB_EPB(7) SEMCHEB_EPB(8) SEMCHEB_EPB(9) SEMCHEB_EPB(10) SEMCHEB_EPB(11) SEMCHEB_EPB(12)
+#undef SEMCHEB_EPB
+    default: return 1;
+  }
 }
 
 bool launch_b_ax32(int N, const LaunchTable &t, const BatchSysDev *sys, int level, int src, hipStream_t s) {
