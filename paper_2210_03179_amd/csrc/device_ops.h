@@ -188,6 +188,10 @@ struct AxPack {
   static constexpr int k = 0;
 };
 template <>
+struct AxPack<3> {
+  static constexpr int k = 16;
+};
+template <>
 struct AxPack<4> {
   static constexpr int k = 5;
 };
