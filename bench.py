@@ -113,8 +113,10 @@ def time_solves(solver, b, steps, warmup):
 
 
 # operator variant index -> (prefetch, occupancy, tile) template arguments; N <= 7 asks for 4 waves
-def _variant_args(variant, N):
+def _variant_args(variant, N, fp64=False):
     mw = 4 if N <= 7 else 2
+    if variant == 5 and fp64:  # the FP64 factor ring (N = 7); other orders launch variant 0
+        return (0, mw, 3) if N == 7 else (1, 1, 0)
     return {0: (1, 1, 0), 1: (0, mw, 0), 2: (1, mw, 0), 3: (1, 1, 1), 4: (0, mw, 1), 5: (0, mw, 2)}[variant]
 
 
@@ -303,7 +305,7 @@ def main():
     tunemx = smx.host_array("ax_tuning", 0)
     nvar = (len(tune64) // s64.num_levels - 2) // 2  # per level: variant, times (FP64), variant, times
     v64, vmx = int(tune64[0]), int(tunemx[1 + nvar])
-    k64 = "ax_local_kernel<%d, double, double, %d, %d, %d>" % ((N,) + _variant_args(v64, N))
+    k64 = "ax_local_kernel<%d, double, double, %d, %d, %d>" % ((N,) + _variant_args(v64, N, fp64=True))
     kmx = "ax_local_kernel<%d, float, bf16, %d, %d, %d>" % ((N,) + _variant_args(vmx, N))
     log(f"operator variants (us) fp64 {[round(x, 1) for x in tune64[1:1 + nvar]]} -> {v64}, "
         f"bf16 {[round(x, 1) for x in tunemx[2 + nvar:2 + 2 * nvar]]} -> {vmx}")
