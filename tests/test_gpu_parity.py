@@ -48,7 +48,7 @@ def test_apply_A_parity(m, N):
 
 
 @pytest.mark.parametrize("variant", range(6))
-@pytest.mark.parametrize("N", [2, 3, 7, 9])
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 7, 9])
 def test_operator_variants_parity(N, variant, monkeypatch):
     # every operator kernel variant the autotuner may pick, FP64 and FP32/BF16, against the oracle
     print(f"operator variant {variant} N={N}", flush=True)
