@@ -2,13 +2,16 @@
 times (32^3 elements, N = 7, opt. 4th-kind (4,0) one-sided cycle; the 64 uneven batched
 systems).
 
-At these sizes the oracle applies the operator (full vectors) but does not run cycles or
-solves, so the cycle and the solvers are checked through properties that hold at any size:
+At these sizes the oracle applies the operator and runs one V-cycle (about a minute on the
+host) but not whole solves, so the solvers are checked through properties that hold at any
+size:
 - operator: the GPU A u equals the oracle's, element by element, stored and trilinear
   factors;
 - solves: the true FP64 residual b - A u of the FP64 and the mixed solutions, evaluated with
   the oracle's operator, meets 1e-8; the mixed solve needs at most one iteration more and
   agrees with the FP64 solution to single-precision level;
+- one cycle of the measured configuration equals the oracle's over all unknowns (FP64 to
+  rounding, mixed within the BF16 factors' accuracy);
 - the symmetric (2,2) FP64 cycle is a symmetric operator (r2 . M r1 = r1 . M r2);
 - batched: every system's true residual (GPU FP64 operator of its own context, and the
   oracle's operator on sampled systems) meets 1e-8.
@@ -18,6 +21,7 @@ import pytest
 import torch
 
 import workload as wl
+from oracle import chebyshev as cheb, mg
 from oracle.sem import SemBox
 from paper_2210_03179_amd import _lib as L
 from paper_2210_03179_amd.solver import BatchedSolver, SemSolver
@@ -70,6 +74,32 @@ def test_cfg3_solves_full_size(cfg3):
     assert abs(r64 - info64.relres) <= 1e-11     # recurrence residual tracks the true one
     assert infomx.iterations <= info64.iterations + 1
     assert np.linalg.norm(xmx - x64) <= 1e-7 * np.linalg.norm(x64)
+
+
+def test_cfg3_vcycle_full_size(cfg3):
+    # one cycle of the measured configuration (opt. 4th-kind (4,0), schedule 7/3/1, exact order-1
+    # coarse solve), the whole output against the oracle's at the full size: FP64 to rounding
+    # (the coarse solves differ in factorization: block elimination with explicit inverses here,
+    # a sparse LU in the oracle), the mixed cycle within its BF16 factors' accuracy. Both sides
+    # use the GPU context's lambda_max (the oracle's Lanczos is pinned on small cases).
+    V, box, _ = cfg3
+    s64 = SemSolver(V, N=7, smoother="cheb4opt", pre=4, post=0, precision="fp64", krylov="fcg")
+    lmax = [float(x) for x in s64.lambda_max()]
+    print(f"building the 32^3, N = 7 oracle hierarchy (lambda_max {lmax})", flush=True)
+    h = mg.sem_hierarchy(V, 7, cheb.CHEB4_OPT, 4, 0, lmax=lmax)
+    r = wl.uniform_noise(box.n, 5)
+    zo = h.vcycle(r)
+    del h
+    z64 = s64.vcycle(dev(r)).cpu().numpy()
+    e64 = np.linalg.norm(z64 - zo) / np.linalg.norm(zo)
+    del s64
+    smx = SemSolver(V, N=7, smoother="cheb4opt", pre=4, post=0, precision="mixed", krylov="fcg",
+                    lambda_max=lmax)
+    zmx = smx.vcycle(dev(r)).cpu().numpy()
+    emx = np.linalg.norm(zmx - zo) / np.linalg.norm(zo)
+    print(f"32^3 N=7 cycle vs oracle: fp64 {e64:.2e}, mixed {emx:.2e}", flush=True)
+    assert e64 <= 1e-12  # measured 4.4e-14
+    assert emx <= 2e-3   # measured 2.2e-4
 
 
 def test_cfg3_symmetric_cycle_full_size(cfg3):
