@@ -382,16 +382,26 @@ void vcycle(sem_ctx *c, int j, hipStream_t s) {
   if (pre > 0) {
     smooth<T>(c, L, pre, true, s);
     apply_level<T>(L, x, w, s);
-    launch_resid_weight<T>(L, w, b, r, s);
   } else {
     launch_zero<T>(L.n, x, s);
-    launch_resid_weight<T>(L, (const T *)nullptr, b, r, s);
   }
+  const T *ad = pre > 0 ? w : (const T *)nullptr;  // A x (element-local on SEM levels)
   Level &C = c->levels[j + 1];
   if (L.type == LVL_SEM) {
-    launch_restrict<T>(L, C, r, V<T>::J(L), V<T>::w(C), s);
+    // the weighted residual is formed inside the restriction where a row-blocked kernel
+    // exists for the order pair (the residual vector is then neither written nor read), in
+    // FP64 and on levels of order <= 3. On a large single-precision level the separate
+    // residual pass is faster: its strided gather of the element copies coalesces better
+    // than the row kernel's (32^3, N = 7: 33 + 23 us separate against 61 us fused; FP64
+    // 56 + 34 against 85 us; 3 -> 1: 13.6 against 10.2 us)
+    const bool fuse = sizeof(T) == sizeof(double) || L.N <= 3;
+    if (!(fuse && launch_restrict_resid<T>(L, C, ad, b, V<T>::J(L), V<T>::w(C), s))) {
+      launch_resid_weight<T>(L, ad, b, r, s);
+      launch_restrict<T>(L, C, r, V<T>::J(L), V<T>::w(C), s);
+    }
     launch_dss<T>(C, V<T>::w(C), V<T>::b(C), s);
   } else {
+    launch_resid_weight<T>(L, ad, b, r, s);
     launch_csr<T>(L.R, V<T>::val(L.R), r, (const T *)nullptr, V<T>::b(C), 0, s);
   }
   vcycle<T>(c, j + 1, s);

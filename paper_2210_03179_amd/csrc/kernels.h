@@ -49,6 +49,12 @@ template <typename T>
 void launch_resid_weight(const Level &L, const T *wL, const T *b, T *rw, hipStream_t s);
 template <typename T>
 void launch_restrict(const Level &F, const Level &C, const T *rw, const T *J, T *rcL, hipStream_t s);
+// The restriction of the weighted residual (b - DSS(wL)) / multiplicity (b / multiplicity when
+// wL is nullptr) formed inside the row-blocked kernel, without the residual vector: false
+// (nothing launched) when the order pair has no row-blocked kernel.
+template <typename T>
+bool launch_restrict_resid(const Level &F, const Level &C, const T *wL, const T *b, const T *J, T *rcL,
+                           hipStream_t s);
 template <typename T>
 // zout (one-sided mixed cycle): write the widened result z instead of updating xf; with dr1
 // (and dr2) also the partial sums of z . dr1 (z . dr2) into partials[block * nd + q], nd = 1

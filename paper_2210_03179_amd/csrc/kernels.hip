@@ -353,7 +353,8 @@ constexpr int prolong_ex() {
 
 template <typename T, int NF, int NC>
 __global__ void __launch_bounds__(256)
-restrict_rows_kernel(Box fb, Box cb, const T *__restrict__ rw, const T *__restrict__ Jm, T *__restrict__ rcL) {
+restrict_rows_kernel(Box fb, Box cb, const T *__restrict__ rw, const T *__restrict__ Jm, T *__restrict__ rcL,
+                     const T *__restrict__ wL, const T *__restrict__ bvec) {
   constexpr int nf = NF + 1, nc = NC + 1, EX = rows_ex<NF, NC, T>(), RW = EX * NF + 1;
   __shared__ T sJ[nf * nc];
   __shared__ T srow[nf * nf * RW];         // fine rows [k][j][i_global]
@@ -366,20 +367,32 @@ restrict_rows_kernel(Box fb, Box cb, const T *__restrict__ rw, const T *__restri
   const int nel = fb.nex - ex0 < EX ? fb.nex - ex0 : EX;
   const int t = threadIdx.x;
   // stage the fine rows: when a thread's share is small (kL values) all of its loads are
-  // issued before the first LDS store, so they are in flight together
+  // issued before the first LDS store, so they are in flight together. With rw == nullptr
+  // the weighted residual is formed here, as resid_weight_body forms it (same operations,
+  // same order): (b - sum of the element copies of wL) / multiplicity, or b / multiplicity
+  // without wL
   constexpr int kL = (nf * nf * RW + 255) / 256;
+  auto fine = [&](int64_t g, int I, int J, int K) -> T {
+    if (rw) return rw[g];
+    const Ijk cc{I, J, K};
+    T v = bvec[g];
+    int faces;
+    if (wL) v -= dss_ijk(wL, fb, cc, &faces);
+    else faces = face_count(fb, cc);
+    return v * (T)inv_mult_faces(faces);
+  };
   if constexpr (kL <= 24) {
     T v[kL];
 #pragma unroll
     for (int it = 0; it < kL; ++it) {
       const int q = t + 256 * it;
-      int64_t g = -1;
+      v[it] = T(0);
       if (q < nf * nf * RW) {
         const int ig = q % RW, j = (q / RW) % nf, k = q / (RW * nf);
-        g = lattice_index(fb, ex0 * NF + ig, ey * NF + j, ez * NF + k);
+        const int I = ex0 * NF + ig, J = ey * NF + j, K = ez * NF + k;
+        const int64_t g = lattice_index(fb, I, J, K);
+        if (g >= 0) v[it] = fine(g, I, J, K);
       }
-      const T x = rw[g >= 0 ? g : 0];
-      v[it] = g >= 0 ? x : T(0);
     }
 #pragma unroll
     for (int it = 0; it < kL; ++it)
@@ -387,9 +400,9 @@ restrict_rows_kernel(Box fb, Box cb, const T *__restrict__ rw, const T *__restri
   } else {
     for (int q = t; q < nf * nf * RW; q += 256) {
       const int ig = q % RW, j = (q / RW) % nf, k = q / (RW * nf);
-      const int64_t g = lattice_index(fb, ex0 * NF + ig, ey * NF + j, ez * NF + k);
-      const T x = rw[g >= 0 ? g : 0];
-      srow[q] = g >= 0 ? x : T(0);
+      const int I = ex0 * NF + ig, J = ey * NF + j, K = ez * NF + k;
+      const int64_t g = lattice_index(fb, I, J, K);
+      srow[q] = g >= 0 ? fine(g, I, J, K) : T(0);
     }
   }
   for (int q = t; q < nf * nc; q += 256) sJ[q] = Jm[q];
@@ -1475,7 +1488,7 @@ void launch_restrict(const Level &F, const Level &C, const T *rw, const T *J, T 
     constexpr int ex = rows_ex<A, B, T>();                                                              \
     const unsigned grid = (unsigned)(((F.nex + ex - 1) / ex) * (int64_t)F.ney * F.nez);                \
     hipLaunchKernelGGL((restrict_rows_kernel<T, A, B>), dim3(grid), dim3(256), 0, s, mkbox(F), mkbox(C), rw, \
-                       J, rcL);                                                                         \
+                       J, rcL, (const T *)nullptr, (const T *)nullptr);                                 \
     return;                                                                                             \
   }
   SEMCHEB_TRANSFER_PAIRS(SEMCHEB_PICK)
@@ -1483,6 +1496,26 @@ void launch_restrict(const Level &F, const Level &C, const T *rw, const T *J, T 
   hipLaunchKernelGGL((restrict_kernel<T, 0, 0>), dim3((unsigned)F.E), dim3(128), lds, s, mkbox(F), mkbox(C), F.E,
                      rw, J, rcL);
 }
+
+template <typename T>
+bool launch_restrict_resid(const Level &F, const Level &C, const T *wL, const T *b, const T *J, T *rcL,
+                           hipStream_t s) {
+#define SEMCHEB_PICK(A, B)                                                                              \
+  if (F.N == A && C.N == B) {                                                                           \
+    constexpr int ex = rows_ex<A, B, T>();                                                              \
+    const unsigned grid = (unsigned)(((F.nex + ex - 1) / ex) * (int64_t)F.ney * F.nez);                \
+    hipLaunchKernelGGL((restrict_rows_kernel<T, A, B>), dim3(grid), dim3(256), 0, s, mkbox(F), mkbox(C), \
+                       (const T *)nullptr, J, rcL, wL, b);                                              \
+    return true;                                                                                        \
+  }
+  SEMCHEB_TRANSFER_PAIRS(SEMCHEB_PICK)
+#undef SEMCHEB_PICK
+  return false;
+}
+template bool launch_restrict_resid<double>(const Level &, const Level &, const double *, const double *,
+                                            const double *, double *, hipStream_t);
+template bool launch_restrict_resid<float>(const Level &, const Level &, const float *, const float *,
+                                           const float *, float *, hipStream_t);
 template void launch_restrict<double>(const Level &, const Level &, const double *, const double *, double *,
                                       hipStream_t);
 template void launch_restrict<float>(const Level &, const Level &, const float *, const float *, float *,
