@@ -353,6 +353,17 @@ void coarse_solve64(sem_ctx *c, const double *b, double *x, hipStream_t s) {
   coarse_solve_blocks(c, b, x, false, s);
 }
 
+// In a single-precision cycle the order-1 coarse level's right-hand side is summed straight
+// into the coarse solver's FP64 vector, and the prolongation from it reads the FP64 solution,
+// when the level above is an SEM level with a row-blocked transfer to order 1 (no precision
+// conversions around the coarse solve then).
+bool coarse_wide(const sem_ctx *c) {
+  const size_t m = c->levels.size();
+  if (m < 2) return false;
+  const Level &P = c->levels[m - 2], &L = c->levels[m - 1];
+  return P.type == LVL_SEM && L.type == LVL_SEM && L.N == 1 && prolong_rows_available(P.N, 1);
+}
+
 template <typename T>
 void coarse_solve(sem_ctx *c, Level &L, hipStream_t s);
 template <>
@@ -363,9 +374,10 @@ template <>
 void coarse_solve<float>(sem_ctx *c, Level &L, hipStream_t s) {
   CoarseSolver &C = c->coarse;
   if (C.n == 0) return;
-  launch_convert(C.n, L.b32, C.b, s);
+  const bool wide = coarse_wide(c);
+  if (!wide) launch_convert(C.n, L.b32, C.b, s);
   coarse_solve_blocks(c, C.b, C.x, C.has32, s);
-  launch_convert(C.n, C.x, L.x32, s);
+  if (!wide) launch_convert(C.n, C.x, L.x32, s);
 }
 
 // One V-cycle on level j: x_j = V_j(b_j) (eq. recursive-v-cycle-err-prop; one-sided
@@ -387,6 +399,9 @@ void vcycle(sem_ctx *c, int j, hipStream_t s) {
   }
   const T *ad = pre > 0 ? w : (const T *)nullptr;  // A x (element-local on SEM levels)
   Level &C = c->levels[j + 1];
+  // single-precision cycle above the order-1 coarse level: FP64 coarse vectors used directly
+  const bool wide = sizeof(T) == sizeof(float) && j + 2 == (int)c->levels.size() && c->coarse.n > 0 &&
+                    coarse_wide(c);
   if (L.type == LVL_SEM) {
     // the weighted residual is formed inside the restriction where a row-blocked kernel
     // exists for the order pair (the residual vector is then neither written nor read), in
@@ -399,7 +414,8 @@ void vcycle(sem_ctx *c, int j, hipStream_t s) {
       launch_resid_weight<T>(L, ad, b, r, s);
       launch_restrict<T>(L, C, r, V<T>::J(L), V<T>::w(C), s);
     }
-    launch_dss<T>(C, V<T>::w(C), V<T>::b(C), s);
+    if (wide) launch_dss_wide(C, C.w32, c->coarse.b, s);
+    else launch_dss<T>(C, V<T>::w(C), V<T>::b(C), s);
   } else {
     launch_resid_weight<T>(L, ad, b, r, s);
     launch_csr<T>(L.R, V<T>::val(L.R), r, (const T *)nullptr, V<T>::b(C), 0, s);
@@ -414,7 +430,8 @@ void vcycle(sem_ctx *c, int j, hipStream_t s) {
   const bool zdots = last && (zout || sizeof(T) == sizeof(double));
   if (L.type == LVL_SEM) {
     const int nb = launch_prolong<T>(L, C, V<T>::x(C), V<T>::J(L), x, zout, s, zdots ? c->zdot_r1 : nullptr,
-                                     zdots ? c->zdot_r2 : nullptr, c->partials, c->partials_cap);
+                                     zdots ? c->zdot_r2 : nullptr, c->partials, c->partials_cap,
+                                     wide ? c->coarse.x : nullptr);
     if (zdots) c->zdot_blocks = nb;
   } else launch_csr<T>(L.P, V<T>::val(L.P), V<T>::x(C), (const T *)nullptr, x, 2, s);
   if (post > 0) smooth<T>(c, L, post, false, s);

@@ -61,9 +61,15 @@ template <typename T>
 // (2), z being the result written (zout, else the updated xf). Returns the number of blocks
 // that wrote them, 0 when none did (orders without the row-blocked kernel, or more blocks
 // than partials_cap / nd).
+// xc64 (single precision, order-1 coarse level, row-blocked pairs only): read the coarse
+// values from this FP64 vector instead of xc.
 int launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *xf, double *zout, hipStream_t s,
                    const double *dr1 = nullptr, const double *dr2 = nullptr, double *partials = nullptr,
-                   int64_t partials_cap = 0);
+                   int64_t partials_cap = 0, const double *xc64 = nullptr);
+// whether (nf, nc) has the row-blocked transfer kernels
+bool prolong_rows_available(int nf, int nc);
+// summation of a single-precision element-local vector into an FP64 global one
+void launch_dss_wide(const Level &L, const float *wL, double *out, hipStream_t s);
 template <typename T>
 void launch_csr(const DevCsr &A, const T *val, const T *x, const T *b, T *y, int mode, hipStream_t s);
 void launch_gemv(int64_t nrows, int64_t ncols, const double *M, const double *x, const double *b, double *y,

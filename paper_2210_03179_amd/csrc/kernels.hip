@@ -45,10 +45,10 @@ ax_tri_kernel(Box b, int64_t E, const T *__restrict__ u, const T *__restrict__ t
 }
 
 // ------------------------------------------------------------------ summation / vector kernels
-template <typename T>
-__global__ void dss_kernel(Box b, int64_t n, const T *__restrict__ wL, T *__restrict__ out) {
+template <typename T, typename TO = T>
+__global__ void dss_kernel(Box b, int64_t n, const T *__restrict__ wL, TO *__restrict__ out) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < n) out[g] = dss_at(wL, b, g);
+  if (g < n) out[g] = (TO)dss_at(wL, b, g);
 }
 
 // Block reduction of one double to thread 0 (fixed order).
@@ -434,9 +434,9 @@ restrict_rows_kernel(Box fb, Box cb, const T *__restrict__ rw, const T *__restri
   }
 }
 
-template <typename T, int NF, int NC>
+template <typename T, int NF, int NC, typename TC = T>
 __global__ void __launch_bounds__(256)
-prolong_rows_kernel(Box fb, Box cb, const T *__restrict__ xc, const T *__restrict__ Jm, T *__restrict__ xf,
+prolong_rows_kernel(Box fb, Box cb, const TC *__restrict__ xc, const T *__restrict__ Jm, T *__restrict__ xf,
                     double *__restrict__ zout, const double *__restrict__ dr1, const double *__restrict__ dr2,
                     double *__restrict__ partials) {
   constexpr int nf = NF + 1, nc = NC + 1, EX = prolong_ex<NF, NC, T>();
@@ -479,7 +479,7 @@ prolong_rows_kernel(Box fb, Box cb, const T *__restrict__ xc, const T *__restric
   for (int q = t; q < EX * nc * nc * nc; q += 256) {
     const int a = q % nc, bq = (q / nc) % nc, c = (q / (nc * nc)) % nc, el = q / (nc * nc * nc);
     const int64_t g = el < nel ? lattice_index(cb, (ex0 + el) * NC + a, ey * NC + bq, ez * NC + c) : -1;
-    const T v = xc[g >= 0 ? g : 0];
+    const T v = (T)xc[g >= 0 ? g : 0];
     sc[q] = g >= 0 ? v : T(0);
   }
   __syncthreads();
@@ -1523,7 +1523,8 @@ template void launch_restrict<float>(const Level &, const Level &, const float *
 
 template <typename T>
 int launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *xf, double *zout, hipStream_t s,
-                   const double *dr1, const double *dr2, double *partials, int64_t partials_cap) {
+                   const double *dr1, const double *dr2, double *partials, int64_t partials_cap,
+                   const double *xc64) {
   const int nf = F.N + 1, nc = C.N + 1;
   const size_t lds = sizeof(T) * (size_t)(nf * nc + nc * nc * nc + nc * nc * nf + nc * nf * nf);
 #define SEMCHEB_PICK(A, B)                                                                              \
@@ -1531,6 +1532,14 @@ int launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *x
     constexpr int ex = prolong_ex<A, B, T>();                                                           \
     const unsigned grid = (unsigned)(((F.nex + ex - 1) / ex) * (int64_t)F.ney * F.nez);                \
     const bool dots = dr1 && partials && (int64_t)grid * (dr2 ? 2 : 1) <= partials_cap;                 \
+    if constexpr (sizeof(T) == 4 && B == 1) {                                                           \
+      if (xc64) {                                                                                       \
+        hipLaunchKernelGGL((prolong_rows_kernel<T, A, B, double>), dim3(grid), dim3(256), 0, s, mkbox(F), \
+                           mkbox(C), xc64, J, xf, zout, dots ? dr1 : nullptr, dots ? dr2 : nullptr,     \
+                           dots ? partials : nullptr);                                                  \
+        return dots ? (int)grid : 0;                                                                    \
+      }                                                                                                 \
+    }                                                                                                   \
     hipLaunchKernelGGL((prolong_rows_kernel<T, A, B>), dim3(grid), dim3(256), 0, s, mkbox(F), mkbox(C), xc, J, \
                        xf, zout, dots ? dr1 : nullptr, dots ? dr2 : nullptr, dots ? partials : nullptr); \
     return dots ? (int)grid : 0;                                                                        \
@@ -1542,9 +1551,23 @@ int launch_prolong(const Level &F, const Level &C, const T *xc, const T *J, T *x
   return 0;
 }
 template int launch_prolong<double>(const Level &, const Level &, const double *, const double *, double *,
-                                    double *, hipStream_t, const double *, const double *, double *, int64_t);
+                                    double *, hipStream_t, const double *, const double *, double *, int64_t,
+                                    const double *);
 template int launch_prolong<float>(const Level &, const Level &, const float *, const float *, float *,
-                                   double *, hipStream_t, const double *, const double *, double *, int64_t);
+                                   double *, hipStream_t, const double *, const double *, double *, int64_t,
+                                   const double *);
+
+bool prolong_rows_available(int nf, int nc) {
+#define SEMCHEB_HAS(A, B) \
+  if (nf == A && nc == B) return true;
+  SEMCHEB_TRANSFER_PAIRS(SEMCHEB_HAS)
+#undef SEMCHEB_HAS
+  return false;
+}
+
+void launch_dss_wide(const Level &L, const float *wL, double *out, hipStream_t s) {
+  hipLaunchKernelGGL((dss_kernel<float, double>), dim3(nblk(L.n)), dim3(256), 0, s, mkbox(L), L.n, wL, out);
+}
 
 template <typename T>
 void launch_csr(const DevCsr &A, const T *val, const T *x, const T *b, T *y, int mode, hipStream_t s) {
