@@ -12,9 +12,11 @@ Both forms are timed on the same GPU: the mixed-precision form (FP32 smoothing
 with BF16 geometric factors inside an FP64 flexible CG, FP64 coarse solve) is
 the reported `value`; the all-FP64 form is reported beside it.
 
-Prints one JSON line (see the fields below). `roofline` is for the dominant
-kernel, the element-local SEM operator, timed with HIP events on the stream
-the library launches on.
+Prints one JSON line (see the fields below). `roofline` is for apply_A, the
+element operator with its direct-stiffness summation, priced with the byte model
+48 L + 16 n (FP64 factors per local node, u and w once per unknown) and timed
+with HIP events on the stream the library launches on; the operator kernel alone
+and the mixed cycle's BF16 operator are reported beside it.
 """
 from __future__ import annotations
 
@@ -69,6 +71,8 @@ def kernel_only(args):
     u32, w32 = u.float(), torch.empty(nloc, dtype=torch.float32, device="cuda")
     t64 = time_kernel(lambda: s64.apply_local(u, w), args.kernel_reps)
     tmx = time_kernel(lambda: smx.apply_local(u32, w32), args.kernel_reps)
+    wg = torch.empty(n, dtype=torch.float64, device="cuda")
+    tap = time_kernel(lambda: s64.apply_A(u, wg), args.kernel_reps)  # operator + summation
     # the same operator with factors formed in the kernel (trilinear geometry option)
     st64 = SemSolver(V, N=args.order, precision="fp64", lambda_max=lam, geometry="trilinear")
     stmx = SemSolver(V, N=args.order, precision="mixed", lambda_max=lam, geometry="trilinear")
@@ -82,6 +86,7 @@ def kernel_only(args):
     print(json.dumps({"kernel_only": True, "unknowns": n, "local_nodes": nloc,
                       "copy_bytes": 2 * src.numel() * 8, "copy_us": tcp * 1e6,
                       "copy_GBs": 2 * src.numel() * 8 / tcp / 1e9,
+                      "apply_A_fp64_us": tap * 1e6, "apply_A_fp64_GBs": (48.0 * nloc + 16.0 * n) / tap / 1e9,
                       "ax_fp64_us": t64 * 1e6, "ax_fp64_GBs": (56.0 * nloc + 8.0 * n) / t64 / 1e9,
                       "ax_bf16_us": tmx * 1e6, "ax_bf16_GBs": (16.0 * nloc + 4.0 * n) / tmx / 1e9,
                       "ax_trilinear_fp64_us": tt64 * 1e6, "ax_trilinear_fp32_us": ttmx * 1e6}), flush=True)
@@ -211,22 +216,44 @@ def bench_batched(steps, nsys=64):
 
 
 def cpu_baseline(m, N, n_global):
-    """The oracle (numpy FP64) on the same workload: one flexible-CG iteration
-    (one V-cycle plus one operator application and the vector updates) timed on
-    the host. The lambda_max values do not change the cost and are set to 2."""
+    """The oracle (numpy FP64) on the same workload, one thread: exactly one flexible-CG
+    iteration, i.e. one operator application w = A p, the residual and iterate updates with
+    their dot products, and one V-cycle z = M r, each timed on the host with the oracle's
+    own functions and summed. BLAS is limited to one thread for the timed calls; numpy's
+    einsum contractions, the oracle's main cost, run on one thread anyway. lambda_max does
+    not change the cost and is set to 2 (no Lanczos run)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
     import workload as wl
-    from oracle import chebyshev as cheb, krylov, mg
-    V = wl.deformed_box(m, 0.05)
-    h = mg.sem_hierarchy(V, N, cheb.CHEB4_OPT, 4, 0, lmax=[2.0, 2.0])
-    box = h.extra["boxes"][0]
-    b = box.mass() * wl.manufactured_load(box.coords())
-    t0 = time.perf_counter()
-    krylov.pcg(box.apply, b, h.vcycle, 1e-8, 1, flexible=True)
-    dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    from oracle import chebyshev as cheb, mg
+    with threadpool_limits(limits=1):
+        threads = max([1] + [int(d.get("num_threads", 1)) for d in threadpool_info()])
+        V = wl.deformed_box(m, 0.05)
+        h = mg.sem_hierarchy(V, N, cheb.CHEB4_OPT, 4, 0, lmax=[2.0, 2.0])
+        box = h.extra["boxes"][0]
+        b = box.mass() * wl.manufactured_load(box.coords())
+        r, p, x, r_old = b.copy(), b.copy(), np.zeros_like(b), b.copy()
+        rz = float(b @ b)
+        t0 = time.perf_counter()
+        w = box.apply(p)                      # w = A p
+        t1 = time.perf_counter()
+        alpha = rz / float(p @ w)             # vector part of the iteration (as oracle.krylov.pcg)
+        x = x + alpha * p
+        r_old, r = r, r - alpha * w
+        float(np.linalg.norm(r))
+        t2 = time.perf_counter()
+        z = h.vcycle(r)                       # z = M r
+        t3 = time.perf_counter()
+        beta = float(z @ (r - r_old)) / rz
+        rz = float(r @ z)
+        p = z + beta * p
+        t4 = time.perf_counter()
+    dt = t4 - t0
     return {"value": round(n_global / dt / 1e9, 6), "unit": "GDOF-iter/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"1 flexible-CG iteration (V-cycle + operator) on the {m}^3 N={N} box, {dt:.2f} s"}
+            "sample": f"one flexible-CG iteration on the full {m}^3 N={N} box ({n_global} unknowns), "
+                      f"single thread: operator {t1 - t0:.2f} s + V-cycle {t3 - t2:.2f} s + vector "
+                      f"updates {t2 - t1 + t4 - t3:.2f} s = {dt:.2f} s"}
 
 
 def main():
@@ -277,17 +304,24 @@ def main():
     rel64, relmx = true_rel(u64), true_rel(umx)
     err_mx = float(torch.linalg.vector_norm(umx - u64) / torch.linalg.vector_norm(u64))
 
-    # dominant kernel: element-local operator, FP64 (48 B factors + 8 B output per local node,
-    # 8 B input per unknown) and the BF16/FP32 form (12 + 4 B per local node, 4 B per unknown)
+    # apply_A as the byte model counts it (48 B of FP64 factors per local node, u read and
+    # w written once per unknown: 48 L + 16 n), timed as the complete sem_apply_A (element
+    # operator + direct-stiffness summation) and as the element operator alone; FLOPs of the
+    # tensor-product operator: 12 (N+1)^4 + 17 (N+1)^3 per element (three derivatives and their
+    # transposes, 15 flops of factor products and 2 of sums per node). The mixed cycle's apply:
+    # 12 L + 8 n (BF16 factors, FP32 vectors).
+    E = nloc // (N + 1) ** 3
+    alg64 = 48.0 * nloc + 16.0 * n
+    algmx = 12.0 * nloc + 8.0 * n
+    flops = float(12 * (N + 1) ** 4 + 17 * (N + 1) ** 3) * E
     u_rand = torch.rand(n, dtype=torch.float64, device="cuda")
+    w_glob = torch.empty(n, dtype=torch.float64, device="cuda")
     w_loc = torch.empty(nloc, dtype=torch.float64, device="cuda")
+    t_apply = time_kernel(lambda: s64.apply_A(u_rand, w_glob), args.kernel_reps)
     t_ax64 = time_kernel(lambda: s64.apply_local(u_rand, w_loc), args.kernel_reps)
-    bytes64 = 56.0 * nloc + 8.0 * n
     u32 = u_rand.float()
     w32 = torch.empty(nloc, dtype=torch.float32, device="cuda")
     t_axmx = time_kernel(lambda: smx.apply_local(u32, w32), args.kernel_reps)
-    bytesmx = 16.0 * nloc + 4.0 * n
-    t_apply = time_kernel(lambda: s64.apply_A(u_rand, w_loc[:n]), args.kernel_reps)
     # achievable streaming bandwidth on this device: a 2 GiB device-to-device copy
     # (1 GiB read + 1 GiB written), the reference the operator's fraction can also be read against
     cpy_src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -295,12 +329,12 @@ def main():
     t_copy = time_kernel(lambda: cpy_dst.copy_(cpy_src), 10)
     copy_gbs = 2.0 * cpy_src.numel() * 8 / t_copy / 1e9
     del cpy_src, cpy_dst
-    log(f"ax fp64 {t_ax64 * 1e6:.1f} us ({bytes64 / t_ax64 / 1e9:.0f} GB/s), "
-        f"ax bf16 {t_axmx * 1e6:.1f} us ({bytesmx / t_axmx / 1e9:.0f} GB/s), apply_A fp64 {t_apply * 1e6:.1f} us")
+    log(f"apply_A fp64 {t_apply * 1e6:.1f} us ({alg64 / t_apply / 1e9:.0f} GB/s), element operator fp64 "
+        f"{t_ax64 * 1e6:.1f} us, bf16 {t_axmx * 1e6:.1f} us ({algmx / t_axmx / 1e9:.0f} GB/s)")
 
     gdof_mx = n * infomx.iterations / dtmx / 1e9
     gdof_64 = n * info64.iterations / dt64 / 1e9
-    ach = bytes64 / t_ax64 / 1e9
+    ach = alg64 / t_apply / 1e9
     tune64 = s64.host_array("ax_tuning", 0)
     tunemx = smx.host_array("ax_tuning", 0)
     nvar = (len(tune64) // s64.num_levels - 2) // 2  # per level: variant, times (FP64), variant, times
@@ -314,7 +348,10 @@ def main():
         t64, tmx = tune64[j * per:(j + 1) * per], tunemx[j * per:(j + 1) * per]
         log(f"level {j} operator variants (us) fp64 {[round(x, 1) for x in t64[1:1 + nvar]]} -> {int(t64[0])}, "
             f"bf16 {[round(x, 1) for x in tmx[2 + nvar:2 + 2 * nvar]]} -> {int(tmx[1 + nvar])}")
-    tr64 = measured_traffic(k64) if N == 7 and m == 32 else None
+    kdss = "dss_kernel<double, double>"
+    tr_ax = measured_traffic(k64) if N == 7 and m == 32 else None
+    tr_dss = measured_traffic(kdss) if N == 7 and m == 32 else None
+    tr_apply = tr_ax + tr_dss if (tr_ax is not None and tr_dss is not None) else None
     trmx = measured_traffic(kmx) if N == 7 and m == 32 else None
     out = {
         "metric": "PCG-to-1e-8 solve time & GDOF-iter/s; mixed/batched vs plain FP64 same GPU",
@@ -342,18 +379,29 @@ def main():
                  "gdof_iter_per_s": round(gdof_64, 4), "true_relres": rel64},
         "speedup_mixed_vs_fp64": round(dt64 / dtmx, 4),
         "setup_s": {"fp64": round(t_setup64, 2), "mixed": round(t_setupmx, 2)},
-        # traffic: measured HBM bytes per launch (profiler counters, committed summary) over the
-        # same launch time as `achieved`, in GB/s; null when the summary does not cover the kernel
+        # roofline of apply_A, the kernel pair the byte model prices (element operator + summation,
+        # one sem_apply_A): achieved = algorithmic bytes / its duration (HIP events on the library's
+        # stream); traffic = HBM bytes the profiler counted for the same pair (committed counter
+        # summary, FETCH_SIZE and WRITE_SIZE scaled by a copy of known size) over the same
+        # duration, null when the summary does not cover the current kernels
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": round(tr64 / t_ax64 / 1e9, 1) if tr64 else None,
+                     "traffic": round(tr_apply / t_apply / 1e9, 1) if tr_apply else None,
+                     "kernel": f"apply_A = {k64} + {kdss}", "us": round(t_apply * 1e6, 2),
+                     "algorithmic_bytes": alg64, "traffic_bytes": tr_apply,
                      "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(ach / copy_gbs, 4),
-                     "kernel": k64, "kernel_us": round(t_ax64 * 1e6, 2),
-                     "bytes_per_launch": bytes64, "traffic_bytes_per_launch": tr64,
-                     "mixed_kernel": {"kernel": kmx, "kernel_us": round(t_axmx * 1e6, 2),
-                                      "achieved": round(bytesmx / t_axmx / 1e9, 1),
-                                      "bytes_per_launch": bytesmx,
-                                      "traffic": round(trmx / t_axmx / 1e9, 1) if trmx else None}},
+                     "flops": flops, "TFLOPs": round(flops / t_apply / 1e12, 3), "fp64_peak_TFLOPs": 78.6,
+                     "flop_frac": round(flops / t_apply / 1e12 / 78.6, 4),
+                     "operator_only": {"kernel": k64, "us": round(t_ax64 * 1e6, 2),
+                                       "achieved": round(alg64 / t_ax64 / 1e9, 1),
+                                       "frac": round(alg64 / t_ax64 / 1e9 / HBM_PEAK_GBS, 4),
+                                       "traffic": round(tr_ax / t_ax64 / 1e9, 1) if tr_ax else None},
+                     "mixed_operator": {"kernel": kmx, "us": round(t_axmx * 1e6, 2),
+                                        "achieved": round(algmx / t_axmx / 1e9, 1),
+                                        "frac": round(algmx / t_axmx / 1e9 / HBM_PEAK_GBS, 4),
+                                        "algorithmic_bytes": algmx,
+                                        "TFLOPs": round(flops / t_axmx / 1e12, 3), "fp32_peak_TFLOPs": 157.3,
+                                        "traffic": round(trmx / t_axmx / 1e9, 1) if trmx else None}},
     }
     # Table ksp-comparison analogue: time per iteration of GMRES(30) (classical Gram-Schmidt)
     # against flexible CG, same mixed-precision preconditioner

@@ -100,7 +100,7 @@ enum { SEM_GEOM_STORED = 0, SEM_GEOM_TRILINEAR = 1 };
 #define SEM_MAX_LEVELS 8
 
 typedef struct {
-  int32_t N;                        /* finest polynomial order, 1..15 */
+  int32_t N;                        /* finest polynomial order, 1..12 */
   int32_t num_levels;               /* 0: default schedule N, floor(N/2), 1 */
   int32_t orders[SEM_MAX_LEVELS];   /* decreasing orders, last must be 1 */
   int32_t smoother;                 /* SEM_CHEB1 ... SEM_CHEB4_OPT */
@@ -258,8 +258,8 @@ sem_status sem_set_smoothing(sem_ctx *ctx, int32_t smoother, int32_t pre_order, 
  * cycle and Krylov settings of *opt and a mixed-precision cycle (FP32 arithmetic,
  * BF16 geometric factors, FP64 Krylov and coarse solve). lambda_max is estimated per
  * system and level. meshes, orders: host arrays of nsys entries. Same errors as
- * sem_setup_box, plus SEM_EINVAL for pre_order < 1, a given lambda_max/schedule, or
- * an outer method other than SEM_PCG and SEM_FCG. */
+ * sem_setup_box, plus SEM_EINVAL for pre_order < 1, pre_order or post_order > 16, a
+ * given lambda_max/schedule, or an outer method other than SEM_PCG and SEM_FCG. */
 sem_status sem_setup_batched(int32_t nsys, const sem_box_mesh *meshes, const int32_t *orders,
                              const sem_options *opt, void *stream, sem_ctx **out);
 

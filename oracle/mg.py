@@ -91,8 +91,45 @@ def lambda_max_nonsym(A, S, n: int) -> float:
     return float(np.max(np.linalg.eigvals(SA).real))
 
 
+def trilinear_1d(m: int) -> sp.csr_matrix:
+    """1D linear interpolation from the interior vertices of m/2 uniform intervals to those
+    of m intervals: fine vertex 2I takes coarse vertex I, an odd fine vertex the mean of its
+    two coarse neighbours (a boundary neighbour is a Dirichlet zero). Tensor products of it
+    interpolate trilinearly."""
+    mc = m // 2
+    rows, cols, vals = [], [], []
+    for I in range(1, mc):
+        for d, wgt in ((-1, 0.5), (0, 1.0), (1, 0.5)):
+            rows.append(2 * I + d - 1)
+            cols.append(I - 1)
+            vals.append(wgt)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(m - 1, mc - 1))
+
+
+def q1_lattice_levels(box1: SemBox, dense_max: int):
+    """Geometric multigrid on the order-1 (Q1) vertex lattice below the p-levels.
+
+    The paper solves its order-1 level with one algebraic multigrid V-cycle (Sec. 4.1); on
+    a structured box the vertex lattice coarsens geometrically: lattices of m, m/2, m/4, ...
+    elements per direction, trilinear interpolation P_j (the Kronecker product of the 1D
+    interpolations, x fastest) and Galerkin operators A_{j+1} = P_j^T A_j P_j (eq.
+    galerkin-coarse-grid), until a level has at most dense_max unknowns or a direction can
+    no longer be halved. Returns (As, Ps): As[0] is the assembled order-1 operator, Ps[j]
+    interpolates level j+1 to level j."""
+    As, Ps = [box1.assemble()], []
+    m = [box1.mx, box1.my, box1.mz]
+    while As[-1].shape[0] > dense_max and all(v % 2 == 0 and v >= 4 for v in m):
+        Px, Py, Pz = (trilinear_1d(v) for v in m)
+        P = sp.kron(Pz, sp.kron(Py, Px)).tocsr()
+        Ps.append(P)
+        As.append((P.T @ As[-1] @ P).tocsr())
+        m = [v // 2 for v in m]
+    return As, Ps
+
+
 def sem_hierarchy(verts, N: int, kind: str, pre: int, post: int, orders=None,
-                  lmax=None, lanczos_seed: int = 7, schwarz: str | None = None) -> Hierarchy:
+                  lmax=None, lanczos_seed: int = 7, schwarz: str | None = None,
+                  coarse: str = "exact", dense_max: int = 4096) -> Hierarchy:
     """p-multigrid hierarchy with rediscretised SEM levels on the same vertices.
 
     lmax: optional list of lambda_max(S_j A_j) per smoothed level; otherwise
@@ -100,25 +137,49 @@ def sem_hierarchy(verts, N: int, kind: str, pre: int, post: int, orders=None,
     schwarz: None for Jacobi smoothing, "asm" or "ras" for the Schwarz smoothers of
     Sec. 4.1 (eq. asm) inside the same Chebyshev algorithms; their lambda_max is
     estimated densely (small problems only) unless given.
+    coarse: "exact" solves the order-1 level exactly (M_l^{-1} = A_l^{-1}, Sec. 2);
+    "hmg" continues the V-cycle below order 1 on the Q1 vertex lattice
+    (q1_lattice_levels) with the same Jacobi-Chebyshev smoothing, and solves only the
+    last lattice level (at most dense_max unknowns) exactly. It equals "exact" when the
+    order-1 level already has at most dense_max unknowns.
     """
     from .schwarz import SchwarzLevel
     orders = default_orders(N) if orders is None else list(orders)
     boxes = [SemBox(verts, o) for o in orders]
+    hAs, hPs = q1_lattice_levels(boxes[-1], dense_max) if coarse == "hmg" else ([None], [])
+    nh = len(hPs)  # smoothed lattice levels (the order-1 level among them when nh > 0)
+    nsm = len(boxes) - 1 + nh
     levels = []
-    for j, bx in enumerate(boxes):
-        smoothed = j < len(boxes) - 1
-        S = SchwarzLevel(bx, schwarz) if (schwarz and smoothed) else 1.0 / bx.diag()
-        lev = Level(A=bx.apply, Sinv=S, n=bx.n)
-        if smoothed:
+
+    def add_level(Aop, S, n):
+        lev = Level(A=Aop, Sinv=S, n=n)
+        j = len(levels)
+        if j < nsm:
             if lmax is not None:
                 lev.lmax = float(lmax[j])
-            elif schwarz:
-                lev.lmax = lambda_max_nonsym(bx.apply, S, bx.n)
-            else:
-                lev.lmax = lambda_max_SA(bx.apply, lev.Sinv, bx.n, seed=lanczos_seed)
+            elif isinstance(S, np.ndarray):   # Jacobi: S A is similar to a symmetric matrix
+                lev.lmax = lambda_max_SA(Aop, S, n, seed=lanczos_seed)
+            else:                             # a Schwarz smoother
+                lev.lmax = lambda_max_nonsym(Aop, S, n)
         levels.append(lev)
-    tr = [SemTransfer(boxes[j], boxes[j + 1]) for j in range(len(boxes) - 1)]
-    coarse = exact_coarse(boxes[-1].assemble())
-    return Hierarchy(levels=levels, prolong=[t.prolong for t in tr],
-                     restrict=[t.restrict for t in tr], coarse_solve=coarse,
-                     kind=kind, pre=pre, post=post, extra={"boxes": boxes, "orders": orders})
+
+    for j, bx in enumerate(boxes[:-1]):
+        add_level(bx.apply, SchwarzLevel(bx, schwarz) if schwarz else 1.0 / bx.diag(), bx.n)
+    prolong = [SemTransfer(boxes[j], boxes[j + 1]) for j in range(len(boxes) - 1)]
+    restrict = [t.restrict for t in prolong]
+    prolong = [t.prolong for t in prolong]
+    if nh == 0:
+        add_level(boxes[-1].apply, 1.0 / boxes[-1].diag(), boxes[-1].n)
+        coarse_solve = exact_coarse(boxes[-1].assemble())
+    else:
+        for A in hAs[:-1]:
+            add_level(lambda x, A=A: A @ x, 1.0 / A.diagonal(), A.shape[0])
+        Ac = hAs[-1]
+        add_level(lambda x, A=Ac: A @ x, 1.0 / Ac.diagonal(), Ac.shape[0])
+        prolong += [(lambda x, P=P: P @ x) for P in hPs]
+        restrict += [(lambda x, P=P: P.T @ x) for P in hPs]
+        coarse_solve = exact_coarse(Ac)
+    return Hierarchy(levels=levels, prolong=prolong, restrict=restrict, coarse_solve=coarse_solve,
+                     kind=kind, pre=pre, post=post,
+                     extra={"boxes": boxes, "orders": orders, "lattice_As": hAs if nh else [],
+                            "lattice_Ps": hPs})

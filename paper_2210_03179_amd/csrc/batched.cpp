@@ -33,9 +33,11 @@ constexpr int kKindBatch = 2;
 
 // Chebyshev coefficients (a, bc, c) of the steps of one smoothing of order k
 // (Algorithms 1 and 2, the same recurrences as the single-system driver).
+// Setup refuses orders k >= kMaxChebSteps; such a k leaves the table zero here as well,
+// so no write can leave it.
 void cheb_coefs(int kind, int k, double lmax, double out[kMaxChebSteps][3]) {
   for (int i = 0; i < kMaxChebSteps; ++i) out[i][0] = out[i][1] = out[i][2] = 0.0;
-  if (k <= 0) return;
+  if (k <= 0 || k >= kMaxChebSteps) return;
   if (kind == SEM_CHEB4 || kind == SEM_CHEB4_OPT) {
     const double *beta = kind == SEM_CHEB4_OPT ? beta_row(k) : nullptr;
     auto B = [&](int i) { return beta ? beta[i - 1] : 1.0; };
@@ -178,8 +180,12 @@ sem_status setup_batched_impl(int nsys, const sem_box_mesh *meshes, const int32_
     c->err = "batched setup needs 1.." + std::to_string(kMaxBatch) + " systems with meshes and orders";
     return SEM_EINVAL;
   }
-  if (opt->device < 0) { c->err = "batched contexts need a device"; return SEM_ENODEV; }
   if (opt->pre_order < 1) { c->err = "batched cycles need pre_order >= 1"; return SEM_EINVAL; }
+  if (opt->pre_order >= kMaxChebSteps || opt->post_order >= kMaxChebSteps) {
+    c->err = "batched cycles take smoothing orders up to " + std::to_string(kMaxChebSteps - 1);
+    return SEM_EINVAL;
+  }
+  if (opt->device < 0) { c->err = "batched contexts need a device"; return SEM_ENODEV; }
   if (opt->schwarz != SEM_JACOBI) { c->err = "batched cycles use Jacobi smoothing"; return SEM_EINVAL; }
   if (opt->geometry != SEM_GEOM_STORED) { c->err = "batched systems use stored factors"; return SEM_EINVAL; }
   if (opt->krylov != SEM_PCG && opt->krylov != SEM_FCG) {

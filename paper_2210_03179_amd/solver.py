@@ -24,10 +24,14 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _ptr(t) -> C.c_void_p:
+def _ptr(t, numel=None, what="tensor") -> C.c_void_p:
+    """Device pointer of a contiguous float64 tensor; with `numel`, the tensor must hold
+    exactly that many elements (the library reads and writes the context's sizes)."""
     torch = _torch()
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
-        raise TypeError("expected a contiguous float64 device tensor")
+        raise TypeError(f"{what}: expected a contiguous float64 device tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what}: expected {numel} elements, got {t.numel()}")
     return C.c_void_p(t.data_ptr())
 
 
@@ -110,27 +114,36 @@ class _Base:
     # ---- device entry points
     def apply_A(self, u, out=None):
         torch = _torch()
+        n = self.n
+        up = _ptr(u, n, "u")
         out = torch.empty_like(u) if out is None else out
-        L.check(self._lib.sem_apply_A(self._ctx, _ptr(u), _ptr(out), _stream()), self._ctx)
+        L.check(self._lib.sem_apply_A(self._ctx, up, _ptr(out, n, "out"), _stream()), self._ctx)
         return out
 
     def vcycle(self, r, out=None):
         torch = _torch()
+        n = self.n
+        rp = _ptr(r, n, "r")
         out = torch.empty_like(r) if out is None else out
-        L.check(self._lib.sem_vcycle(self._ctx, _ptr(r), _ptr(out), _stream()), self._ctx)
+        L.check(self._lib.sem_vcycle(self._ctx, rp, _ptr(out, n, "out"), _stream()), self._ctx)
         return out
 
     def solve(self, b, x0=None, rtol: float = 1e-8, maxit: int = 500, raise_on_fail: bool = False, out=None):
         """Returns (u, SolveInfo). u starts from x0 (zero when None). out: optional preallocated
         tensor like b that receives u (no allocation inside the call)."""
         torch = _torch()
+        n = self.n
+        _ptr(b, n, "b")
+        if x0 is not None:
+            _ptr(x0, n, "x0")
         if out is not None:
+            _ptr(out, n, "out")
             u = out.zero_() if x0 is None else out.copy_(x0)
         else:
             u = torch.zeros_like(b) if x0 is None else x0.clone()
         its, rel = C.c_int32(), C.c_double()
         hist = np.zeros(maxit + 1)
-        st = self._lib.sem_solve(self._ctx, _ptr(b), _ptr(u), float(rtol), int(maxit), C.byref(its),
+        st = self._lib.sem_solve(self._ctx, _ptr(b, n, "b"), _ptr(u, n, "u"), float(rtol), int(maxit), C.byref(its),
                                  C.byref(rel), hist.ctypes.data_as(C.POINTER(C.c_double)), _stream())
         if st not in (L.SEM_OK, L.SEM_ENOTCONV) or (raise_on_fail and st != L.SEM_OK):
             L.check(st, self._ctx)
@@ -182,6 +195,10 @@ class SemSolver(_Base):
         prec = 0 if u.dtype == torch.float64 else 1
         if u.dtype not in (torch.float64, torch.float32) or out.dtype != u.dtype or not u.is_cuda:
             raise TypeError("u and out must be float64 or float32 device tensors")
+        if not (u.is_contiguous() and out.is_contiguous() and out.is_cuda):
+            raise TypeError("u and out must be contiguous device tensors")
+        if u.numel() != self.n or out.numel() != self.n_local:
+            raise ValueError(f"apply_local: u needs {self.n} and out {self.n_local} elements")
         L.check(self._lib.sem_apply_local(self._ctx, prec, C.c_void_p(u.data_ptr()), C.c_void_p(out.data_ptr()),
                                           _stream()), self._ctx)
         return out
@@ -189,30 +206,39 @@ class SemSolver(_Base):
     def coords(self):
         torch = _torch()
         out = torch.empty((self.n, 3), dtype=torch.float64, device="cuda")
-        L.check(self._lib.sem_coords(self._ctx, _ptr(out), _stream()), self._ctx)
+        L.check(self._lib.sem_coords(self._ctx, _ptr(out, 3 * self.n, "xyz"), _stream()), self._ctx)
         return out
 
     def mass_apply(self, f, out=None):
         torch = _torch()
+        n = self.n
+        fp = _ptr(f, n, "f")
         out = torch.empty_like(f) if out is None else out
-        L.check(self._lib.sem_mass_apply(self._ctx, _ptr(f), _ptr(out), _stream()), self._ctx)
+        L.check(self._lib.sem_mass_apply(self._ctx, fp, _ptr(out, n, "out"), _stream()), self._ctx)
         return out
 
     def factors(self):
         torch = _torch()
         out = torch.empty((self.E, 6, self.N + 1, self.N + 1, self.N + 1), dtype=torch.float64, device="cuda")
-        L.check(self._lib.sem_get_factors(self._ctx, _ptr(out), _stream()), self._ctx)
+        L.check(self._lib.sem_get_factors(self._ctx, _ptr(out, self._factor_count(), "G"), _stream()), self._ctx)
         return out
 
+    def _factor_count(self) -> int:
+        return self.E * 6 * (self.N + 1) ** 3
+
     def set_factors(self, G):
-        L.check(self._lib.sem_set_factors(self._ctx, _ptr(G.contiguous()), _stream()), self._ctx)
+        G = G.contiguous()
+        L.check(self._lib.sem_set_factors(self._ctx, _ptr(G, self._factor_count(), "G"), _stream()), self._ctx)
 
     def adjoint_contract(self, lam, u, want_dG=True, want_df=True):
         torch = _torch()
+        n = self.n
+        lp = _ptr(lam, n, "lambda")
+        upp = _ptr(u, n, "u") if u is not None else None
         dG = torch.empty((self.E, 6, self.N + 1, self.N + 1, self.N + 1), dtype=torch.float64,
                          device="cuda") if want_dG else None
         df = torch.empty_like(lam) if want_df else None
-        L.check(self._lib.sem_adjoint_contract(self._ctx, _ptr(lam), _ptr(u) if u is not None else None,
+        L.check(self._lib.sem_adjoint_contract(self._ctx, lp, upp,
                                                _ptr(dG) if dG is not None else None,
                                                _ptr(df) if df is not None else None, _stream()), self._ctx)
         return dG, df
@@ -277,10 +303,11 @@ class BatchedSolver(_Base):
     def solve(self, b, rtol: float = 1e-8, maxit: int = 500):
         """Returns (u, status, iterations per system, relative residual per system)."""
         torch = _torch()
+        bp = _ptr(b, self.n, "b")
         u = torch.empty_like(b)
         its = (C.c_int32 * self.nsys)()
         rel = (C.c_double * self.nsys)()
-        st = self._lib.sem_solve_batched(self._ctx, _ptr(b), _ptr(u), float(rtol), int(maxit), its, rel,
+        st = self._lib.sem_solve_batched(self._ctx, bp, _ptr(u, self.n, "u"), float(rtol), int(maxit), its, rel,
                                          _stream())
         if st not in (L.SEM_OK, L.SEM_ENOTCONV):
             L.check(st, self._ctx)

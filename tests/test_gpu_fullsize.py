@@ -97,9 +97,16 @@ def test_cfg3_vcycle_full_size(cfg3):
                     lambda_max=lmax)
     zmx = smx.vcycle(dev(r)).cpu().numpy()
     emx = np.linalg.norm(zmx - zo) / np.linalg.norm(zo)
-    print(f"32^3 N=7 cycle vs oracle: fp64 {e64:.2e}, mixed {emx:.2e}", flush=True)
-    assert e64 <= 1e-12  # measured 4.4e-14
+    # node by node, relative to the largest entry: FP64 at rounding level; the mixed cycle
+    # within one BF16 unit roundoff (2^-9), the storage rounding of its factors (the 8^3 case
+    # separates that rounding from the FP32 arithmetic against an oracle with rounded factors)
+    m64 = np.max(np.abs(z64 - zo)) / np.max(np.abs(zo))
+    mmx = np.max(np.abs(zmx - zo)) / np.max(np.abs(zo))
+    print(f"32^3 N=7 cycle vs oracle: fp64 {e64:.2e} (max-norm {m64:.2e}), mixed {emx:.2e} "
+          f"(max-norm {mmx:.2e})", flush=True)
+    assert e64 <= 1e-12 and m64 <= 1e-12  # measured 4.4e-14 (2-norm)
     assert emx <= 2e-3   # measured 2.2e-4
+    assert mmx <= 2.0 ** -9
 
 
 def test_cfg3_symmetric_cycle_full_size(cfg3):
@@ -136,3 +143,4 @@ def test_cfg4_batched_full_size():
         bx = SemBox(verts[q], specs[q].N)
         uq = u[bs.offsets[q]:bs.offsets[q + 1]].cpu().numpy()
         assert np.linalg.norm(rhs[q] - bx.apply(uq)) <= 1.01e-8 * np.linalg.norm(rhs[q]), q
+

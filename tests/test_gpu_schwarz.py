@@ -73,6 +73,80 @@ def test_schwarz_lambda_estimate(mesh, lmax_ref, sw):
         assert abs(a - b) <= 1e-3 * b, (est, lmax_ref[sw])
 
 
+# ---- the order the bench times: schedule (7,3,1) on a 3x3x3 mesh, where the middle element
+# has neighbours on every side (full extended boxes in x, y and z) and the FDM kernel runs
+# its order-7 instantiation ((N+3)^3 = 10^3 boxes). lambda_max comes from the GPU's Arnoldi
+# estimate and is handed to the oracle (its dense estimate is compared on the small mesh above).
+ORDERS7 = [7, 3, 1]
+
+
+@pytest.fixture(scope="module")
+def mesh3():
+    return wl.deformed_box(3, 0.05)
+
+
+@pytest.fixture(scope="module")
+def lmax7(mesh3):
+    out = {}
+    for sw in ("asm", "ras"):
+        s = SemSolver(mesh3, N=7, orders=ORDERS7, smoother="cheb4", pre=2, post=2, schwarz=sw)
+        out[sw] = [float(x) for x in s.lambda_max()]
+        s.close()
+    return out
+
+
+def relmax(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("sw", ["asm", "ras"])
+@pytest.mark.parametrize("kind,pre,post", [("cheb4", 2, 2), ("cheb1", 3, 0), ("cheb4opt", 4, 0), ("cheb1opt", 1, 2)])
+def test_schwarz_order7_vcycle_parity(mesh3, lmax7, sw, kind, pre, post):
+    print(f"schwarz order 7 {sw} {kind} ({pre},{post})", flush=True)
+    lmax = lmax7[sw]
+    ref = mg.sem_hierarchy(mesh3, 7, kind, pre, post, orders=ORDERS7, lmax=lmax, schwarz=sw)
+    s = SemSolver(mesh3, N=7, orders=ORDERS7, smoother=kind, pre=pre, post=post, lambda_max=lmax, schwarz=sw)
+    r = wl.uniform_noise(ref.levels[0].n, 23)
+    z = s.vcycle(dev(r)).cpu().numpy()
+    zo = ref.vcycle(r)
+    assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+    assert relmax(z, zo) <= 1e-12
+
+
+@pytest.mark.parametrize("sw", ["asm", "ras"])
+def test_schwarz_order7_gmres_parity(mesh3, lmax7, sw):
+    lmax = lmax7[sw]
+    ref = mg.sem_hierarchy(mesh3, 7, cheb.CHEB4, 2, 0, orders=ORDERS7, lmax=lmax, schwarz=sw)
+    box = ref.extra["boxes"][0]
+    b = box.mass() * wl.manufactured_load(box.coords()) + 1e-3 * wl.uniform_noise(box.n, 0)
+    res = krylov.fgmres(box.apply, b, ref.vcycle, 1e-8, restart=30, maxit=100)
+    s = SemSolver(mesh3, N=7, orders=ORDERS7, smoother="cheb4", pre=2, post=0, lambda_max=lmax, schwarz=sw,
+                  krylov="gmres", restart=30)
+    u, info = s.solve(dev(b), rtol=1e-8, maxit=100)
+    print(f"schwarz order 7 {sw} GMRES: {info.iterations} iterations (oracle {res.iterations})", flush=True)
+    assert info.converged and res.converged and info.iterations == res.iterations
+    assert np.max(np.abs(info.history - np.array(res.history))) <= 1e-11 * np.linalg.norm(b)
+    assert np.linalg.norm(u.cpu().numpy() - res.x) <= 1e-10 * np.linalg.norm(res.x)
+
+
+def test_schwarz_order7_mixed_cycle_elementwise(mesh3, lmax7):
+    """The mixed-precision RAS cycle the bench times (4th kind (2,0), FP32 FDM data and
+    arithmetic, BF16 factors in the operator) against the FP64 oracle, node by node: the
+    largest deviation at any node relative to the largest entry. The BF16 factors carry a
+    relative rounding of 2^-9 into every fine operator application of the cycle, the FP32
+    FDM solves a much smaller one; a few such perturbations, 5 * 2^-9 < 1e-2, bound it."""
+    lmax = lmax7["ras"]
+    ref = mg.sem_hierarchy(mesh3, 7, cheb.CHEB4, 2, 0, orders=ORDERS7, lmax=lmax, schwarz="ras")
+    s = SemSolver(mesh3, N=7, orders=ORDERS7, smoother="cheb4", pre=2, post=0, lambda_max=lmax, schwarz="ras",
+                  precision="mixed", krylov="gmres")
+    r = wl.uniform_noise(ref.levels[0].n, 24)
+    z = s.vcycle(dev(r)).cpu().numpy()
+    zo = ref.vcycle(r)
+    e_max, e_2 = relmax(z, zo), float(np.linalg.norm(z - zo) / np.linalg.norm(zo))
+    print(f"mixed RAS order-7 cycle: max-norm {e_max:.2e}, 2-norm {e_2:.2e}", flush=True)
+    assert e_max <= 1e-2 and e_2 <= 1e-2
+
+
 def test_schwarz_mixed_precision_true_residual():
     V = wl.deformed_box(4, 0.05)
     from oracle.sem import SemBox

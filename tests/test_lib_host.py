@@ -188,3 +188,20 @@ def test_geometry_option_validation():
         SemSolver(V, N=4, coarse_storage="mixed", device=-1, lambda_max=[1.0, 1.0])
     assert ex.value.status == L.SEM_EINVAL
     SemSolver(V, N=4, precision="mixed", coarse_storage="mixed", device=-1, lambda_max=[1.0, 1.0])
+
+
+def test_batched_setup_rejects_orders_beyond_the_coefficient_table():
+    """The batched descriptors hold 16 Chebyshev steps per smoothing: longer smoothings
+    are refused at setup (before any device work), for the pre- and the post-smoother."""
+    lib = L.load()
+    V = np.ascontiguousarray(wl.deformed_box(2, 0.05))
+    meshes = (L.SemBoxMesh * 1)(L.SemBoxMesh(2, 2, 2, V.ctypes.data_as(C.POINTER(C.c_double))))
+    orders = (C.c_int32 * 1)(5)
+    for pre, post in ((20, 0), (17, 0), (4, 17)):
+        opt = L.make_options(5, "cheb4", pre, post, "mixed", "fcg", device=-1)
+        ctx = C.c_void_p()
+        assert lib.sem_setup_batched(1, meshes, orders, C.byref(opt), None, C.byref(ctx)) == L.SEM_EINVAL
+        assert b"16" in lib.sem_global_error()
+    opt = L.make_options(5, "cheb4", 16, 0, "mixed", "fcg", device=-1)
+    ctx = C.c_void_p()
+    assert lib.sem_setup_batched(1, meshes, orders, C.byref(opt), None, C.byref(ctx)) == L.SEM_ENODEV

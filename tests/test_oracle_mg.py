@@ -167,3 +167,74 @@ def test_lanczos_matches_dense_eigensolver():
     dense = lambda_max_dense(A, Sinv)
     lz = lambda_max_SA(box.apply, Sinv, box.n, dense_limit=0)
     assert abs(lz - dense) < 1e-10 * dense
+
+
+# ---- geometric multigrid on the order-1 vertex lattice below the p-levels
+def test_lattice_interpolation_is_the_trilinear_hat():
+    """P e_c (one coarse vertex) is the coarse trilinear hat sampled on the fine lattice:
+    the product over x, y, z of max(0, 1 - |fine index - 2 * coarse index| / 2)."""
+    m = (8, 6, 4)
+    Px, Py, Pz = (mg.trilinear_1d(v) for v in m)
+    import scipy.sparse as sp
+    P = sp.kron(Pz, sp.kron(Py, Px)).tocsr()
+    nf = [v - 1 for v in m]
+    nc = [v // 2 - 1 for v in m]
+    assert P.shape == (np.prod(nf), np.prod(nc))
+    for (ci, cj, ck) in [(1, 1, 1), (3, 2, 1), (2, 1, 1)]:
+        e = np.zeros(np.prod(nc))
+        e[(ci - 1) + nc[0] * ((cj - 1) + nc[1] * (ck - 1))] = 1.0
+        I, J, K = np.meshgrid(np.arange(1, nf[0] + 1), np.arange(1, nf[1] + 1), np.arange(1, nf[2] + 1),
+                              indexing="ij")
+        hat = (np.maximum(0, 1 - np.abs(I - 2 * ci) / 2) * np.maximum(0, 1 - np.abs(J - 2 * cj) / 2)
+               * np.maximum(0, 1 - np.abs(K - 2 * ck) / 2))
+        expect = hat.transpose(2, 1, 0).ravel()   # x fastest
+        assert np.max(np.abs(P @ e - expect)) == 0.0
+
+
+def test_lattice_galerkin_operator_closed_form_on_undeformed_box():
+    """On an undeformed box the order-1 GLL operator is sum over axes of K (x) M (x) M with
+    the 1D stiffness K = tridiag(-1, 2, -1)/h and the lumped mass M = h I. Linear
+    interpolation keeps the stiffness (P^T K_h P = K_H, H = 2h) and turns the lumped mass
+    into H tridiag(1/8, 3/4, 1/8), so the Galerkin lattice operator is that Kronecker sum."""
+    import scipy.sparse as sp
+    m = (8, 4, 6)
+    V = wl.box_vertices(*m)
+    h = mg.sem_hierarchy(V, 3, cheb.CHEB4, 2, 2, lmax=[2.0, 2.0, 2.0], coarse="hmg", dense_max=8)
+    As = h.extra["lattice_As"]
+    assert len(As) == 2 and As[1].shape[0] == 3 * 1 * 2
+
+    def K(nint, H):
+        k = nint - 1
+        return sp.diags([-np.ones(k - 1), 2 * np.ones(k), -np.ones(k - 1)], [-1, 0, 1]) / H
+
+    def Mg(nint, H):
+        k = nint - 1
+        return H * sp.diags([np.full(k - 1, 1 / 8), np.full(k, 3 / 4), np.full(k - 1, 1 / 8)], [-1, 0, 1])
+
+    mc = [v // 2 for v in m]
+    Hs = [2.0 / v for v in m]   # coarse spacing 2h with h = 1/m
+    Kx, Ky, Kz = (K(n, H) for n, H in zip(mc, Hs))
+    Mx, My, Mz = (Mg(n, H) for n, H in zip(mc, Hs))
+    expect = sp.kron(Mz, sp.kron(My, Kx)) + sp.kron(Mz, sp.kron(Ky, Mx)) + sp.kron(Kz, sp.kron(My, Mx))
+    assert abs(As[1] - expect).max() < 1e-13 * abs(expect).max()
+
+
+def test_lattice_multigrid_cycle_is_symmetric_and_reduces_to_exact():
+    """With symmetric smoothing the whole cycle (p-levels, then the lattice levels, exact
+    solve on the last) is a symmetric positive definite operator; with dense_max above
+    the order-1 size it is the cycle with the exact order-1 solve."""
+    V = wl.deformed_box(4, 0.05)
+    h = mg.sem_hierarchy(V, 3, cheb.CHEB4, 2, 2, coarse="hmg", dense_max=8)
+    assert [lev.n for lev in h.levels] == [11 ** 3, 3 ** 3, 1]
+    r1, r2 = wl.uniform_noise(h.levels[0].n, 1), wl.uniform_noise(h.levels[0].n, 2)
+    a, b = r2 @ h.vcycle(r1), r1 @ h.vcycle(r2)
+    assert abs(a - b) <= 1e-12 * abs(a)
+    assert r1 @ h.vcycle(r1) > 0
+    lm = [lev.lmax for lev in h.levels[:2]]
+    he = mg.sem_hierarchy(V, 3, cheb.CHEB4, 2, 2, lmax=lm[:1])
+    hx = mg.sem_hierarchy(V, 3, cheb.CHEB4, 2, 2, lmax=lm[:1], coarse="hmg", dense_max=27)
+    assert np.array_equal(he.vcycle(r1), hx.vcycle(r1))
+    # an inexact lattice cycle still gives a convergent preconditioned solve
+    box = h.extra["boxes"][0]
+    res = krylov.pcg(box.apply, r1, h.vcycle, 1e-10, 60, flexible=True)
+    assert res.converged
