@@ -164,6 +164,17 @@ sem_status sem_level_info(const sem_ctx *ctx, int32_t level, int32_t *order, int
 /* w = A u on the finest level (FP64). u, w: device, n_global doubles. */
 sem_status sem_apply_A(sem_ctx *ctx, const double *u, double *w, void *stream);
 
+/* w = A u exactly as sem_apply_A (same kernels, bitwise the same result), for callers
+ * that cannot allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc. The element-local products live in a file-scope device array of the
+ * library (2^22 doubles, 32 MiB, one per GPU, held until the process ends) instead of
+ * context memory; the call makes no allocation, no synchronisation and no host copy.
+ * SEM contexts only. Returns SEM_EINVAL when the finest level has more than 2^22
+ * element-local nodes (E (N+1)^3). All calls on one GPU share the array: calls that
+ * overlap in time on one GPU (two streams, two threads) race and give wrong results.
+ * u, w: device, n_global doubles. */
+sem_status sem_apply_A_noalloc(sem_ctx *ctx, const double *u, double *w, void *stream);
+
 /* Element-local operator on the finest level: wL = A_L Q R^T u, i.e. the
  * per-element sum_ab D_a^T (G_ab o D_b u_e) before direct-stiffness summation
  * (Sec. 1, a_ij; the tensor-product form of the SEM operator).

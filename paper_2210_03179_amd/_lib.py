@@ -25,7 +25,7 @@ MAX_LEVELS = 8
 # exported entry points, as declared in include/semcheb.h
 EXPORTS = (
     "sem_options_default", "sem_setup_box", "sem_setup_fd2d", "sem_sizes", "sem_level_info",
-    "sem_apply_A", "sem_apply_local", "sem_vcycle", "sem_solve", "sem_coords", "sem_mass_apply", "sem_get_factors",
+    "sem_apply_A", "sem_apply_A_noalloc", "sem_apply_local", "sem_vcycle", "sem_solve", "sem_coords", "sem_mass_apply", "sem_get_factors",
     "sem_set_factors", "sem_adjoint_contract", "sem_apply_counts", "sem_reset_counts",
     "sem_host_array", "sem_set_smoothing", "sem_beta_table", "sem_destroy", "sem_last_error", "sem_global_error",
     "sem_setup_batched", "sem_batch_info", "sem_solve_batched",
@@ -79,6 +79,7 @@ def load() -> C.CDLL:
         "sem_sizes": (i32, [vp, P(i64), P(i32), P(i64)]),
         "sem_level_info": (i32, [vp, i32, P(i32), P(i64), P(dbl)]),
         "sem_apply_A": (i32, [vp, vp, vp, vp]),
+        "sem_apply_A_noalloc": (i32, [vp, vp, vp, vp]),
         "sem_apply_local": (i32, [vp, i32, vp, vp, vp]),
         "sem_vcycle": (i32, [vp, vp, vp, vp]),
         "sem_solve": (i32, [vp, vp, vp, dbl, i32, P(i32), P(dbl), P(dbl), vp]),

@@ -9,6 +9,7 @@
 #include <complex>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -18,9 +19,38 @@
 
 using namespace semcheb;
 
+// Scratch of sem_apply_A_noalloc: the element-local products of the operator, in a
+// file-scope device array instead of context memory, so that the call allocates nothing.
+// Every GPU the library runs on holds its own copy (32 MiB) until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns for the device.
+constexpr int64_t kNoAllocScratchDoubles = int64_t(1) << 22;
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
 namespace {
 
 thread_local std::string g_err;
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device `dev`, looked up once per device (at
+// the setup of the first context on it). nullptr with *e set when the lookup fails.
+double *scratch_address(int dev, hipError_t *e) {
+  *e = hipSuccess;
+  if (dev < 0 || dev >= kMaxScratchDevices) {
+    *e = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    *e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (*e != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = (double *)p;
+  }
+  return g_scratch_ptr[dev];
+}
 
 #define HIPCHK(ctx, call)                                                              \
   do {                                                                                 \
@@ -930,6 +960,13 @@ sem_status init_device(sem_ctx *c, hipStream_t s) {
     return SEM_ENODEV;
   }
   HIPCHK(c, hipSetDevice(c->device));
+  {
+    hipError_t e = hipSuccess;
+    if (!scratch_address(c->device, &e)) {
+      c->err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+      return SEM_EHIP;
+    }
+  }
   // SEMCHEB_GRAPHS=0 launches every V-cycle kernel directly instead of replaying graphs
   const char *env = std::getenv("SEMCHEB_GRAPHS");
   c->use_graphs = !(env && env[0] == '0');
@@ -1347,6 +1384,30 @@ sem_status sem_apply_A(sem_ctx *c, const double *u, double *w, void *stream) {
   TRY(need_device(c));
   if (!u || !w) { c->err = "null vector"; return SEM_EINVAL; }
   fine_apply(c, u, w, nullptr, (hipStream_t)stream);
+  HIPCHK(c, hipGetLastError());
+  return SEM_OK;
+}
+
+sem_status sem_apply_A_noalloc(sem_ctx *c, const double *u, double *w, void *stream) {
+  TRY(need_device(c));
+  if (!u || !w) { c->err = "null vector"; return SEM_EINVAL; }
+  if (c->kind != LVL_SEM) { c->err = "sem_apply_A_noalloc needs a SEM context"; return SEM_EINVAL; }
+  Level &L0 = c->levels[0];
+  if (L0.L > kNoAllocScratchDoubles) {
+    c->err = "sem_apply_A_noalloc: the finest level has " + std::to_string(L0.L) +
+             " element-local nodes, above the scratch maximum of " + std::to_string(kNoAllocScratchDoubles);
+    return SEM_EINVAL;
+  }
+  hipError_t e = hipSuccess;
+  double *buf = scratch_address(c->device, &e);  // looked up at setup: no runtime call here
+  if (!buf) {
+    c->err = std::string("no scratch address for this device: ") + hipGetErrorString(e);
+    return SEM_EHIP;
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  L0.applies++;
+  launch_ax(L0, u, buf, s);          // every element-local entry is written: nothing to clear
+  launch_dss<double>(L0, buf, w, s);
   HIPCHK(c, hipGetLastError());
   return SEM_OK;
 }
