@@ -96,6 +96,18 @@ enum { SEM_PCG = 0, SEM_FCG = 1, SEM_GMRES = 2, SEM_MG = 3 };
  * device (sem_get_factors / sem_set_factors return SEM_EINVAL) and exists for single
  * SEM contexts only. */
 enum { SEM_GEOM_STORED = 0, SEM_GEOM_TRILINEAR = 1 };
+/* Treatment of the order-1 level of a SEM hierarchy. SEM_COARSE_EXACT solves it exactly
+ * (M_l^{-1} = A_l^{-1}, Sec. 2): one dense inverse up to 4096 unknowns, a two-ended block
+ * elimination over z-planes above. SEM_COARSE_LATTICE follows the paper's own practice of
+ * one multigrid V-cycle for the order-1 system (Sec. 4.1, one algebraic V-cycle in its
+ * runs): the cycle continues below order 1 on the box's vertex lattice, halving the
+ * element count per direction with trilinear interpolation and Galerkin operators P^T A P
+ * (eq. galerkin-coarse-grid), smoothed by the context's Chebyshev-Jacobi kind and orders,
+ * down to a level of at most coarse_dense_max unknowns that is solved exactly. The lattice
+ * levels always run in FP64, also inside a mixed-precision cycle. When the order-1 level
+ * already has at most coarse_dense_max unknowns, or a direction cannot be halved, the two
+ * are the same. Needs Jacobi smoothing and SEM_FP64 coarse storage. */
+enum { SEM_COARSE_EXACT = 0, SEM_COARSE_LATTICE = 1 };
 
 #define SEM_MAX_LEVELS 8
 
@@ -119,6 +131,8 @@ typedef struct {
   int32_t coarse_storage;           /* coarse factor blocks read by a SEM_MIXED cycle: SEM_FP64
                                        (default) or SEM_MIXED (FP32 copies; FP64 vectors, products
                                        and sums); FP64 contexts accept SEM_FP64 only */
+  int32_t coarse_solver;            /* SEM_COARSE_EXACT (default) or SEM_COARSE_LATTICE */
+  int32_t coarse_dense_max;         /* lattice multigrid: largest level solved densely, 0 = 4096 */
 } sem_options;
 
 /* Structured hexahedral box mesh: (nex+1)(ney+1)(nez+1) vertices, x fastest.
@@ -131,7 +145,8 @@ typedef struct {
 
 /* Fills *opt with: N = 7, default schedule, SEM_CHEB4_OPT, (4,0), FP64,
  * SEM_FCG, estimated lambda_max, lambda_scale 1, device 0, GMRES restart 30,
- * Jacobi smoothing, stored geometric factors, FP64 coarse factors. */
+ * Jacobi smoothing, stored geometric factors, FP64 coarse factors, exact order-1
+ * solve. */
 void sem_options_default(sem_options *opt);
 
 /* Set up the SEM hierarchy on a box mesh: GLL data, geometric factors, Jacobi

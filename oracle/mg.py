@@ -138,7 +138,7 @@ def sem_hierarchy(verts, N: int, kind: str, pre: int, post: int, orders=None,
     Sec. 4.1 (eq. asm) inside the same Chebyshev algorithms; their lambda_max is
     estimated densely (small problems only) unless given.
     coarse: "exact" solves the order-1 level exactly (M_l^{-1} = A_l^{-1}, Sec. 2);
-    "hmg" continues the V-cycle below order 1 on the Q1 vertex lattice
+    "lattice" continues the V-cycle below order 1 on the Q1 vertex lattice
     (q1_lattice_levels) with the same Jacobi-Chebyshev smoothing, and solves only the
     last lattice level (at most dense_max unknowns) exactly. It equals "exact" when the
     order-1 level already has at most dense_max unknowns.
@@ -146,7 +146,7 @@ def sem_hierarchy(verts, N: int, kind: str, pre: int, post: int, orders=None,
     from .schwarz import SchwarzLevel
     orders = default_orders(N) if orders is None else list(orders)
     boxes = [SemBox(verts, o) for o in orders]
-    hAs, hPs = q1_lattice_levels(boxes[-1], dense_max) if coarse == "hmg" else ([None], [])
+    hAs, hPs = q1_lattice_levels(boxes[-1], dense_max) if coarse == "lattice" else ([None], [])
     nh = len(hPs)  # smoothed lattice levels (the order-1 level among them when nh > 0)
     nsm = len(boxes) - 1 + nh
     levels = []

@@ -20,6 +20,7 @@ PRECISIONS = {"fp64": 0, "mixed": 1}
 KRYLOV = {"pcg": 0, "fcg": 1, "gmres": 2, "mg": 3}
 SCHWARZ = {None: 0, "jacobi": 0, "asm": 1, "ras": 2}
 GEOMETRY = {"stored": 0, "trilinear": 1}
+COARSE = {"exact": 0, "lattice": 1}
 MAX_LEVELS = 8
 
 # exported entry points, as declared in include/semcheb.h
@@ -39,7 +40,8 @@ class SemOptions(C.Structure):
         ("precision", C.c_int32), ("krylov", C.c_int32), ("num_lambda_max", C.c_int32),
         ("lambda_max", C.c_double * MAX_LEVELS), ("lambda_scale", C.c_double), ("device", C.c_int32),
         ("coarse_planes", C.c_int32), ("gmres_restart", C.c_int32), ("schwarz", C.c_int32),
-        ("geometry", C.c_int32), ("coarse_storage", C.c_int32),
+        ("geometry", C.c_int32), ("coarse_storage", C.c_int32), ("coarse_solver", C.c_int32),
+        ("coarse_dense_max", C.c_int32),
     ]
 
 
@@ -119,7 +121,8 @@ def check(status: int, ctx=None) -> int:
 
 def make_options(N=7, smoother="cheb4opt", pre=4, post=0, precision="fp64", krylov="fcg",
                  orders=None, lambda_max=None, lambda_scale=1.0, device=0, coarse_planes=0,
-                 restart=30, schwarz=None, geometry="stored", coarse_storage="fp64") -> SemOptions:
+                 restart=30, schwarz=None, geometry="stored", coarse_storage="fp64", coarse="exact",
+                 dense_max=0) -> SemOptions:
     lib = load()
     o = SemOptions()
     lib.sem_options_default(C.byref(o))
@@ -143,4 +146,6 @@ def make_options(N=7, smoother="cheb4opt", pre=4, post=0, precision="fp64", kryl
     o.schwarz = SCHWARZ[schwarz] if (schwarz is None or isinstance(schwarz, str)) else int(schwarz)
     o.geometry = GEOMETRY[geometry] if isinstance(geometry, str) else int(geometry)
     o.coarse_storage = PRECISIONS[coarse_storage] if isinstance(coarse_storage, str) else int(coarse_storage)
+    o.coarse_solver = COARSE[coarse] if isinstance(coarse, str) else int(coarse)
+    o.coarse_dense_max = int(dense_max)
     return o

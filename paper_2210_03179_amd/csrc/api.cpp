@@ -159,6 +159,18 @@ sem_status validate_common(const sem_options *o, std::string &err) {
     err = "gmres_restart must lie in 0..32 (0 = 30)";
     return SEM_EINVAL;
   }
+  if (o->coarse_solver != SEM_COARSE_EXACT && o->coarse_solver != SEM_COARSE_LATTICE) {
+    err = "unknown coarse_solver";
+    return SEM_EINVAL;
+  }
+  if (o->coarse_dense_max < 0 || o->coarse_dense_max > 8192) {
+    err = "coarse_dense_max must lie in 0..8192 (0 = 4096)";
+    return SEM_EINVAL;
+  }
+  if (o->coarse_solver == SEM_COARSE_LATTICE && (o->schwarz != SEM_JACOBI || o->coarse_storage != SEM_FP64)) {
+    err = "lattice multigrid needs Jacobi smoothing and FP64 coarse storage";
+    return SEM_EINVAL;
+  }
   if (o->num_lambda_max < 0 || o->num_lambda_max > SEM_MAX_LEVELS) { err = "bad num_lambda_max"; return SEM_EINVAL; }
   if (o->lambda_scale < 0) { err = "lambda_scale must be >= 0"; return SEM_EINVAL; }
   return SEM_OK;
@@ -429,9 +441,13 @@ void vcycle(sem_ctx *c, int j, hipStream_t s) {
   }
   const T *ad = pre > 0 ? w : (const T *)nullptr;  // A x (element-local on SEM levels)
   Level &C = c->levels[j + 1];
-  // single-precision cycle above the order-1 coarse level: FP64 coarse vectors used directly
-  const bool wide = sizeof(T) == sizeof(float) && j + 2 == (int)c->levels.size() && c->coarse.n > 0 &&
-                    coarse_wide(c);
+  // single-precision cycle above the order-1 level: FP64 vectors used directly, those of the
+  // exact coarse solver, or those of the order-1 level that starts the FP64 lattice cycle
+  const bool to_lattice = sizeof(T) == sizeof(float) && c->lattice_from >= 0 && j + 1 == c->lattice_from;
+  const bool wide = sizeof(T) == sizeof(float) &&
+                    ((j + 2 == (int)c->levels.size() && c->coarse.n > 0 && coarse_wide(c)) || to_lattice);
+  double *wide_b = to_lattice ? C.b64 : c->coarse.b;
+  double *wide_x = to_lattice ? C.x64 : c->coarse.x;
   if (L.type == LVL_SEM) {
     // the weighted residual is formed inside the restriction where a row-blocked kernel
     // exists for the order pair (the residual vector is then neither written nor read), in
@@ -444,13 +460,14 @@ void vcycle(sem_ctx *c, int j, hipStream_t s) {
       launch_resid_weight<T>(L, ad, b, r, s);
       launch_restrict<T>(L, C, r, V<T>::J(L), V<T>::w(C), s);
     }
-    if (wide) launch_dss_wide(C, C.w32, c->coarse.b, s);
+    if (wide) launch_dss_wide(C, C.w32, wide_b, s);
     else launch_dss<T>(C, V<T>::w(C), V<T>::b(C), s);
   } else {
     launch_resid_weight<T>(L, ad, b, r, s);
     launch_csr<T>(L.R, V<T>::val(L.R), r, (const T *)nullptr, V<T>::b(C), 0, s);
   }
-  vcycle<T>(c, j + 1, s);
+  if (to_lattice) vcycle<double>(c, j + 1, s);
+  else vcycle<T>(c, j + 1, s);
   // a one-sided cycle ends with this prolongation on the finest level. In mixed
   // precision it writes the widened result z directly (c->zout) instead of updating x.
   // Its result is then the cycle's z (FP64: x is z), and the Krylov dot products of z
@@ -461,7 +478,7 @@ void vcycle(sem_ctx *c, int j, hipStream_t s) {
   if (L.type == LVL_SEM) {
     const int nb = launch_prolong<T>(L, C, V<T>::x(C), V<T>::J(L), x, zout, s, zdots ? c->zdot_r1 : nullptr,
                                      zdots ? c->zdot_r2 : nullptr, c->partials, c->partials_cap,
-                                     wide ? c->coarse.x : nullptr);
+                                     wide ? wide_x : nullptr);
     if (zdots) c->zdot_blocks = nb;
   } else launch_csr<T>(L.P, V<T>::val(L.P), V<T>::x(C), (const T *)nullptr, x, 2, s);
   if (post > 0) smooth<T>(c, L, post, false, s);
@@ -723,6 +740,7 @@ sem_status autotune_operator(sem_ctx *c, hipStream_t s) {
   sem_status st = SEM_OK;
   for (size_t j = 0; j + 1 < c->levels.size() && st == SEM_OK; ++j) {
     Level &L = c->levels[j];
+    if (L.type != LVL_SEM) continue;  // CSR levels of lattice multigrid
     for (int prec = 0; prec < 2; ++prec) {
       const bool fp64 = prec == 0;
       if (!fp64 && !(mixed && (L.Gbf || L.tri32) && L.w32)) continue;
@@ -974,6 +992,8 @@ sem_status init_device(sem_ctx *c, hipStream_t s) {
   return SEM_OK;
 }
 
+Csr transpose(const Csr &A);
+
 sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipStream_t s, sem_ctx *c) {
   c->kind = LVL_SEM;
   c->opt = *opt;
@@ -1015,29 +1035,48 @@ sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipS
   for (int j = 0; j < nl; ++j) TRY(build_box_level(*mesh, orders[j], c->host_levels[j], c->err));
   c->host_interp.resize(nl);
   for (int j = 0; j + 1 < nl; ++j) c->host_interp[j] = make_interp(c->host_levels[j].gll, c->host_levels[j + 1].gll);
-  // coarse operator: assembled order-1 matrix, block tridiagonal in z-planes
+  // coarse operator: assembled order-1 matrix, block tridiagonal in z-planes; with lattice
+  // multigrid, the last (smallest) level of the vertex-lattice hierarchy below it, dense
   const BoxLevelHost &H = c->host_levels.back();
-  Csr Ac = assemble_q1(H);
-  const int64_t plane = (int64_t)H.nx * H.ny;
-  int gp = opt->coarse_planes;
-  if (gp <= 0) gp = (H.n <= 4096) ? H.nz : 1;
-  gp = std::min(gp, H.nz);
+  Csr Aq1 = assemble_q1(H);
+  std::vector<LatticeLevelHost> lat;
+  if (opt->coarse_solver == SEM_COARSE_LATTICE && nl >= 2)  // a one-level hierarchy stays exact
+    build_lattice_hierarchy(Aq1, H.nex, H.ney, H.nez, opt->coarse_dense_max > 0 ? opt->coarse_dense_max : 4096,
+                            lat);
+  const bool lattice = lat.size() > 1;
+  const int nlat = lattice ? (int)lat.size() - 1 : 0;  // levels below order 1
+  if (lattice && opt->precision == SEM_MIXED && nl >= 2 && !prolong_rows_available(orders[nl - 2], 1)) {
+    c->err = "lattice multigrid in a mixed cycle needs the row-blocked transfer " + std::to_string(orders[nl - 2]) +
+             " -> 1";
+    return SEM_EINVAL;
+  }
+  const Csr &Ac = lattice ? lat.back().A : Aq1;
+  const int64_t ncoarse = Ac.nrows;
   std::vector<int64_t> start;
-  for (int k = 0; k < H.nz; k += gp) start.push_back((int64_t)k * plane);
-  start.push_back(H.n);
+  if (lattice) {
+    start = {0, ncoarse};
+  } else {
+    const int64_t plane = (int64_t)H.nx * H.ny;
+    int gp = opt->coarse_planes;
+    if (gp <= 0) gp = (H.n <= 4096) ? H.nz : 1;
+    gp = std::min(gp, H.nz);
+    for (int k = 0; k < H.nz; k += gp) start.push_back((int64_t)k * plane);
+    start.push_back(H.n);
+  }
   BlockTri bt;
   if (!block_tridiag_factor(Ac, start, bt, c->err)) return SEM_EINVAL;
-  if (H.n <= 4096) {
-    c->coarse.host_dense.assign((size_t)H.n * H.n, 0.0);
-    for (int64_t r = 0; r < H.n; ++r)
-      for (int64_t p = Ac.rowptr[r]; p < Ac.rowptr[r + 1]; ++p) c->coarse.host_dense[r * H.n + Ac.col[p]] = Ac.val[p];
+  if (ncoarse <= 4096) {
+    c->coarse.host_dense.assign((size_t)ncoarse * ncoarse, 0.0);
+    for (int64_t r = 0; r < ncoarse; ++r)
+      for (int64_t p = Ac.rowptr[r]; p < Ac.rowptr[r + 1]; ++p)
+        c->coarse.host_dense[r * ncoarse + Ac.col[p]] = Ac.val[p];
   }
-  c->coarse.n = H.n;
+  c->coarse.n = ncoarse;
   c->coarse.dense = (start.size() == 2);
   c->coarse.start = start;
 
   // levels
-  c->levels.resize(nl);
+  c->levels.resize(nl + nlat);
   for (int j = 0; j < nl; ++j) {
     const BoxLevelHost &h = c->host_levels[j];
     Level &L = c->levels[j];
@@ -1047,6 +1086,18 @@ sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipS
     L.nex = h.nex; L.ney = h.ney; L.nez = h.nez;
     L.nx = h.nx; L.ny = h.ny; L.nz = h.nz;
     L.E = h.E; L.L = h.L; L.n = h.n;
+  }
+  if (lattice) {
+    // the order-1 level keeps its box (the p-transfer to it is the SEM one) but is smoothed
+    // with its assembled CSR operator, like the lattice levels below it
+    c->lattice_from = nl - 1;
+    c->levels[nl - 1].type = LVL_FD;
+    for (int q = 1; q <= nlat; ++q) {
+      Level &L = c->levels[nl - 1 + q];
+      L.type = LVL_FD;
+      L.N = 1;
+      L.n = lat[q].A.nrows;
+    }
   }
   if (c->host_only) {
     if (opt->num_lambda_max > 0) TRY(estimate_lambdas(c, s));
@@ -1110,7 +1161,7 @@ sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipS
         TRY(dalloc(c, &L.w64, L.L));
       }
     }
-    TRY(alloc_level_vectors(c, L, mixed, coarse));
+    if (!(lattice && coarse)) TRY(alloc_level_vectors(c, L, mixed, coarse));
     if (mixed && j > 0 && !coarse) {
       // FP64 work vectors for Lanczos on coarser levels
       TRY(dalloc(c, &L.w64, L.L));
@@ -1134,6 +1185,37 @@ sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipS
       }
     }
     HIPCHK(c, hipStreamSynchronize(s));
+  }
+  if (lattice) {
+    // CSR operators, diagonals and transfers of the order-1 level and the lattice levels;
+    // FP64 vectors always (also in a mixed context, whose cycle hands these levels FP64 data)
+    for (int q = 0; q <= nlat; ++q) {
+      Level &L = c->levels[nl - 1 + q];
+      const LatticeLevelHost &h = lat[q];
+      TRY(upload_csr(c, L.A, h.A, false, s));
+      std::vector<double> inv(h.A.nrows);
+      for (int64_t r = 0; r < h.A.nrows; ++r)
+        for (int64_t p = h.A.rowptr[r]; p < h.A.rowptr[r + 1]; ++p)
+          if (h.A.col[p] == r) inv[r] = 1.0 / h.A.val[p];
+      // (the order-1 level's diagonal is taken from its CSR matrix like the others)
+      TRY(upload(c, &L.invdiag64, inv.data(), inv.size(), s));
+      const bool last = q == nlat;
+      if (!last) {
+        TRY(upload_csr(c, L.P, h.P, false, s));
+        Csr R = transpose(h.P);
+        TRY(upload_csr(c, L.R, R, false, s));
+      }
+      TRY(dalloc(c, &L.b64, L.n));
+      TRY(dalloc(c, &L.x64, L.n));
+      if (!last) {
+        TRY(dalloc(c, &L.r64, L.n));
+        TRY(dalloc(c, &L.d64, L.n));
+      }
+      // the order-1 level also receives the element-local restriction from the level above
+      TRY(dalloc(c, &L.w64, q == 0 ? std::max(L.L, L.n) : L.n));
+      if (q == 0 && mixed) TRY(dalloc(c, &L.w32, L.L));
+      HIPCHK(c, hipStreamSynchronize(s));
+    }
   }
   // coarse factors
   CoarseSolver &C = c->coarse;
@@ -1333,6 +1415,8 @@ void sem_options_default(sem_options *o) {
   o->schwarz = SEM_JACOBI;
   o->geometry = SEM_GEOM_STORED;
   o->coarse_storage = SEM_FP64;
+  o->coarse_solver = SEM_COARSE_EXACT;
+  o->coarse_dense_max = 0;
 }
 
 sem_status sem_setup_box(const sem_box_mesh *mesh, const sem_options *opt, void *stream, sem_ctx **out) {

@@ -653,6 +653,50 @@ static Csr csr_matmul(const Csr &A, const Csr &B) {
   return csr_from_map(A.nrows, B.ncols, rows);
 }
 
+// Geometric multigrid on the order-1 vertex lattice of an nex x ney x nez box: trilinear
+// interpolation from the lattice of half as many elements per direction (coarse vertex I
+// sits at fine vertex 2I; an odd fine vertex is the mean of its two coarse neighbours, a
+// boundary neighbour being a Dirichlet zero) and Galerkin operators P^T A P, while the
+// level has more than dense_max unknowns and every direction halves to >= 2 elements.
+void build_lattice_hierarchy(const Csr &A0, int nex, int ney, int nez, int64_t dense_max,
+                             std::vector<LatticeLevelHost> &out) {
+  out.clear();
+  LatticeLevelHost f;
+  f.mx = nex;
+  f.my = ney;
+  f.mz = nez;
+  f.A = A0;
+  out.push_back(f);
+  for (;;) {
+    LatticeLevelHost &F = out.back();
+    if (F.A.nrows <= dense_max) break;
+    if (F.mx % 2 || F.my % 2 || F.mz % 2 || F.mx < 4 || F.my < 4 || F.mz < 4) break;
+    const int fx = F.mx - 1, fy = F.my - 1, fz = F.mz - 1;
+    const int cx = F.mx / 2 - 1, cy = F.my / 2 - 1, cz = F.mz / 2 - 1;
+    std::vector<std::map<int32_t, double>> rows((int64_t)fx * fy * fz);
+    // 1D weights of coarse vertex C at fine vertex i: 1 at i = 2C, 1/2 at i = 2C +- 1
+    auto w1 = [](int i, int C) { const int d = std::abs(i - 2 * C); return d == 0 ? 1.0 : (d == 1 ? 0.5 : 0.0); };
+    for (int K = 1; K <= cz; ++K)
+      for (int J = 1; J <= cy; ++J)
+        for (int I = 1; I <= cx; ++I) {
+          const int32_t col = (I - 1) + cx * ((J - 1) + cy * (K - 1));
+          for (int k = 2 * K - 1; k <= 2 * K + 1; ++k)
+            for (int j = 2 * J - 1; j <= 2 * J + 1; ++j)
+              for (int i = 2 * I - 1; i <= 2 * I + 1; ++i)
+                rows[(i - 1) + (int64_t)fx * ((j - 1) + (int64_t)fy * (k - 1))][col] +=
+                    w1(i, I) * w1(j, J) * w1(k, K);
+        }
+    F.P = csr_from_map((int64_t)fx * fy * fz, (int64_t)cx * cy * cz, rows);
+    LatticeLevelHost C;
+    C.mx = F.mx / 2;
+    C.my = F.my / 2;
+    C.mz = F.mz / 2;
+    const Csr PT = csr_transpose(F.P);
+    C.A = csr_matmul(PT, csr_matmul(F.A, F.P));
+    out.push_back(C);
+  }
+}
+
 void build_fd_hierarchy(int n, double Lx, double Ly, int factor, int coarsest_n,
                         std::vector<FdLevelHost> &out) {
   out.clear();

@@ -80,6 +80,17 @@ struct FdLevelHost {
 void build_fd_hierarchy(int n, double Lx, double Ly, int factor, int coarsest_n,
                         std::vector<FdLevelHost> &out);
 
+// Order-1 vertex lattice levels of a box below the p-multigrid levels (lattice multigrid):
+// level q has mx x my x mz elements, operator A (out[0].A = the assembled order-1 SEM
+// operator) and, except on the last level, the trilinear interpolation P from level q+1.
+struct LatticeLevelHost {
+  int mx = 0, my = 0, mz = 0;
+  Csr A;
+  Csr P;
+};
+void build_lattice_hierarchy(const Csr &A0, int nex, int ney, int nez, int64_t dense_max,
+                             std::vector<LatticeLevelHost> &out);
+
 // message returned by sem_global_error()
 void set_global_error(const std::string &msg);
 
@@ -210,6 +221,10 @@ struct sem_ctx {
   std::vector<std::vector<double>> host_interp;
   std::vector<semcheb::FdLevelHost> fd_host;
   semcheb::CoarseSolver coarse;
+  // lattice multigrid (SEM_COARSE_LATTICE): index of the order-1 level when the V-cycle
+  // continues below it on the vertex lattice, -1 otherwise. Levels from this index on are
+  // CSR levels (LVL_FD kernels) and always run in FP64, also inside a mixed cycle.
+  int lattice_from = -1;
   // Krylov work (FP64, finest level)
   double *kr = nullptr, *kr2 = nullptr, *kz = nullptr, *kp = nullptr, *kw = nullptr;
   double *scal = nullptr;      // device scalars

@@ -159,11 +159,14 @@ class SemSolver(_Base):
     geometry: "stored" (factors read from HBM) or "trilinear" (formed in the operator).
     coarse_storage: "fp64" or, with precision="mixed", "mixed" (the cycle reads FP32 copies of the
     coarse factor blocks).
+    coarse: "exact" (exact order-1 solve) or "lattice" (the cycle continues on the vertex lattice
+    with Galerkin levels down to dense_max unknowns, 0 = 4096; FP64 in every precision).
     """
 
     def __init__(self, verts, N=7, smoother="cheb4opt", pre=4, post=0, precision="fp64",
                  krylov="fcg", orders=None, lambda_max=None, lambda_scale=1.0, device=0,
-                 coarse_planes=0, restart=30, schwarz=None, geometry="stored", coarse_storage="fp64"):
+                 coarse_planes=0, restart=30, schwarz=None, geometry="stored", coarse_storage="fp64",
+                 coarse="exact", dense_max=0):
         super().__init__()
         verts = np.ascontiguousarray(np.asarray(verts, dtype=np.float64))
         if verts.ndim != 4 or verts.shape[3] != 3:
@@ -172,7 +175,8 @@ class SemSolver(_Base):
         mesh = L.SemBoxMesh(verts.shape[2] - 1, verts.shape[1] - 1, verts.shape[0] - 1,
                             verts.ctypes.data_as(C.POINTER(C.c_double)))
         opt = L.make_options(N, smoother, pre, post, precision, krylov, orders, lambda_max,
-                             lambda_scale, device, coarse_planes, restart, schwarz, geometry, coarse_storage)
+                             lambda_scale, device, coarse_planes, restart, schwarz, geometry, coarse_storage,
+                             coarse, dense_max)
         ctx = C.c_void_p()
         stream = _stream() if device >= 0 else C.c_void_p(0)
         L.check(self._lib.sem_setup_box(C.byref(mesh), C.byref(opt), stream, C.byref(ctx)))

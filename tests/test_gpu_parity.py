@@ -393,9 +393,9 @@ def test_breakdown_on_indefinite_preconditioner():
     for krylov in ("pcg", "fcg"):
         s = FdSolver(n=16, factor=2, coarsest_n=2, smoother="cheb4", pre=2, post=2, krylov=krylov,
                      lambda_max=bad)
-        u, info = s.solve(dev(b), rtol=1e-8, maxit=50)
-        assert info.status == L.SEM_EBREAKDOWN, info
-        assert "breakdown" in L.load().sem_last_error(s._ctx).decode()
+        with pytest.raises(L.SemError) as ex:   # the binding raises for every status but OK / ENOTCONV
+            s.solve(dev(b), rtol=1e-8, maxit=50)
+        assert ex.value.status == L.SEM_EBREAKDOWN and "breakdown" in str(ex.value)
         s.close()
     # the same hierarchy with the true lambda_max converges
     s = FdSolver(n=16, factor=2, coarsest_n=2, smoother="cheb4", pre=2, post=2, krylov="pcg", lambda_max=true)
@@ -409,8 +409,9 @@ def test_mixed_cycle_elementwise(cfg2):
     - against the FP64 oracle within one BF16 unit roundoff, 2^-9 (the factors' storage
       rounding alone moves this cycle by about 6e-4);
     - against the oracle run with the same BF16-rounded factors (FP64 arithmetic) within
-      1e-4: what is left is the FP32 arithmetic, so a wrong node shows up here far above
-      the rounding level."""
+      1e-5: what is left is the FP32 arithmetic (unit roundoff 6e-8, measured 1.9e-7 over
+      the cycle's operator applications and transfers), so a wrong node shows up here far
+      above the rounding level."""
     V, ref, box, b, lmax = cfg2
     r = wl.uniform_noise(box.n, 5)
     zo = ref.vcycle(r)
@@ -425,4 +426,4 @@ def test_mixed_cycle_elementwise(cfg2):
     print(f"mixed cycle 8^3: vs FP64 oracle max-norm {e64:.2e} (2-norm {e2:.2e}), "
           f"vs BF16-factor oracle {ebf:.2e}; BF16 storage alone {relmax(zb, zo):.2e}", flush=True)
     assert e64 <= 2.0 ** -9
-    assert ebf <= 1e-4
+    assert ebf <= 1e-5

@@ -205,3 +205,29 @@ def test_batched_setup_rejects_orders_beyond_the_coefficient_table():
     opt = L.make_options(5, "cheb4", 16, 0, "mixed", "fcg", device=-1)
     ctx = C.c_void_p()
     assert lib.sem_setup_batched(1, meshes, orders, C.byref(opt), None, C.byref(ctx)) == L.SEM_ENODEV
+
+
+def test_lattice_multigrid_host_hierarchy_matches_oracle():
+    """coarse="lattice": the levels below order 1 (vertex lattice halved per direction) and
+    the Galerkin operator of the last one, built in C++, against the oracle's construction."""
+    from oracle import chebyshev as cheb, mg
+    V = wl.deformed_box((8, 4, 6), 0.05)
+    ref = mg.sem_hierarchy(V, 3, cheb.CHEB4, 2, 2, lmax=[2.0] * 3, coarse="lattice", dense_max=8)
+    s = SemSolver(V, N=3, smoother="cheb4", pre=2, post=2, device=-1, lambda_max=[2.0] * 3,
+                  coarse="lattice", dense_max=8)
+    assert s.num_levels == len(ref.levels) == 3
+    assert [s.level_info(j)[1] for j in range(3)] == [lev.n for lev in ref.levels]
+    assert [s.level_info(j)[0] for j in range(3)] == [3, 1, 1]
+    Ac = ref.extra["lattice_As"][-1].toarray()
+    Ah = s.host_array("coarse_matrix").reshape(Ac.shape)
+    assert np.max(np.abs(Ah - Ac)) < 1e-14 * np.max(np.abs(Ac))
+    # a level that fits dense_max keeps the exact order-1 solve; an odd element count stops
+    # the halving
+    s2 = SemSolver(V, N=3, device=-1, lambda_max=[2.0], coarse="lattice")
+    assert s2.num_levels == 2
+    s3 = SemSolver(wl.deformed_box((8, 5, 6), 0.05), N=3, device=-1, lambda_max=[2.0], coarse="lattice",
+                   dense_max=8)
+    assert s3.num_levels == 2
+    with pytest.raises(L.SemError) as ex:
+        SemSolver(V, N=3, device=-1, lambda_max=[2.0] * 3, coarse="lattice", schwarz="ras")
+    assert ex.value.status == L.SEM_EINVAL

@@ -199,7 +199,7 @@ def test_lattice_galerkin_operator_closed_form_on_undeformed_box():
     import scipy.sparse as sp
     m = (8, 4, 6)
     V = wl.box_vertices(*m)
-    h = mg.sem_hierarchy(V, 3, cheb.CHEB4, 2, 2, lmax=[2.0, 2.0, 2.0], coarse="hmg", dense_max=8)
+    h = mg.sem_hierarchy(V, 3, cheb.CHEB4, 2, 2, lmax=[2.0, 2.0, 2.0], coarse="lattice", dense_max=8)
     As = h.extra["lattice_As"]
     assert len(As) == 2 and As[1].shape[0] == 3 * 1 * 2
 
@@ -224,7 +224,7 @@ def test_lattice_multigrid_cycle_is_symmetric_and_reduces_to_exact():
     solve on the last) is a symmetric positive definite operator; with dense_max above
     the order-1 size it is the cycle with the exact order-1 solve."""
     V = wl.deformed_box(4, 0.05)
-    h = mg.sem_hierarchy(V, 3, cheb.CHEB4, 2, 2, coarse="hmg", dense_max=8)
+    h = mg.sem_hierarchy(V, 3, cheb.CHEB4, 2, 2, coarse="lattice", dense_max=8)
     assert [lev.n for lev in h.levels] == [11 ** 3, 3 ** 3, 1]
     r1, r2 = wl.uniform_noise(h.levels[0].n, 1), wl.uniform_noise(h.levels[0].n, 2)
     a, b = r2 @ h.vcycle(r1), r1 @ h.vcycle(r2)
@@ -232,7 +232,7 @@ def test_lattice_multigrid_cycle_is_symmetric_and_reduces_to_exact():
     assert r1 @ h.vcycle(r1) > 0
     lm = [lev.lmax for lev in h.levels[:2]]
     he = mg.sem_hierarchy(V, 3, cheb.CHEB4, 2, 2, lmax=lm[:1])
-    hx = mg.sem_hierarchy(V, 3, cheb.CHEB4, 2, 2, lmax=lm[:1], coarse="hmg", dense_max=27)
+    hx = mg.sem_hierarchy(V, 3, cheb.CHEB4, 2, 2, lmax=lm[:1], coarse="lattice", dense_max=27)
     assert np.array_equal(he.vcycle(r1), hx.vcycle(r1))
     # an inexact lattice cycle still gives a convergent preconditioned solve
     box = h.extra["boxes"][0]
