@@ -70,7 +70,9 @@ enum {
   SEM_CHEB1 = 1,     /* 1st kind, lambda_min = 0.1 lambda_max ("1st-Cheb") */
   SEM_CHEB1_OPT = 2, /* 1st kind, lambda_min by eq. opt-lambda-min */
   SEM_CHEB4 = 4,     /* 4th kind, beta_i = 1 */
-  SEM_CHEB4_OPT = 5  /* optimised 4th kind, beta from Table beta_coef (order <= 16) */
+  SEM_CHEB4_OPT = 5  /* optimised 4th kind: beta from Table beta_coef (order <= 16), and for
+                        orders 17..32 the beta minimising eq. gamma-defn, computed by the
+                        library (equioscillation of lambda p^2 / (1 - p^2), Newton's method) */
 };
 enum { SEM_FP64 = 0, SEM_MIXED = 1 }; /* precision of the V-cycle */
 /* Basic smoother accelerated by the Chebyshev algorithms (Sec. 4.1): point Jacobi
@@ -102,8 +104,11 @@ enum { SEM_GEOM_STORED = 0, SEM_GEOM_TRILINEAR = 1 };
  * one multigrid V-cycle for the order-1 system (Sec. 4.1, one algebraic V-cycle in its
  * runs): the cycle continues below order 1 on the box's vertex lattice, halving the
  * element count per direction with trilinear interpolation and Galerkin operators P^T A P
- * (eq. galerkin-coarse-grid), smoothed by the context's Chebyshev-Jacobi kind and orders,
- * down to a level of at most coarse_dense_max unknowns that is solved exactly. The lattice
+ * (eq. galerkin-coarse-grid), smoothed by the context's Chebyshev-Jacobi kind,
+ * symmetrically with (m, m), m = max(pre_order, post_order), on every lattice level (the
+ * order-1 level included: a one-sided smoothing there makes the inexact order-1 solve the
+ * weak part of the cycle), down to a level of at most coarse_dense_max unknowns that is
+ * solved exactly. The lattice
  * levels always run in FP64, also inside a mixed-precision cycle. When the order-1 level
  * already has at most coarse_dense_max unknowns, or a direction cannot be halved, the two
  * are the same. Needs Jacobi smoothing and SEM_FP64 coarse storage. */
@@ -143,6 +148,23 @@ typedef struct {
   const double *vertex_xyz; /* host, [(nez+1)][(ney+1)][(nex+1)][3] */
 } sem_box_mesh;
 
+/* Unstructured conforming hexahedral mesh (host memory, read during setup only). Element e
+ * is the trilinear image of the reference cube [-1,1]^3 whose corner ci + 2 cj + 4 ck
+ * (ci, cj, ck in {0,1}) sits at reference point (2ci-1, 2cj-1, 2ck-1) and is vertex
+ * elem_vertices[8e + ci + 2cj + 4ck]. Elements may be numbered and oriented freely; two
+ * elements share a node wherever they share the vertices of a face, an edge or a corner.
+ * Dirichlet conditions hold on the boundary faces (faces of a single element) whose four
+ * corners are all flagged in vertex_dirichlet, on every boundary face when it is NULL;
+ * natural (zero-flux) conditions on the other boundary faces. The global unknowns are
+ * numbered by first appearance when the element-local nodes are visited in the order
+ * (e, k, j, i), i fastest, Dirichlet nodes skipped. */
+typedef struct {
+  int32_t num_elements, num_vertices;
+  const double *vertex_xyz;        /* [num_vertices][3] */
+  const int32_t *elem_vertices;    /* [num_elements][8], lexicographic corner order */
+  const uint8_t *vertex_dirichlet; /* [num_vertices] flags, or NULL: whole boundary Dirichlet */
+} sem_mesh;
+
 /* Fills *opt with: N = 7, default schedule, SEM_CHEB4_OPT, (4,0), FP64,
  * SEM_FCG, estimated lambda_max, lambda_scale 1, device 0, GMRES restart 30,
  * Jacobi smoothing, stored geometric factors, FP64 coarse factors, exact order-1
@@ -158,6 +180,19 @@ void sem_options_default(sem_options *opt);
  * out of range), SEM_EMESH (det J <= 0), SEM_ENOMEM, SEM_EHIP, SEM_ENODEV. */
 sem_status sem_setup_box(const sem_box_mesh *mesh, const sem_options *opt, void *stream,
                          sem_ctx **out);
+
+/* Set up the same hierarchy (orders N, floor(N/2), 1 by default, or opt->orders), smoother,
+ * cycle and Krylov method on an unstructured conforming hexahedral mesh (sem_mesh): Sec. 4.1
+ * notes that p-multigrid coarsens unstructured meshes as robustly as structured ones. The
+ * element operator gathers its input through a local-to-global map and the direct-stiffness
+ * summation runs over per-unknown lists of the element copies, in increasing copy order
+ * (deterministic, no atomics); transfers interpolate per element and average shared nodes.
+ * The order-1 level is solved exactly with a dense inverse: at most 8192 order-1 unknowns.
+ * Jacobi smoothing, stored factors and SEM_COARSE_EXACT only; FP64 and mixed precision.
+ * sem_adjoint_contract's factor gradient and sem_apply_A_noalloc are box-only. Errors as
+ * sem_setup_box, plus SEM_EINVAL for vertex indices out of range, a face shared by more than
+ * two elements, no Dirichlet face, or a larger order-1 level. */
+sem_status sem_setup(const sem_mesh *mesh, const sem_options *opt, void *stream, sem_ctx **out);
 
 /* 2D finite-difference model problem of Sec. 3: [0,Lx]x[0,Ly], n intervals
  * per direction (n-1 interior points, x fastest), 5-point operator, bilinear
@@ -302,7 +337,9 @@ sem_status sem_batch_info(const sem_ctx *ctx, int32_t *nsys, int64_t *offsets);
 sem_status sem_solve_batched(sem_ctx *ctx, const double *b, double *u, double rtol, int32_t maxit,
                              int32_t *iters, double *relres, void *stream);
 
-/* beta_i^{(k)}, i = 1..k, of Table beta_coef into out[0..k-1]; k in 1..16. */
+/* beta_i^{(k)}, i = 1..k, of the optimised 4th-kind smoother into out[0..k-1]: Table
+ * beta_coef as printed for k = 1..16, the minimisers of eq. gamma-defn for k = 17..32.
+ * SEM_EINVAL for other k. */
 sem_status sem_beta_table(int32_t k, double *out);
 
 sem_status sem_destroy(sem_ctx *ctx);

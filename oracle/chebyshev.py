@@ -66,6 +66,92 @@ BETA = {
 }
 
 
+MAX_OPT_ORDER = 32  # optimised 4th kind: the table up to 16, computed beta up to this order
+
+
+def fourth_kind_polynomials(k: int, lam: np.ndarray):
+    """p_i(lam) = W_i(1 - 2 lam) / (2i + 1), i = 0..k, and their first derivatives
+    (eq. fourth-kind-polynomial-iterate with the recurrence of eq. fourth-kind-chebyshev:
+    W_0 = 1, W_1 = 2x + 1, W_n = 2x W_{n-1} - W_{n-2})."""
+    x = 1.0 - 2.0 * np.asarray(lam, dtype=np.float64)
+    W = [np.ones_like(x), 2.0 * x + 1.0]
+    dW = [np.zeros_like(x), np.full_like(x, 2.0)]
+    for n in range(2, k + 1):
+        W.append(2.0 * x * W[n - 1] - W[n - 2])
+        dW.append(2.0 * W[n - 1] + 2.0 * x * dW[n - 1] - dW[n - 2])
+    p = [W[n] / (2 * n + 1) for n in range(k + 1)]
+    dp = [-2.0 * dW[n] / (2 * n + 1) for n in range(k + 1)]   # d/dlam, x = 1 - 2 lam
+    return p, dp
+
+
+def _gamma_terms(beta, lam):
+    """f(lam) = lam p^2 / (1 - p^2) of eq. gamma-defn and df/dlam for the optimised
+    polynomial p = 1 + sum_i beta_i (p_i - p_{i-1}) (the error polynomial of Algorithm 2:
+    its iterate adds beta_i times the plain 4th-kind increments)."""
+    k = len(beta)
+    P, dP = fourth_kind_polynomials(k, lam)
+    p = 1.0 + sum(beta[i - 1] * (P[i] - P[i - 1]) for i in range(1, k + 1))
+    dp = sum(beta[i - 1] * (dP[i] - dP[i - 1]) for i in range(1, k + 1))
+    g = 1.0 - p * p
+    f = lam * p * p / g
+    df = (p * p + 2.0 * lam * p * dp) / g + lam * p * p * (2.0 * p * dp) / (g * g)
+    return f, df
+
+
+def minimax_betas(kmax: int) -> dict:
+    """beta^{(k)}, k = 1..kmax, minimising gamma (eq. gamma-defn) over the coefficients of
+    Algorithm 2 (paper, Sec. 2: the beta_i come from optimising eq. gamma-defn).
+
+    Characterisation used: at the minimum, f(lam) = lam p^2 / (1 - p^2) attains its
+    supremum gamma at k+1 points: lam -> 0 (where f tends to 3 / (8 sum_i i beta_i),
+    since p'(0) = -(4/3) sum_i i beta_i), k-1 interior maxima (f = gamma, f' = 0) and
+    lam = 1. Those 2k equations in (beta, gamma, interior maxima) are solved by Newton's
+    method (Jacobian by central differences), continued in k from beta^{(1)}: the start
+    for order k spreads beta^{(k-1)} over k indices and takes the maxima of f on a grid."""
+    out = {}
+    grid = np.linspace(1e-9, 1.0, 100001)
+
+    def residual(z, k):
+        beta, gam, lam = z[:k], z[k], z[k + 1:]
+        f, df = _gamma_terms(beta, lam)
+        f1, _ = _gamma_terms(beta, np.array([1.0]))
+        f0 = 3.0 / (8.0 * float(np.dot(np.arange(1, k + 1), beta)))
+        return np.concatenate([f - gam, df, [f1[0] - gam, f0 - gam]])
+
+    beta = np.array([1.0])
+    for k in range(1, kmax + 1):
+        if k > 1:   # spread the previous coefficients over k indices
+            t_old = (np.arange(1, k) - 0.5) / (k - 1)
+            t_new = (np.arange(1, k + 1) - 0.5) / k
+            beta = np.interp(t_new, t_old, beta)
+        f, _ = _gamma_terms(beta, grid)
+        inner = np.nonzero((f[1:-1] >= f[:-2]) & (f[1:-1] >= f[2:]))[0] + 1
+        if len(inner) != k - 1:
+            raise RuntimeError(f"order {k}: the start has {len(inner)} interior maxima, not {k - 1}")
+        z = np.concatenate([beta, [float(f[-1])], grid[inner]])
+        close = False
+        for _ in range(40):
+            F = residual(z, k)
+            J = np.empty((len(F), len(z)))
+            for c in range(len(z)):
+                h = 1e-7 * max(1.0, abs(z[c]))
+                zp, zm = z.copy(), z.copy()
+                zp[c] += h
+                zm[c] -= h
+                J[:, c] = (residual(zp, k) - residual(zm, k)) / (2.0 * h)
+            dz = np.linalg.solve(J, -F)
+            z = z + dz
+            if close:            # one step after the update fell below 1e-12: converged
+                break
+            close = np.max(np.abs(dz)) < 1e-12
+        beta = z[:k]
+        out[k] = [float(v) for v in beta]
+    return out
+
+
+_COMPUTED: dict = {}
+
+
 def lambda_min_fraction(kind: str, k: int) -> float:
     """lambda_min / lambda_max for the 1st-kind smoothers."""
     if kind == CHEB1:
@@ -79,9 +165,13 @@ def betas(kind: str, k: int) -> list:
     if kind == CHEB4:
         return [1.0] * k
     if kind == CHEB4_OPT:
-        if k not in BETA:
-            raise ValueError("optimised 4th-kind coefficients are tabulated for k <= 16")
-        return list(BETA[k])
+        if k in BETA:                         # the printed Table beta_coef
+            return list(BETA[k])
+        if not 1 <= k <= MAX_OPT_ORDER:
+            raise ValueError(f"optimised 4th-kind coefficients exist for k <= {MAX_OPT_ORDER}")
+        if k not in _COMPUTED:                # beyond the table: minimise eq. gamma-defn
+            _COMPUTED.update(minimax_betas(k))
+        return list(_COMPUTED[k])
     raise ValueError(kind)
 
 

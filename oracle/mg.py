@@ -47,20 +47,23 @@ class Hierarchy:
     pre: int
     post: int
     extra: dict = field(default_factory=dict)
+    # (pre, post) orders of individual levels, where they differ from (pre, post)
+    level_orders: dict = field(default_factory=dict)
 
     def vcycle(self, b: np.ndarray, j: int = 0) -> np.ndarray:
         if j == len(self.levels) - 1:
             return self.coarse_solve(b)
         lev = self.levels[j]
-        if self.pre > 0:
-            x = cheb.smooth(self.kind, self.pre, lev.apply, lev.Sinv, lev.lmax, b, None)
+        pre, post = self.level_orders.get(j, (self.pre, self.post))
+        if pre > 0:
+            x = cheb.smooth(self.kind, pre, lev.apply, lev.Sinv, lev.lmax, b, None)
             r = b - lev.apply(x)
         else:
             x = np.zeros_like(b)
             r = b.copy()
         x = x + self.prolong[j](self.vcycle(self.restrict[j](r), j + 1))
-        if self.post > 0:
-            x = cheb.smooth(self.kind, self.post, lev.apply, lev.Sinv, lev.lmax, b, x)
+        if post > 0:
+            x = cheb.smooth(self.kind, post, lev.apply, lev.Sinv, lev.lmax, b, x)
         return x
 
     def reset_counters(self):
@@ -132,6 +135,9 @@ def sem_hierarchy(verts, N: int, kind: str, pre: int, post: int, orders=None,
                   coarse: str = "exact", dense_max: int = 4096) -> Hierarchy:
     """p-multigrid hierarchy with rediscretised SEM levels on the same vertices.
 
+    verts: box vertices (mz+1, my+1, mx+1, 3), or an unstructured conforming hexahedral
+    mesh as a tuple (vertex_xyz, elem_vertices[, vertex_dirichlet]) (oracle.mesh).
+
     lmax: optional list of lambda_max(S_j A_j) per smoothed level; otherwise
     each is estimated (dense eigensolve for small levels, Lanczos otherwise).
     schwarz: None for Jacobi smoothing, "asm" or "ras" for the Schwarz smoothers of
@@ -139,13 +145,20 @@ def sem_hierarchy(verts, N: int, kind: str, pre: int, post: int, orders=None,
     estimated densely (small problems only) unless given.
     coarse: "exact" solves the order-1 level exactly (M_l^{-1} = A_l^{-1}, Sec. 2);
     "lattice" continues the V-cycle below order 1 on the Q1 vertex lattice
-    (q1_lattice_levels) with the same Jacobi-Chebyshev smoothing, and solves only the
-    last lattice level (at most dense_max unknowns) exactly. It equals "exact" when the
-    order-1 level already has at most dense_max unknowns.
+    (q1_lattice_levels) with the same Jacobi-Chebyshev kind, smoothed symmetrically with
+    (m, m), m = max(pre, post), on every lattice level (the order-1 level included), and
+    solves only the last lattice level (at most dense_max unknowns) exactly. It equals
+    "exact" when the order-1 level already has at most dense_max unknowns.
     """
     from .schwarz import SchwarzLevel
     orders = default_orders(N) if orders is None else list(orders)
-    boxes = [SemBox(verts, o) for o in orders]
+    if isinstance(verts, tuple):   # unstructured mesh: (vertex_xyz, elem_vertices, vertex_dirichlet)
+        from .mesh import SemMesh
+        if coarse != "exact" or schwarz:
+            raise ValueError("unstructured meshes use Jacobi smoothing and the exact order-1 solve")
+        boxes = [SemMesh(verts[0], verts[1], o, verts[2] if len(verts) > 2 else None) for o in orders]
+    else:
+        boxes = [SemBox(verts, o) for o in orders]
     hAs, hPs = q1_lattice_levels(boxes[-1], dense_max) if coarse == "lattice" else ([None], [])
     nh = len(hPs)  # smoothed lattice levels (the order-1 level among them when nh > 0)
     nsm = len(boxes) - 1 + nh
@@ -179,7 +192,9 @@ def sem_hierarchy(verts, N: int, kind: str, pre: int, post: int, orders=None,
         prolong += [(lambda x, P=P: P @ x) for P in hPs]
         restrict += [(lambda x, P=P: P.T @ x) for P in hPs]
         coarse_solve = exact_coarse(Ac)
+    m = max(pre, post)
+    lattice_orders = {j: (m, m) for j in range(len(boxes) - 1, nsm)} if nh else {}
     return Hierarchy(levels=levels, prolong=prolong, restrict=restrict, coarse_solve=coarse_solve,
-                     kind=kind, pre=pre, post=post,
+                     kind=kind, pre=pre, post=post, level_orders=lattice_orders,
                      extra={"boxes": boxes, "orders": orders, "lattice_As": hAs if nh else [],
                             "lattice_Ps": hPs})

@@ -50,31 +50,19 @@ def grad_transpose_local(D: np.ndarray, wr, ws, wt):
             + np.einsum("lk,elji->ekji", D, wt))
 
 
-class SemBox:
-    """Order-N SEM discretisation of -Laplace(u) = f on a structured hexahedral box.
+class SemDiscretisation:
+    """Order-N SEM discretisation of -Laplace(u) = f on hexahedral elements, each the
+    trilinear image of the reference cube under its 8 corners. Subclasses give the
+    corners and the local-to-global map; the operator and its relatives only use D, G,
+    B_local and l2g."""
 
-    verts: (mz+1, my+1, mx+1, 3) vertex coordinates (x fastest). Dirichlet
-    conditions hold on the whole boundary of the box.
-    """
-
-    def __init__(self, verts: np.ndarray, N: int):
-        verts = np.asarray(verts, dtype=np.float64)
-        self.verts = verts
+    def _set_geometry(self, C: np.ndarray, N: int):
+        """C[e, ck, cj, ci, d]: corner coordinates, reference corner (ci, cj, ck) in {0,1}^3."""
         self.N = N
-        self.mz, self.my, self.mx = (s - 1 for s in verts.shape[:3])
-        self.E = self.mx * self.my * self.mz
+        self.E = C.shape[0]
         n1 = N + 1
         self.xi, self.w = gll_nodes_weights(N)
         self.D = derivative_matrix(N)
-
-        # element corner coordinates C[e, ck, cj, ci, d]
-        C = np.empty((self.E, 2, 2, 2, 3))
-        e = 0
-        for ez in range(self.mz):
-            for ey in range(self.my):
-                for ex in range(self.mx):
-                    C[e] = verts[ez:ez + 2, ey:ey + 2, ex:ex + 2, :]
-                    e += 1
         self.corners = C
         # trilinear map evaluated at the GLL points
         h = np.stack([(1.0 - self.xi) / 2.0, (1.0 + self.xi) / 2.0], axis=0)  # h[c, i]
@@ -97,6 +85,31 @@ class SemBox:
                 self.G[:, _comp(a, b)] = self.B_local * np.einsum(
                     "...d,...d->...", Jinv[..., a, :], Jinv[..., b, :])
 
+
+class SemBox(SemDiscretisation):
+    """Order-N SEM discretisation of -Laplace(u) = f on a structured hexahedral box.
+
+    verts: (mz+1, my+1, mx+1, 3) vertex coordinates (x fastest). Dirichlet
+    conditions hold on the whole boundary of the box.
+    """
+
+    def __init__(self, verts: np.ndarray, N: int):
+        verts = np.asarray(verts, dtype=np.float64)
+        self.verts = verts
+        self.mz, self.my, self.mx = (s - 1 for s in verts.shape[:3])
+        E = self.mx * self.my * self.mz
+        n1 = N + 1
+
+        # element corner coordinates C[e, ck, cj, ci, d]
+        C = np.empty((E, 2, 2, 2, 3))
+        e = 0
+        for ez in range(self.mz):
+            for ey in range(self.my):
+                for ex in range(self.mx):
+                    C[e] = verts[ez:ez + 2, ey:ey + 2, ex:ex + 2, :]
+                    e += 1
+        self._set_geometry(C, N)
+
         # local-to-global map of interior unknowns (-1 on the Dirichlet boundary)
         self.nx, self.ny, self.nz = self.mx * N - 1, self.my * N - 1, self.mz * N - 1
         self.n = self.nx * self.ny * self.nz
@@ -115,6 +128,7 @@ class SemBox:
         self.mult = self.gather(np.ones_like(self.B_local))  # copies per unknown
 
     # ---- Q and Q^T (with the Dirichlet restriction R) -------------------------
+    # (these and the methods below need only D, G, B_local, X and l2g; SemMesh shares them)
     def scatter(self, u: np.ndarray) -> np.ndarray:
         """Q R^T u: global unknowns -> element-local copies (zero on the boundary)."""
         out = np.zeros(self.l2g.shape)

@@ -25,7 +25,7 @@ MAX_LEVELS = 8
 
 # exported entry points, as declared in include/semcheb.h
 EXPORTS = (
-    "sem_options_default", "sem_setup_box", "sem_setup_fd2d", "sem_sizes", "sem_level_info",
+    "sem_options_default", "sem_setup_box", "sem_setup", "sem_setup_fd2d", "sem_sizes", "sem_level_info",
     "sem_apply_A", "sem_apply_A_noalloc", "sem_apply_local", "sem_vcycle", "sem_solve", "sem_coords", "sem_mass_apply", "sem_get_factors",
     "sem_set_factors", "sem_adjoint_contract", "sem_apply_counts", "sem_reset_counts",
     "sem_host_array", "sem_set_smoothing", "sem_beta_table", "sem_destroy", "sem_last_error", "sem_global_error",
@@ -48,6 +48,12 @@ class SemOptions(C.Structure):
 class SemBoxMesh(C.Structure):
     _fields_ = [("nex", C.c_int32), ("ney", C.c_int32), ("nez", C.c_int32),
                 ("vertex_xyz", C.POINTER(C.c_double))]
+
+
+class SemMesh(C.Structure):
+    _fields_ = [("num_elements", C.c_int32), ("num_vertices", C.c_int32),
+                ("vertex_xyz", C.POINTER(C.c_double)), ("elem_vertices", C.POINTER(C.c_int32)),
+                ("vertex_dirichlet", C.POINTER(C.c_uint8))]
 
 
 class SemError(RuntimeError):
@@ -77,6 +83,7 @@ def load() -> C.CDLL:
     sig = {
         "sem_options_default": (None, [P(SemOptions)]),
         "sem_setup_box": (i32, [P(SemBoxMesh), P(SemOptions), vp, P(vp)]),
+        "sem_setup": (i32, [P(SemMesh), P(SemOptions), vp, P(vp)]),
         "sem_setup_fd2d": (i32, [i32, dbl, dbl, i32, i32, P(SemOptions), vp, P(vp)]),
         "sem_sizes": (i32, [vp, P(i64), P(i32), P(i64)]),
         "sem_level_info": (i32, [vp, i32, P(i32), P(i64), P(dbl)]),

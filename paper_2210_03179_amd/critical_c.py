@@ -143,8 +143,8 @@ def _rate(solver: FdSolver, b, kind: str, m: int, nn: int, rtol: float, maxit: i
 
 
 def max_order(kind: str, kmax: int) -> int:
-    """Largest k whose (2k,0) cycle the smoother supports (tabulated beta: 2k <= 16)."""
-    return min(kmax, 8) if kind == "cheb4opt" else kmax
+    """Largest k whose (2k,0) cycle the smoother supports (optimised 4th kind: 2k <= 32)."""
+    return min(kmax, 16) if kind == "cheb4opt" else kmax
 
 
 def run_study(n=128, factors=(2, 8), Lxs=(1, 2, 4, 8, 16, 32, 64), kmax=10, rtol=1e-6, maxit=200,

@@ -134,8 +134,9 @@ sem_status validate_common(const sem_options *o, std::string &err) {
     return SEM_EINVAL;
   }
   if (o->pre_order + o->post_order < 1) { err = "pre_order + post_order must be >= 1"; return SEM_EINVAL; }
-  if (o->smoother == SEM_CHEB4_OPT && (o->pre_order > 16 || o->post_order > 16)) {
-    err = "optimised 4th-kind coefficients are tabulated for orders <= 16";
+  if (o->smoother == SEM_CHEB4_OPT &&
+      ((o->pre_order > 0 && !beta_row(o->pre_order)) || (o->post_order > 0 && !beta_row(o->post_order)))) {
+    err = "optimised 4th-kind coefficients exist for orders <= " + std::to_string(kMaxOptOrder);
     return SEM_EINVAL;
   }
   if (o->precision != SEM_FP64 && o->precision != SEM_MIXED) { err = "unknown precision"; return SEM_EINVAL; }
@@ -191,6 +192,8 @@ template <> struct V<double> {
   static const double *swD(const Level &L) { return L.swD64; }
   static double *swY(Level &L) { return L.swY64; }
   static double *swT(Level &L) { return L.swT64; }
+  static double *wl(Level &L) { return L.wl64; }
+  static const double *winv(const Level &L) { return L.winv64; }
 };
 template <> struct V<float> {
   static float *&b(Level &L) { return L.b32; }
@@ -205,6 +208,8 @@ template <> struct V<float> {
   static const float *swD(const Level &L) { return L.swD32; }
   static float *swY(Level &L) { return L.swY32; }
   static float *swT(Level &L) { return L.swT32; }
+  static float *wl(Level &L) { return L.wl32; }
+  static const float *winv(const Level &L) { return L.winv32; }
 };
 
 // operator on level L: SEM -> element-local result in w (length E (N+1)^3),
@@ -212,8 +217,14 @@ template <> struct V<float> {
 template <typename T>
 void apply_level(Level &L, const T *u, T *w, hipStream_t s) {
   L.applies++;
-  if (L.type == LVL_SEM) launch_ax(L, u, w, s);
-  else launch_csr(L.A, V<T>::val(L.A), u, (const T *)nullptr, w, 0, s);
+  if (L.type == LVL_SEM) {
+    launch_ax(L, u, w, s);
+  } else if (L.type == LVL_GEN) {  // unstructured mesh: element products, then their sums
+    launch_ax_map(L, u, V<T>::wl(L), s);
+    launch_sum_lists<T, T>(L, V<T>::wl(L), w, nullptr, false, s);
+  } else {
+    launch_csr(L.A, V<T>::val(L.A), u, (const T *)nullptr, w, 0, s);
+  }
 }
 
 // Chebyshev smoothing with a Schwarz smoother S in place of diag(A)^{-1} (Sec. 4.1: the
@@ -431,7 +442,9 @@ void vcycle(sem_ctx *c, int j, hipStream_t s) {
     coarse_solve<T>(c, L, s);
     return;
   }
-  const int pre = c->opt.pre_order, post = c->opt.post_order;
+  int pre = c->opt.pre_order, post = c->opt.post_order;
+  // lattice levels (lattice multigrid below order 1): symmetric (m, m), m = max(pre, post)
+  if (c->lattice_from >= 0 && j >= c->lattice_from) pre = post = std::max(pre, post);
   T *b = V<T>::b(L), *x = V<T>::x(L), *r = V<T>::r(L), *w = V<T>::w(L);
   if (pre > 0) {
     smooth<T>(c, L, pre, true, s);
@@ -462,6 +475,13 @@ void vcycle(sem_ctx *c, int j, hipStream_t s) {
     }
     if (wide) launch_dss_wide(C, C.w32, wide_b, s);
     else launch_dss<T>(C, V<T>::w(C), V<T>::b(C), s);
+  } else if (L.type == LVL_GEN) {
+    // P^T r on a mesh: the residual weighted by 1 / copies, gathered to the element copies,
+    // interpolated back to the coarse order per element and summed over the coarse copies
+    launch_resid_weight<T>(L, ad, b, r, s);
+    launch_gather_map<T>(L, r, V<T>::winv(L), V<T>::wl(L), s);
+    launch_interp_elem<T>(L.E, C.N + 1, L.N + 1, V<T>::J(L), V<T>::wl(L), V<T>::wl(C), true, s);
+    launch_sum_lists<T, T>(C, V<T>::wl(C), V<T>::b(C), nullptr, false, s);
   } else {
     launch_resid_weight<T>(L, ad, b, r, s);
     launch_csr<T>(L.R, V<T>::val(L.R), r, (const T *)nullptr, V<T>::b(C), 0, s);
@@ -480,7 +500,14 @@ void vcycle(sem_ctx *c, int j, hipStream_t s) {
                                      zdots ? c->zdot_r2 : nullptr, c->partials, c->partials_cap,
                                      wide ? wide_x : nullptr);
     if (zdots) c->zdot_blocks = nb;
-  } else launch_csr<T>(L.P, V<T>::val(L.P), V<T>::x(C), (const T *)nullptr, x, 2, s);
+  } else if (L.type == LVL_GEN) {
+    // x += P x_c: coarse copies, interpolated per element, averaged over the fine copies
+    launch_gather_map<T>(C, V<T>::x(C), (const T *)nullptr, V<T>::wl(C), s);
+    launch_interp_elem<T>(L.E, C.N + 1, L.N + 1, V<T>::J(L), V<T>::wl(C), V<T>::wl(L), false, s);
+    launch_sum_lists<T, T>(L, V<T>::wl(L), x, V<T>::winv(L), true, s);
+  } else {
+    launch_csr<T>(L.P, V<T>::val(L.P), V<T>::x(C), (const T *)nullptr, x, 2, s);
+  }
   if (post > 0) smooth<T>(c, L, post, false, s);
 }
 
@@ -578,6 +605,13 @@ void fine_apply(sem_ctx *c, const double *u, double *w, const double *p, hipStre
     launch_ax(L0, u, L0.w64, s);
     if (p) c->npartials = launch_dss_dot(L0, L0.w64, w, p, c->partials, s);
     else launch_dss<double>(L0, L0.w64, w, s);
+  } else if (L0.type == LVL_GEN) {
+    launch_ax_map(L0, u, L0.wl64, s);
+    launch_sum_lists<double, double>(L0, L0.wl64, w, nullptr, false, s);
+    if (p) {
+      launch_dots<double>(L0.n, 1, p, w, nullptr, nullptr, nullptr, nullptr, c->partials, kReduceBlocks, s);
+      c->npartials = kReduceBlocks;
+    }
   } else {
     launch_csr<double>(L0.A, L0.A.val64, u, nullptr, w, 0, s);
     if (p) {
@@ -621,6 +655,9 @@ sem_status lanczos(sem_ctx *c, int j, double &out, hipStream_t s) {
     if (L.type == LVL_SEM) {
       launch_ax(L, v, L.w64, s);
       launch_dss<double>(L, L.w64, wv, s);
+    } else if (L.type == LVL_GEN) {
+      launch_ax_map(L, v, L.wl64, s);
+      launch_sum_lists<double, double>(L, L.wl64, wv, nullptr, false, s);
     } else {
       launch_csr<double>(L.A, L.A.val64, v, nullptr, wv, 0, s);
     }
@@ -1266,6 +1303,150 @@ sem_status setup_box_impl(const sem_box_mesh *mesh, const sem_options *opt, hipS
   return SEM_OK;
 }
 
+// Set-up on an unstructured conforming hexahedral mesh: the same hierarchy as on a box
+// (orders N, floor(N/2), 1 by default, rediscretised on the same elements) with LVL_GEN
+// levels, and the exact order-1 solve by one dense inverse.
+sem_status setup_mesh_impl(const sem_mesh *mesh, const sem_options *opt, hipStream_t s, sem_ctx *c) {
+  c->kind = LVL_SEM;
+  c->opt = *opt;
+  c->host_only = opt->device < 0;
+  c->device = opt->device < 0 ? 0 : opt->device;
+  TRY(validate_common(opt, c->err));
+  if (!mesh || !mesh->vertex_xyz || !mesh->elem_vertices || mesh->num_elements < 1 || mesh->num_vertices < 8) {
+    c->err = "mesh needs elements, vertices and their coordinates";
+    return SEM_EINVAL;
+  }
+  for (int64_t q = 0; q < 8 * (int64_t)mesh->num_elements; ++q)
+    if (mesh->elem_vertices[q] < 0 || mesh->elem_vertices[q] >= mesh->num_vertices) {
+      c->err = "elem_vertices holds an index outside 0..num_vertices-1";
+      return SEM_EINVAL;
+    }
+  if (opt->N < 1 || opt->N > 12) { c->err = "order N must lie in 1..12"; return SEM_EINVAL; }
+  if ((int64_t)mesh->num_elements * (opt->N + 1) * (opt->N + 1) * (opt->N + 1) >= (int64_t(1) << 31)) {
+    c->err = "more than 2^31 element-local nodes";
+    return SEM_EINVAL;
+  }
+  if (opt->schwarz != SEM_JACOBI || opt->geometry != SEM_GEOM_STORED || opt->coarse_solver != SEM_COARSE_EXACT ||
+      opt->coarse_storage != SEM_FP64) {
+    c->err = "unstructured meshes use Jacobi smoothing, stored factors and the exact FP64 order-1 solve";
+    return SEM_EINVAL;
+  }
+  std::vector<int> orders;
+  if (opt->num_levels == 0) {
+    orders.push_back(opt->N);
+    if (opt->N / 2 >= 1 && opt->N / 2 < opt->N) orders.push_back(opt->N / 2);
+    if (orders.back() > 1) orders.push_back(1);
+  } else {
+    if (opt->num_levels < 1 || opt->num_levels > SEM_MAX_LEVELS) { c->err = "bad num_levels"; return SEM_EINVAL; }
+    for (int j = 0; j < opt->num_levels; ++j) orders.push_back(opt->orders[j]);
+    if (orders[0] != opt->N) { c->err = "orders[0] must equal N"; return SEM_EINVAL; }
+    for (size_t j = 1; j < orders.size(); ++j)
+      if (orders[j] >= orders[j - 1] || orders[j] < 1) { c->err = "orders must decrease"; return SEM_EINVAL; }
+    if (orders.back() != 1) { c->err = "the coarsest order must be 1"; return SEM_EINVAL; }
+  }
+  TRY(init_device(c, s));
+  const int nl = (int)orders.size();
+  c->host_levels.resize(nl);
+  for (int j = 0; j < nl; ++j) {
+    const sem_status st = build_mesh_level(*mesh, orders[j], c->host_levels[j], c->err);
+    if (st != SEM_OK) return st;
+  }
+  c->host_interp.resize(nl);
+  for (int j = 0; j + 1 < nl; ++j) c->host_interp[j] = make_interp(c->host_levels[j].gll, c->host_levels[j + 1].gll);
+  const BoxLevelHost &H = c->host_levels.back();
+  constexpr int64_t kMeshCoarseMax = 8192;
+  if (H.n > kMeshCoarseMax) {
+    c->err = "unstructured meshes need an order-1 level of at most 8192 unknowns (dense exact solve)";
+    return SEM_EINVAL;
+  }
+  const Csr Ac = assemble_q1(H);
+  BlockTri bt;
+  if (!block_tridiag_factor(Ac, {0, H.n}, bt, c->err)) return SEM_EINVAL;
+  if (H.n <= 4096) {
+    c->coarse.host_dense.assign((size_t)H.n * H.n, 0.0);
+    for (int64_t r = 0; r < H.n; ++r)
+      for (int64_t p = Ac.rowptr[r]; p < Ac.rowptr[r + 1]; ++p) c->coarse.host_dense[r * H.n + Ac.col[p]] = Ac.val[p];
+  }
+  c->coarse.n = H.n;
+  c->coarse.dense = true;
+  c->coarse.start = {0, H.n};
+  c->levels.resize(nl);
+  for (int j = 0; j < nl; ++j) {
+    const BoxLevelHost &h = c->host_levels[j];
+    Level &L = c->levels[j];
+    L.type = LVL_GEN;
+    L.N = h.N;
+    L.n1 = h.n1;
+    L.nex = L.ney = L.nez = 1;
+    L.nx = L.ny = L.nz = 1;
+    L.E = h.E;
+    L.L = h.L;
+    L.n = h.n;
+  }
+  if (c->host_only) {
+    if (opt->num_lambda_max > 0) TRY(estimate_lambdas(c, s));
+    return SEM_OK;
+  }
+  const bool mixed = opt->precision == SEM_MIXED;
+  for (int j = 0; j < nl; ++j) {
+    const BoxLevelHost &h = c->host_levels[j];
+    Level &L = c->levels[j];
+    const bool coarse = j == nl - 1;
+    TRY(upload(c, &L.G64, h.G.data(), h.G.size(), s));
+    TRY(upload(c, &L.D64, h.gll.D.data(), h.gll.D.size(), s));
+    std::vector<float> D32(h.gll.D.begin(), h.gll.D.end());
+    TRY(upload(c, &L.D32, D32.data(), D32.size(), s));
+    std::vector<double> inv(h.n), winv(h.n);
+    for (int64_t i = 0; i < h.n; ++i) {
+      inv[i] = 1.0 / h.diag[i];
+      winv[i] = 1.0 / (double)(h.lrow[i + 1] - h.lrow[i]);
+    }
+    TRY(upload(c, &L.invdiag64, inv.data(), inv.size(), s));
+    std::vector<float> inv32(inv.begin(), inv.end()), winv32(winv.begin(), winv.end());
+    TRY(upload(c, &L.invdiag32, inv32.data(), inv32.size(), s));
+    TRY(upload(c, &L.winv64, winv.data(), winv.size(), s));
+    TRY(upload(c, &L.winv32, winv32.data(), winv32.size(), s));
+    TRY(upload(c, &L.map, h.l2g.data(), h.l2g.size(), s));
+    TRY(upload(c, &L.lrow, h.lrow.data(), h.lrow.size(), s));
+    TRY(upload(c, &L.lidx, h.lidx.data(), h.lidx.size(), s));
+    if (mixed && !coarse) {
+      std::vector<uint16_t> gb(h.G.size());
+      for (size_t q = 0; q < gb.size(); ++q) gb[q] = to_bf16(h.G[q]);
+      TRY(upload(c, &L.Gbf, gb.data(), gb.size(), s));
+    }
+    if (!coarse) {
+      const std::vector<double> &J = c->host_interp[j];
+      TRY(upload(c, &L.J64, J.data(), J.size(), s));
+      std::vector<float> J32(J.begin(), J.end());
+      TRY(upload(c, &L.J32, J32.data(), J32.size(), s));
+    }
+    if (j == 0) {
+      TRY(upload(c, &L.mass, h.mass.data(), h.mass.size(), s));
+      TRY(upload(c, &L.coords, h.coords.data(), h.coords.size(), s));
+    }
+    TRY(alloc_level_vectors(c, L, mixed, coarse));
+    // element-local work arrays: FP64 for the Krylov operator and the Lanczos estimates (and
+    // the FP64 cycle), FP32 for the mixed cycle's smoothing and transfers
+    TRY(dalloc(c, &L.wl64, (size_t)L.L));
+    if (mixed) {
+      TRY(dalloc(c, &L.wl32, (size_t)L.L));
+      if (!coarse || j == 0) TRY(dalloc(c, &L.w64, (size_t)L.n));
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  CoarseSolver &C = c->coarse;
+  TRY(dalloc(c, &C.b, C.n));
+  TRY(dalloc(c, &C.x, C.n));
+  TRY(dalloc(c, &C.y, C.n));
+  TRY(dalloc(c, &C.t, C.n));
+  TRY(upload(c, &C.Minv, bt.Minv[0].data(), bt.Minv[0].size(), s));
+  TRY(alloc_krylov(c, c->levels[0].n));
+  HIPCHK(c, hipStreamSynchronize(s));
+  TRY(estimate_lambdas(c, s));
+  for (auto &L : c->levels) L.applies = 0;
+  return SEM_OK;
+}
+
 Csr transpose(const Csr &A) {
   Csr T;
   T.nrows = A.ncols;
@@ -1433,6 +1614,21 @@ sem_status sem_setup_box(const sem_box_mesh *mesh, const sem_options *opt, void 
   return SEM_OK;
 }
 
+sem_status sem_setup(const sem_mesh *mesh, const sem_options *opt, void *stream, sem_ctx **out) {
+  if (!out || !opt) { set_global_error("null argument"); return SEM_EINVAL; }
+  *out = nullptr;
+  sem_ctx *c = new sem_ctx();
+  const sem_status st = setup_mesh_impl(mesh, opt, (hipStream_t)stream, c);
+  if (st != SEM_OK) {
+    const std::string msg = c->err;
+    release(c);
+    set_global_error(msg);
+    return st;
+  }
+  *out = c;
+  return SEM_OK;
+}
+
 sem_status sem_setup_fd2d(int32_t n, double Lx, double Ly, int32_t factor, int32_t coarsest_n,
                           const sem_options *opt, void *stream, sem_ctx **out) {
   if (!out || !opt) { g_err = "null argument"; return SEM_EINVAL; }
@@ -1475,7 +1671,10 @@ sem_status sem_apply_A(sem_ctx *c, const double *u, double *w, void *stream) {
 sem_status sem_apply_A_noalloc(sem_ctx *c, const double *u, double *w, void *stream) {
   TRY(need_device(c));
   if (!u || !w) { c->err = "null vector"; return SEM_EINVAL; }
-  if (c->kind != LVL_SEM) { c->err = "sem_apply_A_noalloc needs a SEM context"; return SEM_EINVAL; }
+  if (c->kind != LVL_SEM || c->levels[0].type != LVL_SEM) {
+    c->err = "sem_apply_A_noalloc needs a SEM box context";
+    return SEM_EINVAL;
+  }
   Level &L0 = c->levels[0];
   if (L0.L > kNoAllocScratchDoubles) {
     c->err = "sem_apply_A_noalloc: the finest level has " + std::to_string(L0.L) +
@@ -1500,10 +1699,13 @@ sem_status sem_apply_local(sem_ctx *c, int32_t precision, const void *u, void *w
   TRY(need_device(c));
   if (c->kind != LVL_SEM || !u || !wL) { c->err = "element-local apply needs a SEM context and vectors"; return SEM_EINVAL; }
   const Level &L0 = c->levels[0];
+  const bool gen = L0.type == LVL_GEN;
   if (precision == SEM_FP64) {
-    launch_ax(L0, (const double *)u, (double *)wL, (hipStream_t)stream);
+    if (gen) launch_ax_map(L0, (const double *)u, (double *)wL, (hipStream_t)stream);
+    else launch_ax(L0, (const double *)u, (double *)wL, (hipStream_t)stream);
   } else if (precision == SEM_MIXED && (L0.Gbf || L0.tri32)) {
-    launch_ax(L0, (const float *)u, (float *)wL, (hipStream_t)stream);
+    if (gen) launch_ax_map(L0, (const float *)u, (float *)wL, (hipStream_t)stream);
+    else launch_ax(L0, (const float *)u, (float *)wL, (hipStream_t)stream);
   } else {
     c->err = "precision not available on this context";
     return SEM_EINVAL;
@@ -1797,6 +1999,10 @@ sem_status sem_adjoint_contract(sem_ctx *c, const double *lam, const double *u, 
                                 void *stream) {
   TRY(need_device(c));
   if (c->kind != LVL_SEM || !lam || (!u && dG)) { c->err = "invalid adjoint arguments"; return SEM_EINVAL; }
+  if (dG && c->levels[0].type != LVL_SEM) {
+    c->err = "the adjoint factor contraction exists for box meshes";
+    return SEM_EINVAL;
+  }
   hipStream_t s = (hipStream_t)stream;
   if (dG && !launch_adjoint(c->levels[0], lam, u, dG, s)) { c->err = "unsupported order"; return SEM_EINVAL; }
   if (df) launch_mul(c->levels[0].n, c->levels[0].mass, lam, df, s);

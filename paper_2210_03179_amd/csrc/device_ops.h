@@ -217,10 +217,12 @@ struct AxShape {
 // PF = 0: each plane loads its own factors (fewer registers, latency hidden by occupancy).
 // The plane loop stays rolled (the FP64 kernel would not fit its registers
 // unrolled); register arrays are then indexed through selects on k.
-template <int N, typename T, typename GT, int PF = 1>
+// MAP = true (unstructured meshes): the element's input values are gathered through the
+// local-to-global map (-1: Dirichlet node, value 0) instead of the box lattice arithmetic.
+template <int N, typename T, typename GT, int PF = 1, bool MAP = false>
 __device__ __forceinline__ void ax_body(unsigned blk, const Box &b, int64_t E, const T *__restrict__ u,
                                         const GT *__restrict__ G, const T *__restrict__ Dm,
-                                        T *__restrict__ wL) {
+                                        T *__restrict__ wL, const int32_t *__restrict__ map = nullptr) {
   using S = AxShape<N>;
   constexpr int n1 = S::n1, n3 = n1 * n1 * n1;
   __shared__ T sD[n1 * n1];
@@ -253,10 +255,16 @@ __device__ __forceinline__ void ax_body(unsigned blk, const Box &b, int64_t E, c
   for (int k = 0; k < n1; ++k) {
     // unconditional load from a valid index, then select: no branch per load, so the
     // whole column is in flight at once
-    const int K = ez * N + k;
-    const bool ok = inIJ && K >= 1 && K <= b.nz;
-    const T v = u[ok ? gIJ + plane * (K - 1) : 0];
-    ureg[k] = ok ? v : T(0);
+    if constexpr (MAP) {
+      const int32_t gi = active ? map[e * n3 + (k * n1 + j) * n1 + i] : -1;
+      const T v = u[gi >= 0 ? gi : 0];
+      ureg[k] = gi >= 0 ? v : T(0);
+    } else {
+      const int K = ez * N + k;
+      const bool ok = inIJ && K >= 1 && K <= b.nz;
+      const T v = u[ok ? gIJ + plane * (K - 1) : 0];
+      ureg[k] = ok ? v : T(0);
+    }
     wreg[k] = T(0);
   }
   __syncthreads();

@@ -7,6 +7,9 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <unordered_map>
+#include <array>
 
 #include "internal.h"
 
@@ -83,34 +86,24 @@ static inline int64_t vidx(const sem_box_mesh &m, int i, int j, int k) {
   return (int64_t)i + (int64_t)(m.nex + 1) * ((int64_t)j + (int64_t)(m.ney + 1) * k);
 }
 
-sem_status build_box_level(const sem_box_mesh &mesh, int N, BoxLevelHost &L, std::string &err) {
-  L.N = N;
-  L.n1 = N + 1;
-  L.nex = mesh.nex;
-  L.ney = mesh.ney;
-  L.nez = mesh.nez;
-  L.nx = mesh.nex * N - 1;
-  L.ny = mesh.ney * N - 1;
-  L.nz = mesh.nez * N - 1;
-  L.E = (int64_t)mesh.nex * mesh.ney * mesh.nez;
-  const int n1 = L.n1, n3 = n1 * n1 * n1;
-  L.L = L.E * n3;
-  L.n = (int64_t)L.nx * L.ny * L.nz;
-  L.gll = make_gll(N);
-  const Gll &g = L.gll;
-  L.G.assign((size_t)L.E * 6 * n3, 0.0);
-  std::vector<double> Bl((size_t)L.L), dl((size_t)L.L), Xl((size_t)L.L * 3);
+// Per-element geometry of trilinear elements at order g.N: factors G ([e][6][n1^3]), local
+// mass Bl, local diagonal dl of sum_ab D_a^T G_ab D_b and node coordinates Xl. corner(e, C)
+// fills C[ck][cj][ci][d] with the element's corners. Returns the number of GLL points with a
+// non-positive Jacobian.
+template <class CornerFn>
+static int element_geometry(int64_t E, const Gll &g, CornerFn corner, std::vector<double> &G, std::vector<double> &Bl,
+                            std::vector<double> &dl, std::vector<double> &Xl) {
+  const int N = g.N, n1 = N + 1, n3 = n1 * n1 * n1;
+  G.assign((size_t)E * 6 * n3, 0.0);
+  Bl.assign((size_t)E * n3, 0.0);
+  dl.assign((size_t)E * n3, 0.0);
+  Xl.assign((size_t)E * n3 * 3, 0.0);
   int bad = 0;
 
 #pragma omp parallel for schedule(static) reduction(+ : bad)
-  for (int64_t e = 0; e < L.E; ++e) {
-    const int ex = (int)(e % L.nex), ey = (int)((e / L.nex) % L.ney), ez = (int)(e / ((int64_t)L.nex * L.ney));
+  for (int64_t e = 0; e < E; ++e) {
     double C[2][2][2][3];
-    for (int ck = 0; ck < 2; ++ck)
-      for (int cj = 0; cj < 2; ++cj)
-        for (int ci = 0; ci < 2; ++ci)
-          for (int d = 0; d < 3; ++d)
-            C[ck][cj][ci][d] = mesh.vertex_xyz[3 * vidx(mesh, ex + ci, ey + cj, ez + ck) + d];
+    corner(e, C);
     std::vector<double> X(3 * n3);
     for (int k = 0; k < n1; ++k)
       for (int j = 0; j < n1; ++j)
@@ -125,7 +118,7 @@ sem_status build_box_level(const sem_box_mesh &mesh, int N, BoxLevelHost &L, std
             X[3 * ((k * n1 + j) * n1 + i) + d] = s;
           }
         }
-    double *Ge = &L.G[(size_t)e * 6 * n3];
+    double *Ge = &G[(size_t)e * 6 * n3];
     for (int k = 0; k < n1; ++k)
       for (int j = 0; j < n1; ++j)
         for (int i = 0; i < n1; ++i) {
@@ -183,6 +176,34 @@ sem_status build_box_level(const sem_box_mesh &mesh, int N, BoxLevelHost &L, std
           dl[(size_t)e * n3 + q] = s;
         }
   }
+  return bad;
+}
+
+sem_status build_box_level(const sem_box_mesh &mesh, int N, BoxLevelHost &L, std::string &err) {
+  L.N = N;
+  L.n1 = N + 1;
+  L.nex = mesh.nex;
+  L.ney = mesh.ney;
+  L.nez = mesh.nez;
+  L.nx = mesh.nex * N - 1;
+  L.ny = mesh.ney * N - 1;
+  L.nz = mesh.nez * N - 1;
+  L.E = (int64_t)mesh.nex * mesh.ney * mesh.nez;
+  const int n1 = L.n1, n3 = n1 * n1 * n1;
+  L.L = L.E * n3;
+  L.n = (int64_t)L.nx * L.ny * L.nz;
+  L.gll = make_gll(N);
+  std::vector<double> Bl, dl, Xl;
+  const int bad = element_geometry(
+      L.E, L.gll,
+      [&](int64_t e, double C[2][2][2][3]) {
+        const int ex = (int)(e % L.nex), ey = (int)((e / L.nex) % L.ney), ez = (int)(e / ((int64_t)L.nex * L.ney));
+        for (int ck = 0; ck < 2; ++ck)
+          for (int cj = 0; cj < 2; ++cj)
+            for (int ci = 0; ci < 2; ++ci)
+              for (int d = 0; d < 3; ++d) C[ck][cj][ci][d] = mesh.vertex_xyz[3 * vidx(mesh, ex + ci, ey + cj, ez + ck) + d];
+      },
+      L.G, Bl, dl, Xl);
   if (bad) {
     err = "mesh has " + std::to_string(bad) + " GLL points with non-positive Jacobian at order " +
           std::to_string(N);
@@ -211,6 +232,192 @@ sem_status build_box_level(const sem_box_mesh &mesh, int N, BoxLevelHost &L, std
         }
       }
     }
+  }
+  return SEM_OK;
+}
+
+// ------------------------------------------------------------------ unstructured meshes
+namespace {
+
+// Identity of a GLL node of a conforming mesh, independent of the element it is seen from:
+// kind 0 vertex (v), 1 edge node (lower vertex id, higher id, position from the lower),
+// 2 face node (the face's smallest vertex id, its neighbour along the first canonical axis,
+// along the second, and the position (p, q) on those axes; the first axis points to the
+// smaller neighbour id), 3 element-interior node (element, local index).
+struct NodeKey {
+  int64_t a, b, c;
+  bool operator==(const NodeKey &o) const { return a == o.a && b == o.b && c == o.c; }
+};
+struct NodeKeyHash {
+  size_t operator()(const NodeKey &k) const {
+    uint64_t h = (uint64_t)k.a * 0x9E3779B97F4A7C15ull;
+    h ^= (uint64_t)k.b + 0xBF58476D1CE4E5B9ull + (h << 6) + (h >> 2);
+    h ^= (uint64_t)k.c + 0x94D049BB133111EBull + (h << 6) + (h >> 2);
+    return (size_t)h;
+  }
+};
+
+inline int corner_of(int bi, int bj, int bk) { return bi + 2 * bj + 4 * bk; }
+
+// Key of local node (i, j, k) of element e (corners cv[8], order N).
+NodeKey node_key(int64_t e, const int32_t *cv, int N, int i, int j, int k) {
+  const int idx[3] = {i, j, k};
+  int ext = 0;
+  for (int d = 0; d < 3; ++d) ext += (idx[d] == 0 || idx[d] == N);
+  if (ext == 0) return NodeKey{(int64_t)3 << 60 | e, (int64_t)((k * (N + 1) + j) * (N + 1) + i), 0};
+  if (ext == 3) return NodeKey{(int64_t)cv[corner_of(i == N, j == N, k == N)], 0, 0};
+  if (ext == 2) {
+    int fa = 0;  // the free axis
+    for (int d = 0; d < 3; ++d)
+      if (idx[d] != 0 && idx[d] != N) fa = d;
+    int bits[3] = {i == N, j == N, k == N};
+    bits[fa] = 0;
+    const int va = cv[corner_of(bits[0], bits[1], bits[2])];
+    bits[fa] = 1;
+    const int vb = cv[corner_of(bits[0], bits[1], bits[2])];
+    const int t = idx[fa];
+    if (va < vb) return NodeKey{(int64_t)1 << 60 | va, vb, t};
+    return NodeKey{(int64_t)1 << 60 | vb, va, N - t};
+  }
+  // face node: the fixed axis and the two free axes a1 < a2
+  int fx = 0;
+  for (int d = 0; d < 3; ++d)
+    if (idx[d] == 0 || idx[d] == N) fx = d;
+  const int a1 = fx == 0 ? 1 : 0, a2 = fx == 2 ? 1 : 2;
+  int v[2][2];
+  for (int c1 = 0; c1 < 2; ++c1)
+    for (int c2 = 0; c2 < 2; ++c2) {
+      int bits[3];
+      bits[fx] = idx[fx] == N;
+      bits[a1] = c1;
+      bits[a2] = c2;
+      v[c1][c2] = cv[corner_of(bits[0], bits[1], bits[2])];
+    }
+  int o1 = 0, o2 = 0;
+  for (int c1 = 0; c1 < 2; ++c1)
+    for (int c2 = 0; c2 < 2; ++c2)
+      if (v[c1][c2] < v[o1][o2]) {
+        o1 = c1;
+        o2 = c2;
+      }
+  const int s1 = o1 ? N - idx[a1] : idx[a1], s2 = o2 ? N - idx[a2] : idx[a2];
+  const int n1v = v[1 - o1][o2], n2v = v[o1][1 - o2];
+  const int64_t org = (int64_t)2 << 60 | v[o1][o2];
+  if (n1v < n2v) return NodeKey{org, (int64_t)n1v << 32 | n2v, (int64_t)s1 << 16 | s2};
+  return NodeKey{org, (int64_t)n2v << 32 | n1v, (int64_t)s2 << 16 | s1};
+}
+
+}  // namespace
+
+sem_status build_mesh_level(const sem_mesh &mesh, int N, BoxLevelHost &L, std::string &err) {
+  L.N = N;
+  L.n1 = N + 1;
+  L.general = true;
+  L.E = mesh.num_elements;
+  const int n1 = N + 1, n3 = n1 * n1 * n1;
+  L.L = L.E * n3;
+  L.gll = make_gll(N);
+  std::vector<double> Bl, dl, Xl;
+  const int bad = element_geometry(
+      L.E, L.gll,
+      [&](int64_t e, double C[2][2][2][3]) {
+        for (int c = 0; c < 8; ++c)
+          for (int d = 0; d < 3; ++d)
+            C[c >> 2][(c >> 1) & 1][c & 1][d] = mesh.vertex_xyz[3 * (int64_t)mesh.elem_vertices[8 * e + c] + d];
+      },
+      L.G, Bl, dl, Xl);
+  if (bad) {
+    err = "mesh has " + std::to_string(bad) + " GLL points with non-positive Jacobian at order " +
+          std::to_string(N);
+    return SEM_EMESH;
+  }
+  // faces: boundary faces belong to one element; Dirichlet faces have every corner flagged
+  std::map<std::array<int32_t, 4>, int> face_count;
+  auto face_vertices = [&](int64_t e, int axis, int side) {
+    std::array<int32_t, 4> f{};
+    int q = 0;
+    for (int c = 0; c < 8; ++c)
+      if (((c >> axis) & 1) == side) f[q++] = mesh.elem_vertices[8 * e + c];
+    std::sort(f.begin(), f.end());
+    return f;
+  };
+  for (int64_t e = 0; e < L.E; ++e)
+    for (int axis = 0; axis < 3; ++axis)
+      for (int side = 0; side < 2; ++side) face_count[face_vertices(e, axis, side)]++;
+  for (auto &kv : face_count)
+    if (kv.second > 2) {
+      err = "a face is shared by more than two elements";
+      return SEM_EINVAL;
+    }
+  std::unordered_map<NodeKey, int64_t, NodeKeyHash> id;  // surface nodes -> global id (-1: Dirichlet)
+  for (int64_t e = 0; e < L.E; ++e) {
+    const int32_t *cv = &mesh.elem_vertices[8 * e];
+    for (int axis = 0; axis < 3; ++axis)
+      for (int side = 0; side < 2; ++side) {
+        const auto f = face_vertices(e, axis, side);
+        if (face_count[f] != 1) continue;
+        bool flagged = true;
+        if (mesh.vertex_dirichlet)
+          for (int32_t v : f) flagged = flagged && mesh.vertex_dirichlet[v] != 0;
+        if (!flagged) continue;
+        for (int s1 = 0; s1 < n1; ++s1)
+          for (int s2 = 0; s2 < n1; ++s2) {
+            int idx[3];
+            idx[axis] = side ? N : 0;
+            idx[axis == 0 ? 1 : 0] = s1;
+            idx[axis == 2 ? 1 : 2] = s2;
+            id[node_key(e, cv, N, idx[0], idx[1], idx[2])] = -1;
+          }
+      }
+  }
+  // numbering: first appearance in (e, k, j, i) order, Dirichlet nodes skipped
+  L.l2g.assign((size_t)L.L, -1);
+  int64_t next = 0;
+  for (int64_t e = 0; e < L.E; ++e) {
+    const int32_t *cv = &mesh.elem_vertices[8 * e];
+    for (int k = 0; k < n1; ++k)
+      for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n1; ++i) {
+          const size_t q = (size_t)e * n3 + (k * n1 + j) * n1 + i;
+          const bool interior = i > 0 && i < N && j > 0 && j < N && k > 0 && k < N;
+          if (interior) {
+            L.l2g[q] = (int32_t)next++;
+            continue;
+          }
+          auto it = id.find(node_key(e, cv, N, i, j, k));
+          if (it == id.end()) it = id.emplace(node_key(e, cv, N, i, j, k), next++).first;
+          L.l2g[q] = (int32_t)it->second;
+        }
+  }
+  if (next == 0) {
+    err = "every node of the mesh is a Dirichlet node";
+    return SEM_EINVAL;
+  }
+  bool any_dirichlet = false;
+  for (auto &kv : id) any_dirichlet = any_dirichlet || kv.second < 0;
+  if (!any_dirichlet) {
+    err = "no Dirichlet face: the operator would be singular";
+    return SEM_EINVAL;
+  }
+  L.n = next;
+  // summation lists (local copies of every unknown in increasing local index), diagonal,
+  // mass and coordinates
+  L.lrow.assign(L.n + 1, 0);
+  for (int32_t g : L.l2g)
+    if (g >= 0) L.lrow[g + 1]++;
+  for (int64_t g = 0; g < L.n; ++g) L.lrow[g + 1] += L.lrow[g];
+  L.lidx.assign(L.lrow[L.n], 0);
+  std::vector<int64_t> pos(L.lrow.begin(), L.lrow.end() - 1);
+  L.diag.assign(L.n, 0.0);
+  L.mass.assign(L.n, 0.0);
+  L.coords.assign((size_t)L.n * 3, 0.0);
+  for (int64_t q = 0; q < L.L; ++q) {
+    const int32_t g = L.l2g[q];
+    if (g < 0) continue;
+    L.lidx[pos[g]++] = (int32_t)q;
+    L.diag[g] += dl[q];
+    L.mass[g] += Bl[q];
+    for (int d = 0; d < 3; ++d) L.coords[3 * (size_t)g + d] = Xl[3 * q + d];
   }
   return SEM_OK;
 }
@@ -245,13 +452,17 @@ Csr assemble_q1(const BoxLevelHost &L) {
             for (int pp = 0; pp < n3; ++pp) Ae[p * n3 + pp] += da * gq * Da[(b * n3 + q) * n3 + pp];
           }
         }
-    const int ex = (int)(e % L.nex), ey = (int)((e / L.nex) % L.ney), ez = (int)(e / ((int64_t)L.nex * L.ney));
     std::vector<int64_t> gid(n3);
-    for (int p = 0; p < n3; ++p) {
-      const int I = ex * L.N + p % n1, J = ey * L.N + (p / n1) % n1, K = ez * L.N + p / (n1 * n1);
-      gid[p] = (I >= 1 && I <= L.nx && J >= 1 && J <= L.ny && K >= 1 && K <= L.nz)
-                   ? (I - 1) + (int64_t)L.nx * ((J - 1) + (int64_t)L.ny * (K - 1))
-                   : -1;
+    if (L.general) {
+      for (int p = 0; p < n3; ++p) gid[p] = L.l2g[(size_t)e * n3 + p];
+    } else {
+      const int ex = (int)(e % L.nex), ey = (int)((e / L.nex) % L.ney), ez = (int)(e / ((int64_t)L.nex * L.ney));
+      for (int p = 0; p < n3; ++p) {
+        const int I = ex * L.N + p % n1, J = ey * L.N + (p / n1) % n1, K = ez * L.N + p / (n1 * n1);
+        gid[p] = (I >= 1 && I <= L.nx && J >= 1 && J <= L.ny && K >= 1 && K <= L.nz)
+                     ? (I - 1) + (int64_t)L.nx * ((J - 1) + (int64_t)L.ny * (K - 1))
+                     : -1;
+      }
     }
     for (int p = 0; p < n3; ++p) {
       if (gid[p] < 0) continue;
@@ -809,9 +1020,181 @@ static const double kBeta[] = {
     1.51427891730346,
 };
 
+// ---- optimised 4th kind beyond the table: beta minimising gamma (eq. gamma-defn)
+// For coefficients beta, the error polynomial of Algorithm 2 is
+//   p(l) = 1 + sum_i beta_i (p_i(l) - p_{i-1}(l)),  p_i(l) = W_i(1 - 2l) / (2i + 1),
+// and gamma = sup_{0 < l <= 1} f(l), f = l p^2 / (1 - p^2). At the optimum f equioscillates:
+// its supremum is reached as l -> 0 (f -> 3 / (8 sum_i i beta_i)), at the k-1 interior
+// maxima of f and at l = 1. This solver locates the interior maxima for the current beta
+// (scan in t with l = sin^2(t/2), then bisection on f'), and applies Newton's method to the
+// k+1 equations "each of the k+1 extreme values equals gamma" in the k+1 unknowns
+// (beta, gamma); at a maximum f' = 0, so the derivative of the extreme value with respect
+// to beta_j is the partial derivative at fixed l: 2 l p (p_j - p_{j-1}) / (1 - p^2)^2.
+namespace {
+
+struct PolyEval {
+  double p, dp;               // p(l), dp/dl
+  std::vector<double> q;      // p_j - p_{j-1}, j = 1..k
+};
+
+PolyEval eval_opt4(const std::vector<double> &beta, double l) {
+  const int k = (int)beta.size();
+  const double x = 1.0 - 2.0 * l;
+  // W_n(x) and W_n'(x) by the 4th-kind recurrence W_n = 2x W_{n-1} - W_{n-2}
+  double w0 = 1.0, w1 = 2.0 * x + 1.0, d0 = 0.0, d1 = 2.0;
+  PolyEval r;
+  r.q.resize(k);
+  double prev = 1.0, dprev = 0.0;  // p_0 and its derivative
+  r.p = 1.0;
+  r.dp = 0.0;
+  for (int n = 1; n <= k; ++n) {
+    double wn, dn;
+    if (n == 1) {
+      wn = w1;
+      dn = d1;
+    } else {
+      wn = 2.0 * x * w1 - w0;
+      dn = 2.0 * w1 + 2.0 * x * d1 - d0;
+      w0 = w1;
+      w1 = wn;
+      d0 = d1;
+      d1 = dn;
+    }
+    const double pn = wn / (2 * n + 1), dpn = -2.0 * dn / (2 * n + 1);
+    r.q[n - 1] = pn - prev;
+    r.p += beta[n - 1] * (pn - prev);
+    r.dp += beta[n - 1] * (dpn - dprev);
+    prev = pn;
+    dprev = dpn;
+  }
+  return r;
+}
+
+double f_of(const PolyEval &e, double l) { return l * e.p * e.p / (1.0 - e.p * e.p); }
+double fprime_of(const PolyEval &e, double l) {
+  const double g = 1.0 - e.p * e.p;
+  return (e.p * e.p + 2.0 * l * e.p * e.dp) / g + l * e.p * e.p * 2.0 * e.p * e.dp / (g * g);
+}
+
+// Gaussian elimination with partial pivoting; false if singular.
+bool solve_dense(std::vector<double> A, std::vector<double> &b, int n) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[(size_t)r * n + c]) > std::fabs(A[(size_t)piv * n + c])) piv = r;
+    if (A[(size_t)piv * n + c] == 0.0) return false;
+    if (piv != c) {
+      for (int q = 0; q < n; ++q) std::swap(A[(size_t)c * n + q], A[(size_t)piv * n + q]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const double m = A[(size_t)r * n + c] / A[(size_t)c * n + c];
+      for (int q = c; q < n; ++q) A[(size_t)r * n + q] -= m * A[(size_t)c * n + q];
+      b[r] -= m * b[c];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    double sacc = b[r];
+    for (int q = r + 1; q < n; ++q) sacc -= A[(size_t)r * n + q] * b[q];
+    b[r] = sacc / A[(size_t)r * n + r];
+  }
+  return true;
+}
+
+// Interior local maxima of f for the current beta (as many as found).
+std::vector<double> interior_maxima(const std::vector<double> &beta) {
+  constexpr int kScan = 20000;
+  const double pi = 3.14159265358979323846;
+  std::vector<double> out;
+  auto lam = [&](int i) { const double t = pi * i / kScan; const double s = std::sin(0.5 * t); return s * s; };
+  double lprev = lam(1), fp_prev = fprime_of(eval_opt4(beta, lprev), lprev);
+  for (int i = 2; i < kScan; ++i) {
+    const double l = lam(i), fp = fprime_of(eval_opt4(beta, l), l);
+    if (fp_prev > 0.0 && fp <= 0.0) {  // f' changes sign from + to -: a maximum
+      double a = lprev, b = l;
+      for (int it = 0; it < 200 && b - a > 1e-17; ++it) {
+        const double m = 0.5 * (a + b);
+        if (fprime_of(eval_opt4(beta, m), m) > 0.0) a = m;
+        else b = m;
+      }
+      out.push_back(0.5 * (a + b));
+    }
+    lprev = l;
+    fp_prev = fp;
+  }
+  return out;
+}
+
+// Coefficients for k = 1..kmax by continuation in k; rows[k-1] holds beta^{(k)}.
+std::vector<std::vector<double>> minimax_rows(int kmax) {
+  std::vector<std::vector<double>> rows;
+  std::vector<double> beta{1.0};
+  for (int k = 1; k <= kmax; ++k) {
+    if (k > 1) {  // spread beta^{(k-1)} over k indices (linear interpolation in (i - 1/2) / k)
+      std::vector<double> nb(k);
+      for (int i = 0; i < k; ++i) {
+        const double t = (i + 0.5) / k * (k - 1) - 0.5;  // position on the old index axis
+        const int i0 = std::max(0, std::min(k - 2, (int)std::floor(t)));
+        const double w = std::max(0.0, std::min(1.0, t - i0));
+        nb[i] = k - 1 == 1 ? beta[0] : beta[i0] * (1.0 - w) + beta[std::min(i0 + 1, k - 2)] * w;
+      }
+      beta = nb;
+    }
+    double gam = f_of(eval_opt4(beta, 1.0), 1.0);
+    for (int it = 0; it < 50; ++it) {
+      const std::vector<double> lm = interior_maxima(beta);
+      if ((int)lm.size() != k - 1) break;  // leave the last good iterate
+      const int n = k + 1;
+      std::vector<double> J((size_t)n * n, 0.0), F(n, 0.0);
+      std::vector<double> pts(lm);
+      pts.push_back(1.0);
+      for (int r = 0; r < k; ++r) {  // interior maxima and l = 1
+        const double l = pts[r];
+        const PolyEval e = eval_opt4(beta, l);
+        const double g = 1.0 - e.p * e.p;
+        F[r] = f_of(e, l) - gam;
+        for (int j = 0; j < k; ++j) J[(size_t)r * n + j] = 2.0 * l * e.p * e.q[j] / (g * g);
+        J[(size_t)r * n + k] = -1.0;
+      }
+      double S = 0.0;  // l -> 0
+      for (int j = 0; j < k; ++j) S += (j + 1) * beta[j];
+      F[k] = 3.0 / (8.0 * S) - gam;
+      for (int j = 0; j < k; ++j) J[(size_t)k * n + j] = -3.0 * (j + 1) / (8.0 * S * S);
+      J[(size_t)k * n + k] = -1.0;
+      for (double &v : F) v = -v;
+      if (!solve_dense(J, F, n)) break;
+      double dmax = 0.0;
+      for (int j = 0; j < k; ++j) {
+        beta[j] += F[j];
+        dmax = std::max(dmax, std::fabs(F[j]));
+      }
+      gam += F[k];
+      if (dmax < 1e-15) break;
+    }
+    // accept the row only if its k+1 extreme values agree (the minimax property)
+    const std::vector<double> lm = interior_maxima(beta);
+    bool ok = (int)lm.size() == k - 1;
+    double S = 0.0;
+    for (int j = 0; j < k; ++j) S += (j + 1) * beta[j];
+    const double g1 = f_of(eval_opt4(beta, 1.0), 1.0);
+    ok = ok && std::fabs(3.0 / (8.0 * S) - g1) <= 1e-11 * g1;
+    for (double l : lm) ok = ok && std::fabs(f_of(eval_opt4(beta, l), l) - g1) <= 1e-11 * g1;
+    rows.push_back(ok ? beta : std::vector<double>());
+    if (!ok) break;  // no start for the next order
+  }
+  while ((int)rows.size() < kmax) rows.emplace_back();
+  return rows;
+}
+
+}  // namespace
+
 const double *beta_row(int k) {
-  if (k < 1 || k > 16) return nullptr;
-  return &kBeta[(k - 1) * k / 2];
+  if (k < 1 || k > kMaxOptOrder) return nullptr;
+  if (k <= 16) return &kBeta[(k - 1) * k / 2];  // Table beta_coef as printed
+  static std::vector<std::vector<double>> rows;
+  static std::once_flag once;
+  std::call_once(once, [] { rows = minimax_rows(kMaxOptOrder); });
+  return rows[k - 1].empty() ? nullptr : rows[k - 1].data();
 }
 
 }  // namespace semcheb

@@ -19,7 +19,10 @@ struct Gll {
 Gll make_gll(int N);
 // J[i*(Nc+1)+a] = l_a^{(Nc)}(x_i^{(Nf)})
 std::vector<double> make_interp(const Gll &fine, const Gll &coarse);
-// Table beta_coef of the supplementary material, k = 1..16
+// beta_i^{(k)} of the optimised 4th-kind smoother: Table beta_coef of the supplementary
+// material for k = 1..16 as printed, computed by minimising eq. gamma-defn for
+// 16 < k <= kMaxOptOrder (nullptr beyond)
+constexpr int kMaxOptOrder = 32;
 const double *beta_row(int k);
 
 // Structured box geometry of one order (SEM level), built on the host.
@@ -33,9 +36,21 @@ struct BoxLevelHost {
   std::vector<double> diag;    // [n]
   std::vector<double> mass;    // [n]
   std::vector<double> coords;  // [n][3]
+  // unstructured meshes (general = true; the box fields above are unused): local-to-global
+  // map (-1 on Dirichlet nodes) and the summation lists, the local copies of unknown g being
+  // lidx[lrow[g] .. lrow[g+1]) in increasing order
+  bool general = false;
+  std::vector<int32_t> l2g;
+  std::vector<int64_t> lrow;
+  std::vector<int32_t> lidx;
 };
 // Returns SEM_EMESH on a non-positive Jacobian.
 sem_status build_box_level(const sem_box_mesh &mesh, int N, BoxLevelHost &out, std::string &err);
+// Unstructured conforming hexahedral mesh: geometry, node numbering (first appearance over
+// (e, k, j, i), nodes identified by the vertices of the edge or face they lie on) and
+// Dirichlet nodes (boundary faces with all corners flagged). SEM_EMESH on a non-positive
+// Jacobian, SEM_EINVAL on a face of more than two elements or without Dirichlet nodes.
+sem_status build_mesh_level(const sem_mesh &mesh, int N, BoxLevelHost &out, std::string &err);
 std::vector<double> trilinear_edges(const sem_box_mesh &mesh);
 // Assembled order-1 operator in CSR (rows = n).
 struct Csr {
@@ -98,7 +113,10 @@ void set_global_error(const std::string &msg);
 double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &b);
 
 // ---------------------------------------------------------------- device level data
-enum LevelType { LVL_SEM = 0, LVL_FD = 1 };
+// LVL_SEM: box lattice (index-free); LVL_FD: CSR operator; LVL_GEN: unstructured SEM mesh
+// (element operator through a local-to-global map, summation over per-unknown copy lists;
+// its operator results and transfers are global vectors, like those of LVL_FD)
+enum LevelType { LVL_SEM = 0, LVL_FD = 1, LVL_GEN = 2 };
 
 struct DevCsr {
   int64_t nrows = 0;
@@ -129,6 +147,13 @@ struct Level {
   double *coords = nullptr;   // [n][3] (finest level)
   // FD
   DevCsr A, P, R;             // A_j; P: level j+1 -> j (rows n); R = P^T (rows n_{j+1})
+  // unstructured mesh: local-to-global map (E (N+1)^3, -1 Dirichlet), copy lists of every
+  // unknown, 1 / (number of copies), element-local work arrays
+  int32_t *map = nullptr;
+  int64_t *lrow = nullptr;
+  int32_t *lidx = nullptr;
+  double *winv64 = nullptr, *wl64 = nullptr;
+  float *winv32 = nullptr, *wl32 = nullptr;
   // both
   double *invdiag64 = nullptr;
   float *invdiag32 = nullptr;

@@ -37,6 +37,17 @@ constexpr int kReduceBlocks = 1024;  // fixed grid of the reduction kernels (det
 
 bool launch_ax(const Level &L, const double *u, double *wL, hipStream_t s);
 bool launch_ax(const Level &L, const float *u, float *wL, hipStream_t s);
+// unstructured meshes (LVL_GEN): operator with the input gathered through L.map, summation
+// over the local copies (optionally scaled per unknown, optionally added to out), gather of
+// a global vector to element-local copies, element-local interpolation (J: no x ni)
+bool launch_ax_map(const Level &L, const double *u, double *wL, hipStream_t s);
+bool launch_ax_map(const Level &L, const float *u, float *wL, hipStream_t s);
+template <typename T, typename TO>
+void launch_sum_lists(const Level &L, const T *wL, TO *out, const T *scale, bool add, hipStream_t s);
+template <typename T>
+void launch_gather_map(const Level &L, const T *u, const T *scale, T *uL, hipStream_t s);
+template <typename T>
+void launch_interp_elem(int64_t E, int ni, int no, const T *J, const T *in, T *out, bool transpose, hipStream_t s);
 template <typename T>
 void launch_dss(const Level &L, const T *wL, T *out, hipStream_t s);
 // out = DSS(wL) and per-block partials of p . out; returns the number of partials written

@@ -44,6 +44,92 @@ ax_tri_kernel(Box b, int64_t E, const T *__restrict__ u, const T *__restrict__ t
   else ax_body_tri<N, T>(xcd_block(blockIdx.x, gridDim.x), b, E, u, tri, gxw, Dm, wL);
 }
 
+// Operator on an unstructured mesh: the register-column body with the input gathered
+// through the local-to-global map (the box lattice fields of b are unused).
+template <int N, typename T, typename GT>
+__global__ void __launch_bounds__(AxShape<N>::block, 1)
+ax_map_kernel(Box b, int64_t E, const int32_t *__restrict__ map, const T *__restrict__ u,
+              const GT *__restrict__ G, const T *__restrict__ Dm, T *__restrict__ wL) {
+  ax_body<N, T, GT, 1, true>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL, map);
+}
+
+// ------------------------------------------------------------------ unstructured meshes
+// out[g] = (add ? out[g] : 0) + scale[g] * sum of the local copies wL[idx[rowptr[g] ..
+// rowptr[g+1])] (scale optional), summed in increasing local index: the fixed-order
+// direct-stiffness summation of a mesh without lattice structure.
+template <typename T, typename TO>
+__global__ void __launch_bounds__(256)
+sum_lists_kernel(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ idx,
+                 const T *__restrict__ wL, TO *__restrict__ out, const T *__restrict__ scale, int add) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  T acc = T(0);
+  for (int64_t p = rowptr[g]; p < rowptr[g + 1]; ++p) acc += wL[idx[p]];
+  if (scale) acc *= scale[g];
+  out[g] = add ? (TO)(out[g] + (TO)acc) : (TO)acc;
+}
+
+// uL[l] = u[map[l]] * (scale ? scale[map[l]] : 1), 0 on Dirichlet nodes (map -1).
+template <typename T>
+__global__ void __launch_bounds__(256)
+gather_map_kernel(int64_t L, const int32_t *__restrict__ map, const T *__restrict__ u,
+                  const T *__restrict__ scale, T *__restrict__ uL) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= L) return;
+  const int32_t g = map[l];
+  T v = T(0);
+  if (g >= 0) v = scale ? u[g] * scale[g] : u[g];
+  uL[l] = v;
+}
+
+// Element-local tensor-product interpolation (one block per element): out = (J x J x J) in
+// with J of size no x ni (row-major, J[o * ni + a]), or with transpose, out = (J^T x J^T x
+// J^T) in where in has no^3 and out ni^3 values. Three one-dimensional contractions through
+// shared memory; sizes are at most 13.
+template <typename T>
+__global__ void __launch_bounds__(256)
+interp_elem_kernel(int64_t E, int ni, int no, const T *__restrict__ J, const T *__restrict__ in,
+                   T *__restrict__ out, int transpose) {
+  extern __shared__ unsigned char smem_raw[];
+  T *sm = reinterpret_cast<T *>(smem_raw);
+  const int64_t e = blockIdx.x;
+  if (e >= E) return;
+  // source size a, target size c per axis, and the 1D matrix M[c][a]
+  const int a = transpose ? no : ni, c = transpose ? ni : no;
+  T *sJ = sm;                      // c x a
+  T *s0 = sJ + c * a;              // a^3 input
+  T *s1 = s0 + a * a * a;          // [k][j][x] after the i contraction: a * a * c
+  T *s2 = s1 + a * a * c;          // [k][y][x]: a * c * c
+  for (int q = threadIdx.x; q < c * a; q += blockDim.x) {
+    const int r = q / a, t = q % a;
+    sJ[q] = transpose ? J[t * ni + r] : J[r * ni + t];
+  }
+  const T *ie = in + e * (int64_t)a * a * a;
+  for (int q = threadIdx.x; q < a * a * a; q += blockDim.x) s0[q] = ie[q];
+  __syncthreads();
+  for (int q = threadIdx.x; q < a * a * c; q += blockDim.x) {  // along i
+    const int x = q % c, jk = q / c;
+    T acc = T(0);
+    for (int t = 0; t < a; ++t) acc += sJ[x * a + t] * s0[jk * a + t];
+    s1[q] = acc;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < a * c * c; q += blockDim.x) {  // along j
+    const int x = q % c, y = (q / c) % c, k = q / (c * c);
+    T acc = T(0);
+    for (int t = 0; t < a; ++t) acc += sJ[y * a + t] * s1[(k * a + t) * c + x];
+    s2[q] = acc;
+  }
+  __syncthreads();
+  T *oe = out + e * (int64_t)c * c * c;
+  for (int q = threadIdx.x; q < c * c * c; q += blockDim.x) {  // along k
+    const int xy = q % (c * c), z = q / (c * c);
+    T acc = T(0);
+    for (int t = 0; t < a; ++t) acc += sJ[z * a + t] * s2[t * c * c + xy];
+    oe[q] = acc;
+  }
+}
+
 // ------------------------------------------------------------------ summation / vector kernels
 template <typename T, typename TO = T>
 __global__ void dss_kernel(Box b, int64_t n, const T *__restrict__ wL, TO *__restrict__ out) {
@@ -1409,6 +1495,65 @@ bool launch_ax(const Level &L, const float *u, float *wL, hipStream_t s) {
   if (L.tri32) return launch_ax_tri<float>(L, u, L.tri32, L.gxw32, L.D32, wL, s);
   return launch_ax_t<float, uint16_t>(L, u, L.Gbf, L.D32, wL, s);
 }
+
+template <int N, typename T, typename GT>
+void launch_ax_map_n(const Level &L, const T *u, const GT *G, const T *D, T *wL, hipStream_t s) {
+  using S = AxShape<N>;
+  const unsigned grid = (unsigned)((L.E + S::epb - 1) / S::epb);
+  const Box b{N, 1, 1, 1, 1, 1, 1, make_fastdiv(N)};
+  hipLaunchKernelGGL((ax_map_kernel<N, T, GT>), dim3(grid), dim3(S::block), 0, s, b, L.E, L.map, u, G, D, wL);
+}
+
+template <typename T, typename GT>
+bool launch_ax_map_t(const Level &L, const T *u, const GT *G, const T *D, T *wL, hipStream_t s) {
+  switch (L.N) {
+#define SEMCHEB_AXM_CASE(n) \
+  case n: launch_ax_map_n<n, T, GT>(L, u, G, D, wL, s); return true;
+    SEMCHEB_AXM_CASE(1) SEMCHEB_AXM_CASE(2) SEMCHEB_AXM_CASE(3) SEMCHEB_AXM_CASE(4)
+    SEMCHEB_AXM_CASE(5) SEMCHEB_AXM_CASE(6) SEMCHEB_AXM_CASE(7) SEMCHEB_AXM_CASE(8)
+    SEMCHEB_AXM_CASE(9) SEMCHEB_AXM_CASE(10) SEMCHEB_AXM_CASE(11) SEMCHEB_AXM_CASE(12)
+#undef SEMCHEB_AXM_CASE
+    default: return false;
+  }
+}
+
+bool launch_ax_map(const Level &L, const double *u, double *wL, hipStream_t s) {
+  return launch_ax_map_t<double, double>(L, u, L.G64, L.D64, wL, s);
+}
+bool launch_ax_map(const Level &L, const float *u, float *wL, hipStream_t s) {
+  return launch_ax_map_t<float, uint16_t>(L, u, L.Gbf, L.D32, wL, s);
+}
+
+template <typename T, typename TO>
+void launch_sum_lists(const Level &L, const T *wL, TO *out, const T *scale, bool add, hipStream_t s) {
+  hipLaunchKernelGGL((sum_lists_kernel<T, TO>), dim3(nblk(L.n)), dim3(256), 0, s, L.n, L.lrow, L.lidx, wL, out,
+                     scale, add ? 1 : 0);
+}
+template void launch_sum_lists<double, double>(const Level &, const double *, double *, const double *, bool,
+                                               hipStream_t);
+template void launch_sum_lists<float, float>(const Level &, const float *, float *, const float *, bool,
+                                             hipStream_t);
+template void launch_sum_lists<float, double>(const Level &, const float *, double *, const float *, bool,
+                                              hipStream_t);
+
+template <typename T>
+void launch_gather_map(const Level &L, const T *u, const T *scale, T *uL, hipStream_t s) {
+  hipLaunchKernelGGL((gather_map_kernel<T>), dim3(nblk(L.L)), dim3(256), 0, s, L.L, L.map, u, scale, uL);
+}
+template void launch_gather_map<double>(const Level &, const double *, const double *, double *, hipStream_t);
+template void launch_gather_map<float>(const Level &, const float *, const float *, float *, hipStream_t);
+
+template <typename T>
+void launch_interp_elem(int64_t E, int ni, int no, const T *J, const T *in, T *out, bool transpose, hipStream_t s) {
+  const int a = transpose ? no : ni, c = transpose ? ni : no;
+  const size_t lds = sizeof(T) * (size_t)(c * a + a * a * a + a * a * c + a * c * c);
+  hipLaunchKernelGGL((interp_elem_kernel<T>), dim3((unsigned)E), dim3(256), lds, s, E, ni, no, J, in, out,
+                     transpose ? 1 : 0);
+}
+template void launch_interp_elem<double>(int64_t, int, int, const double *, const double *, double *, bool,
+                                         hipStream_t);
+template void launch_interp_elem<float>(int64_t, int, int, const float *, const float *, float *, bool,
+                                        hipStream_t);
 
 template <typename T>
 void launch_dss(const Level &L, const T *wL, T *out, hipStream_t s) {

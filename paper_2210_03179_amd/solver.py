@@ -248,6 +248,39 @@ class SemSolver(_Base):
         return dG, df
 
 
+class MeshSolver(SemSolver):
+    """The same solver on an unstructured conforming hexahedral mesh (sem_setup).
+
+    vertex_xyz: (num_vertices, 3); elem_vertices: (E, 8) corner vertices per element in
+    lexicographic reference order (corner ci + 2 cj + 4 ck at (2ci-1, 2cj-1, 2ck-1));
+    vertex_dirichlet: (num_vertices,) flags, or None for a Dirichlet condition on the whole
+    boundary. Unknowns are numbered by first appearance over the element-local nodes."""
+
+    def __init__(self, vertex_xyz, elem_vertices, N=7, vertex_dirichlet=None, smoother="cheb4opt", pre=4, post=0,
+                 precision="fp64", krylov="fcg", orders=None, lambda_max=None, lambda_scale=1.0, device=0,
+                 restart=30):
+        _Base.__init__(self)
+        xyz = np.ascontiguousarray(np.asarray(vertex_xyz, dtype=np.float64))
+        ev = np.ascontiguousarray(np.asarray(elem_vertices, dtype=np.int32))
+        if xyz.ndim != 2 or xyz.shape[1] != 3 or ev.ndim != 2 or ev.shape[1] != 8:
+            raise ValueError("vertex_xyz must be (num_vertices, 3) and elem_vertices (E, 8)")
+        flags = None if vertex_dirichlet is None else np.ascontiguousarray(np.asarray(vertex_dirichlet, np.uint8))
+        if flags is not None and flags.shape != (xyz.shape[0],):
+            raise ValueError("vertex_dirichlet needs one flag per vertex")
+        self._arrays = (xyz, ev, flags)
+        mesh = L.SemMesh(ev.shape[0], xyz.shape[0], xyz.ctypes.data_as(C.POINTER(C.c_double)),
+                         ev.ctypes.data_as(C.POINTER(C.c_int32)),
+                         flags.ctypes.data_as(C.POINTER(C.c_uint8)) if flags is not None else None)
+        opt = L.make_options(N, smoother, pre, post, precision, krylov, orders, lambda_max, lambda_scale, device,
+                             0, restart)
+        ctx = C.c_void_p()
+        stream = _stream() if device >= 0 else C.c_void_p(0)
+        L.check(self._lib.sem_setup(C.byref(mesh), C.byref(opt), stream, C.byref(ctx)))
+        self._ctx = ctx
+        self.N = N
+        self.E = ev.shape[0]
+
+
 class FdSolver(_Base):
     """2D finite-difference Poisson with Galerkin geometric multigrid (the paper's Sec. 3 problem).
 

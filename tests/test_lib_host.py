@@ -37,7 +37,17 @@ def test_beta_table_matches_golden():
     for k, vals in rows.items():
         assert beta_table(k) == vals
     lib = L.load()
-    assert lib.sem_beta_table(17, (C.c_double * 17)()) == L.SEM_EINVAL
+    assert lib.sem_beta_table(33, (C.c_double * 33)()) == L.SEM_EINVAL
+    assert lib.sem_beta_table(0, (C.c_double * 1)()) == L.SEM_EINVAL
+
+
+def test_computed_beta_rows_match_the_oracle():
+    """Orders 17..32: the library's own minimax solver (maxima located by bisection, Newton
+    on the extreme values) and the oracle's (maxima as unknowns of one Newton system) agree."""
+    from oracle import chebyshev as cheb
+    ref = cheb.minimax_betas(32)
+    for k in range(17, 33):
+        assert np.max(np.abs(np.array(beta_table(k)) - np.array(ref[k]))) < 1e-12, k
 
 
 @pytest.fixture(scope="module")
@@ -97,7 +107,7 @@ def test_fd_host_hierarchy_matches_oracle():
 def test_error_codes():
     V = wl.deformed_box(3, 0.05)
     with pytest.raises(L.SemError) as e:
-        SemSolver(V, N=5, smoother="cheb4opt", pre=17, device=-1)
+        SemSolver(V, N=5, smoother="cheb4opt", pre=33, device=-1)
     assert e.value.status == L.SEM_EINVAL
     with pytest.raises(L.SemError) as e:
         SemSolver(V, N=13, device=-1)
@@ -167,7 +177,8 @@ def test_fd_sparse_host_arrays_match_oracle():
 def test_set_smoothing_validation_and_mg_option():
     s = FdSolver(n=16, factor=2, coarsest_n=2, device=-1, lambda_max=[1, 1, 1], krylov="mg")
     s.set_smoothing("cheb1opt", 3, 3)
-    for args in (("cheb4opt", 17, 0), ("cheb4", 0, 0), (9, 1, 1)):
+    s.set_smoothing("cheb4opt", 20, 0)   # beyond the printed table: computed coefficients
+    for args in (("cheb4opt", 33, 0), ("cheb4", 0, 0), (9, 1, 1)):
         with pytest.raises(L.SemError) as ex:
             s.set_smoothing(*args)
         assert ex.value.status == L.SEM_EINVAL
@@ -231,3 +242,45 @@ def test_lattice_multigrid_host_hierarchy_matches_oracle():
     with pytest.raises(L.SemError) as ex:
         SemSolver(V, N=3, device=-1, lambda_max=[2.0] * 3, coarse="lattice", schwarz="ras")
     assert ex.value.status == L.SEM_EINVAL
+
+
+@pytest.mark.parametrize("faces", [None, ("x0",), ("x0", "y1", "z0")])
+def test_mesh_host_setup_matches_oracle(faces):
+    """sem_setup on an unstructured mesh (a box with shuffled, rotated elements and renumbered
+    vertices): the library numbers nodes by the vertices of their edge or face, the oracle by
+    position; both number the unknowns by first appearance, so the host arrays must agree
+    entry by entry: coordinates, diagonal, mass, factors and the order-1 matrix."""
+    from oracle.mesh import SemMesh as OracleMesh
+    from paper_2210_03179_amd.solver import MeshSolver
+    V = wl.deformed_box((3, 2, 2), 0.06)
+    xyz, ev = wl.box_as_mesh(V)
+    xyz, ev, _ = wl.shuffled_mesh(xyz, ev, 7)
+    flags = None if faces is None else wl.face_flags(xyz, faces)
+    s = MeshSolver(xyz, ev, N=4, vertex_dirichlet=flags, device=-1, lambda_max=[2.0, 2.0])
+    assert s.num_levels == 3
+    for j, N in enumerate([4, 2, 1]):
+        ref = OracleMesh(xyz, ev, N, flags)
+        assert s.level_info(j)[1] == ref.n
+        assert np.max(np.abs(s.host_array("coords", j).reshape(-1, 3) - ref.coords())) < 1e-15
+        assert np.max(np.abs(s.host_array("diag", j) - ref.diag())) < 1e-13 * np.max(ref.diag())
+        assert np.max(np.abs(s.host_array("mass", j) - ref.mass())) < 1e-15
+        G = s.host_array("factors", j).reshape(ref.G.shape)
+        assert np.max(np.abs(G - ref.G)) < 1e-14 * np.max(np.abs(ref.G))
+    A1 = OracleMesh(xyz, ev, 1, flags).assemble().toarray()
+    Ah = s.host_array("coarse_matrix").reshape(A1.shape)
+    assert np.max(np.abs(Ah - A1)) < 1e-14 * np.max(np.abs(A1))
+
+
+def test_mesh_setup_validation():
+    from paper_2210_03179_amd.solver import MeshSolver
+    xyz, ev = wl.box_as_mesh(wl.deformed_box(2, 0.05))
+    for bad_ev, flags in ((np.where(ev == 5, 999, ev), None),             # vertex index out of range
+                          (ev, np.zeros(len(xyz), np.uint8))):           # no Dirichlet face
+        with pytest.raises(L.SemError) as ex:
+            MeshSolver(xyz, bad_ev, N=2, vertex_dirichlet=flags, device=-1, lambda_max=[2.0])
+        assert ex.value.status == L.SEM_EINVAL
+    inverted = ev.copy()
+    inverted[0, [0, 1]] = inverted[0, [1, 0]]                           # mirrored element
+    with pytest.raises(L.SemError) as ex:
+        MeshSolver(xyz, inverted, N=2, device=-1, lambda_max=[2.0])
+    assert ex.value.status == L.SEM_EMESH

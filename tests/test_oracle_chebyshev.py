@@ -52,8 +52,8 @@ def p1(k, lam, lmin):
     return T(k, (theta - lam) / delta) / T(k, np.array([theta / delta]))[0]
 
 
-def p4opt(k, lam):
-    beta = cheb.BETA[k]
+def p4opt(k, lam, beta=None):
+    beta = cheb.betas(cheb.CHEB4_OPT, k) if beta is None else beta
     out = np.ones_like(lam)
     prev = np.ones_like(lam)
     for i in range(1, k + 1):
@@ -93,7 +93,7 @@ def fd_eig():
 
 
 @pytest.mark.parametrize("kind", cheb.KINDS)
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 8])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 8, 20])
 def test_smoother_closed_form_on_eigenvectors(fd_eig, kind, k):
     A, Sinv, lmax, modes = fd_eig
     for v, lam in modes:
@@ -198,3 +198,49 @@ def test_critical_C_closed_forms(k):
     printed = (2 * (6 * (2 * k + 1) ** 2 - np.pi ** 2) ** 2
                / (3 * np.pi ** 2 * (-12 * (2 * k + 1) ** 2 + 6 * (4 * k + 1) ** 2 + np.pi ** 2)))
     assert abs(an.critical_C(g(k), g(2 * k)) - printed) < 1e-12 * printed
+
+
+# ---- optimised 4th kind beyond the printed table: beta minimising eq. gamma-defn
+@pytest.fixture(scope="module")
+def computed_betas():
+    return cheb.minimax_betas(cheb.MAX_OPT_ORDER)
+
+
+def test_minimax_betas_reproduce_the_printed_table(computed_betas):
+    """The optimisation, run from beta^{(1)} by continuation and knowing nothing of the
+    table, lands on every printed coefficient of Table beta_coef (k = 1..16, 15 digits)."""
+    rows = {}
+    for line in open(GOLDEN):
+        if line.strip() and not line.startswith("#"):
+            k, i, v = line.split()
+            rows.setdefault(int(k), []).append(float(v))
+    for k, vals in rows.items():
+        assert np.max(np.abs(np.array(computed_betas[k]) - np.array(vals))) < 1e-12, k
+
+
+@pytest.mark.parametrize("k", [17, 18, 20, 24, 32])
+def test_computed_betas_equioscillate(computed_betas, k):
+    """For k > 16: lam p^2 / (1 - p^2), p evaluated with the trigonometric closed form of
+    W_k, reaches the same maximum at lam -> 0, at k-1 interior points and at lam = 1 (the
+    minimax characterisation), and that gamma^{-1} lies above the plain 4th kind's
+    (4/3) k (k+1) and within 0.1 % of the approximation eq. gamma-opt-4th-kind."""
+    beta = computed_betas[k]
+    lam = np.linspace(1e-8, 1.0, 200001)
+    p = p4opt(k, lam, beta)
+    f = lam * p ** 2 / (1 - p ** 2)
+    inner = np.nonzero((f[1:-1] >= f[:-2]) & (f[1:-1] >= f[2:]))[0] + 1
+    assert len(inner) == k - 1
+    gam = f[-1]
+    # refine each interior maximum on a local grid; the grid maximum sits below the true one
+    for i in inner:
+        loc = np.linspace(lam[i - 1], lam[i + 1], 2001)
+        pl = p4opt(k, loc, beta)
+        fl = np.max(loc * pl ** 2 / (1 - pl ** 2))
+        assert abs(fl - gam) <= 1e-9 * gam
+    f0 = 3.0 / (8.0 * sum(i * b for i, b in enumerate(beta, start=1)))
+    assert abs(f0 - gam) <= 1e-12 * gam       # f -> 3 / (8 sum_i i beta_i) as lam -> 0
+    ginv = 1.0 / gam
+    assert ginv > 4.0 / 3.0 * k * (k + 1)
+    approx = 4.0 / np.pi ** 2 * (2 * k + 1) ** 2 - 2.0 / 3.0
+    assert abs(ginv - approx) <= 1e-3 * ginv
+    assert cheb.betas(cheb.CHEB4_OPT, k) == beta

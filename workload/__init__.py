@@ -18,4 +18,7 @@ from .gen import (  # noqa: F401
     target_coeffs,
     gaussian_directions,
     BoxSpec,
+    box_as_mesh,
+    shuffled_mesh,
+    face_flags,
 )

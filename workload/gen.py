@@ -134,3 +134,63 @@ def gaussian_directions(count: int, sizes: tuple, seed: int = 1):
         nrm = np.sqrt(sum(float(np.dot(p, p)) for p in parts))
         out.append([p / nrm for p in parts])
     return out
+
+
+# ---- unstructured (element list) form of a box mesh
+def _rotations():
+    """The 24 proper rotations of the cube as signed 3x3 permutation matrices."""
+    out = []
+    for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        for signs in np.ndindex(2, 2, 2):
+            R = np.zeros((3, 3), dtype=int)
+            for r in range(3):
+                R[r, perm[r]] = 1 - 2 * signs[r]
+            if round(np.linalg.det(R)) == 1:
+                out.append(R)
+    return out
+
+
+def box_as_mesh(V: np.ndarray):
+    """(vertex_xyz (nv, 3), elem_vertices (E, 8)) of a box given as (mz+1, my+1, mx+1, 3)
+    vertices: vertex (i, j, k) -> i + (mx+1)(j + (my+1) k); elements x fastest; corner
+    ci + 2 cj + 4 ck of element (ex, ey, ez) is vertex (ex+ci, ey+cj, ez+ck)."""
+    mz, my, mx = (s - 1 for s in V.shape[:3])
+    xyz = V.reshape(-1, 3).copy()
+    ev = []
+    for ez in range(mz):
+        for ey in range(my):
+            for ex in range(mx):
+                ev.append([(ex + ci) + (mx + 1) * ((ey + cj) + (my + 1) * (ez + ck))
+                           for ck in (0, 1) for cj in (0, 1) for ci in (0, 1)])
+    return xyz, np.array(ev, dtype=np.int64)
+
+
+def shuffled_mesh(xyz: np.ndarray, ev: np.ndarray, seed: int):
+    """The same mesh with its elements in random order, every element's reference frame
+    turned by a random proper rotation of the cube (its corner list reordered to match)
+    and its vertices renumbered at random. Returns (xyz, ev, vertex_perm) with
+    vertex_perm[old] = new index."""
+    g = _rng(seed)
+    rots = _rotations()
+    nv = len(xyz)
+    vperm = g.permutation(nv)
+    new_xyz = np.empty_like(xyz)
+    new_xyz[vperm] = xyz
+    out = np.empty_like(ev)
+    for q, e in enumerate(g.permutation(len(ev))):
+        R = rots[int(g.integers(len(rots)))]
+        for c in range(8):
+            ref = np.array([2 * (c & 1) - 1, 2 * ((c >> 1) & 1) - 1, 2 * ((c >> 2) & 1) - 1])
+            rc = R @ ref                                   # the corner's new reference position
+            cn = ((rc[0] + 1) // 2) + 2 * ((rc[1] + 1) // 2) + 4 * ((rc[2] + 1) // 2)
+            out[q, cn] = vperm[ev[e, c]]
+    return new_xyz, out, vperm
+
+
+def face_flags(xyz: np.ndarray, faces) -> np.ndarray:
+    """Vertex flags of the unit-box faces named in `faces` ("x0", "x1", "y0", ...)."""
+    out = np.zeros(len(xyz), dtype=np.uint8)
+    for f in faces:
+        d, side = "xyz".index(f[0]), float(f[1])
+        out |= np.isclose(xyz[:, d], side, atol=1e-12).astype(np.uint8)
+    return out
