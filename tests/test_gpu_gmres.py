@@ -51,25 +51,35 @@ def test_sem_gmres_parity(kind, pre, post, restart):
     assert s.apply_counts()[0] == info.iterations * (pre + post + 1) + restarts
 
 
-def test_fd_table_case_gmres20():
-    # Sec. 3, Table fastest_solver_fd, L_x = 8, coarsening 2, 4th kind (14,0): printed 5 iterations
-    n, Lx, f, pre, post = 128, 8.0, 2, 14, 0
-    As, _, _ = fd2d.hierarchy_matrices(n, f, Lx, 1.0, 2)
+FD_ROWS = [(1, 2, "cheb4", 2, 2), (8, 2, "cheb4", 14, 0), (64, 2, "cheb4opt", 20, 0), (128, 2, "cheb4opt", 20, 0),
+           (1, 8, "cheb4", 7, 7), (8, 8, "cheb4opt", 14, 0), (64, 8, "cheb4opt", 18, 0),
+           (128, 8, "cheb4opt", 20, 0)]
+
+
+@pytest.mark.parametrize("Lx,f,kind,pre,post", FD_ROWS)
+def test_fd_table_rows_gmres20(Lx, f, kind, pre, post):
+    """Every row of Sec. 3's Table fastest_solver_fd on the GPU (n = 128, GMRES(20), 1e-6):
+    identical iterations and recurrences with the oracle, and fine-grid mat-vecs equal to
+    iterations x (m + n + 1); the printed counts themselves are compared on the oracle
+    (test_oracle_gmres)."""
+    print(f"FD table row Lx={Lx} f={f} {kind} ({pre},{post})", flush=True)
+    n = 128
+    As, _, _ = fd2d.hierarchy_matrices(n, f, float(Lx), 1.0, 2)
     lmax = [1.0 + np.cos(np.pi / n)] + [lambda_max_SA(lambda x, A=A: A @ x, 1.0 / A.diagonal(), A.shape[0])
                                          for A in As[1:-1]]
-    h = fd2d.fd_hierarchy(n, f, cheb.CHEB4, pre, post, Lx=Lx, Ly=1.0, coarsest_n=2, lmax=lmax)
+    h = fd2d.fd_hierarchy(n, f, kind, pre, post, Lx=float(Lx), Ly=1.0, coarsest_n=2, lmax=lmax)
     A = h.extra["As"][0]
     X, Y = np.meshgrid(np.arange(1, n) / n * Lx, np.arange(1, n) / n)
     u_ex = (np.sin(3 * np.pi * X / Lx) * np.sin(4 * np.pi * Y)).ravel() + wl.uniform_noise((n - 1) ** 2, 0)
     b = A @ u_ex
     res = krylov.fgmres(lambda x: A @ x, b, h.vcycle, 1e-6, restart=20, maxit=200)
-    s = FdSolver(n=n, Lx=Lx, Ly=1.0, factor=f, coarsest_n=2, smoother="cheb4", pre=pre, post=post,
+    s = FdSolver(n=n, Lx=float(Lx), Ly=1.0, factor=f, coarsest_n=2, smoother=kind, pre=pre, post=post,
                  krylov="gmres", restart=20, lambda_max=lmax)
     s.reset_counts()
     u, info = s.solve(dev(b), rtol=1e-6, maxit=200)
+    print(f"  {info.iterations} iterations (oracle {res.iterations}), {s.apply_counts()[0]} mat-vecs", flush=True)
     _compare(info, u, res, np.linalg.norm(b))
-    assert info.iterations == 5
-    assert s.apply_counts()[0] == 75  # printed mat-vec count
+    assert s.apply_counts()[0] == info.iterations * (pre + post + 1)
 
 
 def test_mixed_gmres_true_residual():
