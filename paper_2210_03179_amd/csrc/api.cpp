@@ -722,6 +722,8 @@ sem_status alloc_krylov(sem_ctx *c, int64_t n) {
   TRY(dalloc(c, &c->kw, n));
   TRY(dalloc(c, &c->scal, S_COUNT));
   c->partials_cap = (int64_t)std::max<size_t>((size_t)kReduceBlocks * kMaxRestart, (size_t)(n / 256 + 2));
+  // the fused Krylov operator writes one partial per operator block (at most one per element)
+  if (!c->levels.empty()) c->partials_cap = std::max<int64_t>(c->partials_cap, c->levels[0].E + 2);
   TRY(dalloc(c, &c->partials, (size_t)c->partials_cap));
   HIPCHK(c, hipHostMalloc((void **)&c->pinned, S_COUNT * sizeof(double), hipHostMallocDefault));
   if (c->opt.krylov == SEM_GMRES) {
@@ -1914,12 +1916,27 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
   sem_status status = SEM_ENOTCONV;
   int it = 0;
   bool x_pending = false;  // x += alpha p of the last residual update not yet applied
+  // On box levels with stored factors the Krylov operator reduces p . Ap itself (u . A_L u per
+  // element) and the residual update sums the element copies of Ap, so A p is never stored
+  // as a global vector (one pass and one launch less per iteration)
+  Level &L0 = c->levels[0];
+  // (SEMCHEB_FUSED_KRYLOV=0 in the environment keeps the separate summation pass)
+  const char *fk = std::getenv("SEMCHEB_FUSED_KRYLOV");
+  const bool fused = L0.type == LVL_SEM && !L0.tri64 && L0.G64 && !(fk && fk[0] == '0');
   for (it = 1; it <= maxit; ++it) {
-    fine_apply(c, p, w, p, s);
-    launch_finalize(c->npartials, 1, c->partials, c->scal, S_PW, FIN_NONE, s);
-    launch_update_r(n, c->scal, r, w, r2, c->partials, kReduceBlocks, mixed ? c->levels[0].b32 : nullptr, s);
+    if (fused) {
+      L0.applies++;
+      const int nb = launch_ax_dot(L0, p, L0.w64, c->partials, s);
+      launch_finalize(nb, 1, c->partials, c->scal, S_PW, FIN_NONE, s);
+      const int nr = launch_update_r_dss(L0, c->scal, r, L0.w64, r2, c->partials, mixed ? L0.b32 : nullptr, s);
+      launch_finalize(nr, 1, c->partials, c->scal, S_RR, FIN_NONE, s);
+    } else {
+      fine_apply(c, p, w, p, s);
+      launch_finalize(c->npartials, 1, c->partials, c->scal, S_PW, FIN_NONE, s);
+      launch_update_r(n, c->scal, r, w, r2, c->partials, kReduceBlocks, mixed ? c->levels[0].b32 : nullptr, s);
+      launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_RR, FIN_NONE, s);
+    }
     x_pending = true;
-    launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_RR, FIN_NONE, s);
     TRY(read_scalars(c, s));
     const double rz = c->pinned[S_RZ], pw = c->pinned[S_PW], rr = c->pinned[S_RR];
     if (!std::isfinite(rr) || !std::isfinite(pw) || !std::isfinite(rz)) {

@@ -174,7 +174,26 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
   return (b % kXcd) * (full / kXcd) + b / kXcd;
 }
 
+// Sum of v over the block in a fixed order (wave shuffles, then the waves in order), stored
+// by thread 0 in *out. Every thread of the block calls it; blockDim.x is a multiple of 64.
+__device__ __forceinline__ void block_sum_store(double v, double *out) {
+  __shared__ double wsum[16];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) wsum[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) acc += wsum[w];
+    *out = acc;
+  }
+}
+
 // ------------------------------------------------------------------ operator (element-local)
+// pdot (optional, FP64): the block's share of u . A_L u, the p . Ap of a Krylov iteration.
+// By the tensor-product form it is sum over nodes of (D_r u, D_s u, D_t u) . G (D_r u, D_s u,
+// D_t u), i.e. ur wr + us ws + ut wt at every node where the plane loop forms them, so it needs
+// neither the summed result nor u after the loop; one partial per block in pdot[blockIdx.x].
 // One (N+1)^2 thread slab per element, looping over the k planes:
 //   u column (i,j,:) held in registers, plane k of u staged in LDS for the r and s
 //   derivatives; the t derivative and its transpose stay in registers.
@@ -222,7 +241,8 @@ struct AxShape {
 template <int N, typename T, typename GT, int PF = 1, bool MAP = false>
 __device__ __forceinline__ void ax_body(unsigned blk, const Box &b, int64_t E, const T *__restrict__ u,
                                         const GT *__restrict__ G, const T *__restrict__ Dm,
-                                        T *__restrict__ wL, const int32_t *__restrict__ map = nullptr) {
+                                        T *__restrict__ wL, const int32_t *__restrict__ map = nullptr,
+                                        double *__restrict__ pdot = nullptr) {
   using S = AxShape<N>;
   constexpr int n1 = S::n1, n3 = n1 * n1 * n1;
   __shared__ T sD[n1 * n1];
@@ -291,6 +311,7 @@ __device__ __forceinline__ void ax_body(unsigned blk, const Box &b, int64_t E, c
     g4 = load_factor<GT, T>(Ge + 4 * n3);
     g5 = load_factor<GT, T>(Ge + 5 * n3);
   }
+  double dacc = 0.0;
 #pragma unroll 1
   for (int k = 0; k < n1; ++k) {
     // register arrays are only indexed with compile-time indices (selects on k)
@@ -323,6 +344,7 @@ __device__ __forceinline__ void ax_body(unsigned blk, const Box &b, int64_t E, c
     const T wr = g0 * ur + g1 * us + g2 * ut;
     const T ws = g1 * ur + g3 * us + g4 * ut;
     const T wt = g2 * ur + g4 * us + g5 * ut;
+    if (pdot && active) dacc += (double)(ur * wr + us * ws + ut * wt);
     if (active) {
       sr[lec][j][i] = wr;
       ss[lec][j][i] = ws;
@@ -344,6 +366,7 @@ __device__ __forceinline__ void ax_body(unsigned blk, const Box &b, int64_t E, c
 #pragma unroll
     for (int k = 0; k < n1; ++k) we[(k * n1 + j) * n1 + i] = wreg[k];
   }
+  if (pdot) block_sum_store(dacc, pdot + blockIdx.x);
 }
 
 
@@ -584,7 +607,7 @@ __device__ __forceinline__ void ax_body_tri_tile(unsigned blk, const Box &b, int
 template <int N, typename T, typename GT, int PF = 1>
 __device__ __forceinline__ void ax_body_tile(unsigned blk, const Box &b, int64_t E, const T *__restrict__ u,
                                              const GT *__restrict__ G, const T *__restrict__ Dm,
-                                             T *__restrict__ wL) {
+                                             T *__restrict__ wL, double *__restrict__ pdot = nullptr) {
   using S = AxShape<N>;
   constexpr int n1 = S::n1, n3 = n1 * n1 * n1;
   __shared__ T sD[n1 * n1];
@@ -648,6 +671,7 @@ __device__ __forceinline__ void ax_body_tile(unsigned blk, const Box &b, int64_t
     g4 = load_factor<GT, T>(Ge + 4 * n3);
     g5 = load_factor<GT, T>(Ge + 5 * n3);
   }
+  double dacc = 0.0;
 #pragma unroll 1
   for (int k = 0; k < n1; ++k) {
     T h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0, h5 = 0;
@@ -674,6 +698,7 @@ __device__ __forceinline__ void ax_body_tile(unsigned blk, const Box &b, int64_t
     const T wr = g0 * ur + g1 * us + g2 * ut;
     const T ws = g1 * ur + g3 * us + g4 * ut;
     const T wt = g2 * ur + g4 * us + g5 * ut;
+    if (pdot && active) dacc += (double)(ur * wr + us * ws + ut * wt);
     if (active) {
       sr[lec][j][i] = wr;
       ss[lec][j][i] = ws;
@@ -696,6 +721,7 @@ __device__ __forceinline__ void ax_body_tile(unsigned blk, const Box &b, int64_t
 #pragma unroll
     for (int k = 0; k < n1; ++k) we[(k * n1 + j) * n1 + i] = su[lec][k][j][i] + tt[k];
   }
+  if (pdot) block_sum_store(dacc, pdot + blockIdx.x);
 }
 
 // Single-precision operator with BF16 factors whose element factor blocks are copied
@@ -827,7 +853,7 @@ __device__ __forceinline__ void ax_body_dma(unsigned blk, const Box &b, int64_t 
 template <int N>
 __device__ __forceinline__ void ax_body_ring64(unsigned blk, const Box &b, int64_t E, const double *__restrict__ u,
                                                const double *__restrict__ G, const double *__restrict__ Dm,
-                                               double *__restrict__ wL) {
+                                               double *__restrict__ wL, double *__restrict__ pdot = nullptr) {
   static_assert(N == 7, "the ring variant assumes one 64-lane element per wave");
   using T = double;
   constexpr int n1 = N + 1, n2 = n1 * n1, n3 = n1 * n2;
@@ -840,7 +866,10 @@ __device__ __forceinline__ void ax_body_ring64(unsigned blk, const Box &b, int64
   const int t = threadIdx.x;  // 64 threads
   const int i = t % n1, j = t / n1;
   const int64_t e = blk;
-  if (e >= E) return;  // one element per block: the whole block leaves together
+  if (e >= E) {  // one element per block: the whole block leaves together
+    if (pdot && t == 0) pdot[blockIdx.x] = 0.0;
+    return;
+  }
   sD[t] = Dm[t];
   T ureg[n1], tt[n1];
   const Exyz ec = elem_xyz(b, e);
@@ -874,6 +903,7 @@ __device__ __forceinline__ void ax_body_ring64(unsigned blk, const Box &b, int64
   T Di[n1];
 #pragma unroll
   for (int l = 0; l < n1; ++l) Di[l] = sD[i * n1 + l];
+  double dacc = 0.0;
 #pragma unroll 1
   for (int k = 0; k < n1; ++k) {
     // loads issued after plane k's: planes k+1 .. min(k+kRing-1, n1-1), three each
@@ -894,6 +924,7 @@ __device__ __forceinline__ void ax_body_ring64(unsigned blk, const Box &b, int64
     const T wr = g0 * ur + g1 * us + g2 * ut;
     const T ws = g1 * ur + g3 * us + g4 * ut;
     const T wt = g2 * ur + g4 * us + g5 * ut;
+    if (pdot) dacc += (double)(ur * wr + us * ws + ut * wt);
     sr[j][i] = wr;
     ss[j][i] = ws;
     __syncthreads();
@@ -913,6 +944,7 @@ __device__ __forceinline__ void ax_body_ring64(unsigned blk, const Box &b, int64
   T *we = wL + e * n3;
 #pragma unroll
   for (int k = 0; k < n1; ++k) we[(k * n1 + j) * n1 + i] = su[k][j][i] + tt[k];
+  if (pdot) block_sum_store(dacc, pdot + blockIdx.x);
 }
 
 }  // namespace dev

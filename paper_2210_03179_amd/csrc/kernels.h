@@ -37,6 +37,16 @@ constexpr int kReduceBlocks = 1024;  // fixed grid of the reduction kernels (det
 
 bool launch_ax(const Level &L, const double *u, double *wL, hipStream_t s);
 bool launch_ax(const Level &L, const float *u, float *wL, hipStream_t s);
+// FP64 operator of a box level with stored factors that also reduces u . A_L u (p . Ap) into
+// one partial per block; returns the number of partials, 0 (nothing launched) when the level
+// cannot (trilinear factors, other level types)
+int launch_ax_dot(const Level &L, const double *u, double *wL, double *partials, hipStream_t s);
+int ax_elems_per_block(int N);
+// r_new = r - alpha * DSS(wL) with alpha = scal[S_RZ] / scal[S_PW], partials of ||r_new||^2 and
+// the optional FP32 copy; returns the number of partials
+int launch_update_r_dss(const Level &L, double *scal, const double *r, const double *wL, double *rnew,
+                        double *partials, float *r32, hipStream_t s);
+int update_r_dss_blocks(int64_t n);
 // unstructured meshes (LVL_GEN): operator with the input gathered through L.map, summation
 // over the local copies (optionally scaled per unknown, optionally added to out), gather of
 // a global vector to element-local copies, element-local interpolation (J: no x ni)

@@ -23,14 +23,16 @@ using namespace dev;
 // and TILE (0: u column in registers with one LDS plane, 1: whole u tile in LDS,
 // 2: u tile and the element's BF16 factors in LDS, single precision only; 3: u tile and a
 // ring of FP64 factor planes in LDS, N = 7 only).
+// pdot (FP64 variants, optional): per-block partials of u . A_L u (see ax_body).
 template <int N, typename T, typename GT, int PF, int OCC, int TILE = 0>
 __global__ void __launch_bounds__(AxShape<N>::block, OCC)
 ax_local_kernel(Box b, int64_t E, const T *__restrict__ u, const GT *__restrict__ G,
-                const T *__restrict__ Dm, T *__restrict__ wL) {
-  if constexpr (TILE == 3) ax_body_ring64<N>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
+                const T *__restrict__ Dm, T *__restrict__ wL, double *__restrict__ pdot) {
+  if constexpr (TILE == 3) ax_body_ring64<N>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL, pdot);
   else if constexpr (TILE == 2) ax_body_dma<N>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
-  else if constexpr (TILE == 1) ax_body_tile<N, T, GT, PF>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
-  else ax_body<N, T, GT, PF>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
+  else if constexpr (TILE == 1)
+    ax_body_tile<N, T, GT, PF>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL, pdot);
+  else ax_body<N, T, GT, PF>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL, nullptr, pdot);
 }
 
 // Operator of trilinear elements with factors computed in the kernel; OCC as above and
@@ -1076,6 +1078,43 @@ update_r_kernel(int64_t n, double *__restrict__ scal, const double *__restrict__
   if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA] = alpha;
 }
 
+// The same residual update with A p given as element-local copies (the operator reduced p . Ap
+// itself): r_new = r - alpha * sum of the copies, with the partial ||r_new||^2 per block and the
+// optional single-precision copy. Lanes take VEC unknowns 64 apart (see strided_first).
+template <int VEC>
+__global__ void __launch_bounds__(256)
+update_r_dss_kernel(Box b, int64_t n, double *__restrict__ scal, const double *__restrict__ r,
+                    const double *__restrict__ wL, double *__restrict__ rnew, double *__restrict__ partials,
+                    float *__restrict__ r32) {
+  __shared__ double sm[4];
+  const double alpha = scal[S_RZ] / scal[S_PW];
+  double acc = 0.0;
+  const int64_t g0 = strided_first<VEC>(blockIdx.x);
+  if (g0 < n) {
+    double rv[VEC], wv[VEC];
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) rv[q] = (g0 + 64 * q < n) ? r[g0 + 64 * q] : 0.0;
+    Ijk cc = ijk_of(b, g0);
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      wv[q] = (g0 + 64 * q < n) ? dss_ijk(wL, b, cc) : 0.0;
+      if (q + 1 < VEC) ijk_advance(b, cc, 64);
+    }
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      if (g0 + 64 * q < n) {
+        const double v = rv[q] - alpha * wv[q];
+        rnew[g0 + 64 * q] = v;
+        if (r32) r32[g0 + 64 * q] = (float)v;
+        acc += v * v;
+      }
+    }
+  }
+  const double t = block_sum(acc, sm);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA] = alpha;
+}
+
 __global__ void update_xp_kernel(int64_t n, const double *__restrict__ scal, double *__restrict__ x,
                                  const double *__restrict__ z, double *__restrict__ p) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1396,38 +1435,39 @@ inline bool al16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 // variant 0: prefetch, compiler's register choice; 1: no prefetch, AxShape::min_waves;
 // 2: prefetch, AxShape::min_waves
 template <int N, typename T, typename GT>
-void launch_ax_n(const Level &L, const T *u, const GT *G, const T *D, T *wL, int variant, hipStream_t s) {
+void launch_ax_n(const Level &L, const T *u, const GT *G, const T *D, T *wL, int variant, hipStream_t s,
+                 double *pdot = nullptr) {
   using S = AxShape<N>;
   const unsigned grid = (unsigned)((L.E + S::epb - 1) / S::epb);
   if constexpr (sizeof(GT) == 8 && N == 7) {
     if (variant == 5) {
       hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, 4, 3>), dim3(grid), dim3(S::block), 0, s, mkbox(L), L.E, u,
-                         G, D, wL);
+                         G, D, wL, pdot);
       return;
     }
   }
   if constexpr (sizeof(GT) == 2) {
     if (variant == 5) {
       hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, S::min_waves, 2>), dim3(grid), dim3(S::block), 0, s,
-                         mkbox(L), L.E, u, G, D, wL);
+                         mkbox(L), L.E, u, G, D, wL, pdot);
       return;
     }
   }
   if (variant == 3)
     hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 1, 1, 1>), dim3(grid), dim3(S::block), 0, s, mkbox(L), L.E, u,
-                       G, D, wL);
+                       G, D, wL, pdot);
   else if (variant == 4)
     hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, S::min_waves, 1>), dim3(grid), dim3(S::block), 0, s,
-                       mkbox(L), L.E, u, G, D, wL);
+                       mkbox(L), L.E, u, G, D, wL, pdot);
   else if (variant == 1)
     hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, S::min_waves>), dim3(grid), dim3(S::block), 0, s, mkbox(L),
-                       L.E, u, G, D, wL);
+                       L.E, u, G, D, wL, pdot);
   else if (variant == 2)
     hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 1, S::min_waves>), dim3(grid), dim3(S::block), 0, s, mkbox(L),
-                       L.E, u, G, D, wL);
+                       L.E, u, G, D, wL, pdot);
   else
     hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 1, 1>), dim3(grid), dim3(S::block), 0, s, mkbox(L), L.E, u, G,
-                       D, wL);
+                       D, wL, pdot);
 }
 
 template <int N, typename T>
@@ -1464,11 +1504,12 @@ bool launch_ax_tri(const Level &L, const T *u, const T *tri, const T *gxw, const
 }
 
 template <typename T, typename GT>
-bool launch_ax_t(const Level &L, const T *u, const GT *G, const T *D, T *wL, hipStream_t s) {
+bool launch_ax_t(const Level &L, const T *u, const GT *G, const T *D, T *wL, hipStream_t s,
+                 double *pdot = nullptr) {
   const int variant = sizeof(T) == 8 ? L.ax_variant64 : L.ax_variant32;
   switch (L.N) {
 #define SEMCHEB_AX_CASE(n) \
-  case n: launch_ax_n<n, T, GT>(L, u, G, D, wL, variant, s); return true;
+  case n: launch_ax_n<n, T, GT>(L, u, G, D, wL, variant, s, pdot); return true;
     SEMCHEB_AX_CASE(1) SEMCHEB_AX_CASE(2) SEMCHEB_AX_CASE(3) SEMCHEB_AX_CASE(4)
     SEMCHEB_AX_CASE(5) SEMCHEB_AX_CASE(6) SEMCHEB_AX_CASE(7) SEMCHEB_AX_CASE(8)
     SEMCHEB_AX_CASE(9) SEMCHEB_AX_CASE(10) SEMCHEB_AX_CASE(11) SEMCHEB_AX_CASE(12)
@@ -1486,6 +1527,17 @@ void launch_adj_n(const Level &L, const double *lam, const double *u, double *dG
 
 }  // namespace
 
+int ax_elems_per_block(int N) {
+  switch (N) {
+#define SEMCHEB_EPB(n) \
+  case n: return AxShape<n>::epb;
+    SEMCHEB_EPB(1) SEMCHEB_EPB(2) SEMCHEB_EPB(3) SEMCHEB_EPB(4) SEMCHEB_EPB(5) SEMCHEB_EPB(6)
+    SEMCHEB_EPB(7) SEMCHEB_EPB(8) SEMCHEB_EPB(9) SEMCHEB_EPB(10) SEMCHEB_EPB(11) SEMCHEB_EPB(12)
+#undef SEMCHEB_EPB
+    default: return 1;
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 bool launch_ax(const Level &L, const double *u, double *wL, hipStream_t s) {
   if (L.tri64) return launch_ax_tri<double>(L, u, L.tri64, L.gxw64, L.D64, wL, s);
@@ -1494,6 +1546,22 @@ bool launch_ax(const Level &L, const double *u, double *wL, hipStream_t s) {
 bool launch_ax(const Level &L, const float *u, float *wL, hipStream_t s) {
   if (L.tri32) return launch_ax_tri<float>(L, u, L.tri32, L.gxw32, L.D32, wL, s);
   return launch_ax_t<float, uint16_t>(L, u, L.Gbf, L.D32, wL, s);
+}
+
+int launch_ax_dot(const Level &L, const double *u, double *wL, double *partials, hipStream_t s) {
+  if (L.type != LVL_SEM || L.tri64 || !L.G64) return 0;
+  if (!launch_ax_t<double, double>(L, u, L.G64, L.D64, wL, s, partials)) return 0;
+  return (int)((L.E + ax_elems_per_block(L.N) - 1) / ax_elems_per_block(L.N));
+}
+
+int update_r_dss_blocks(int64_t n) { return (int)nblk((n + 1) / 2); }
+
+int launch_update_r_dss(const Level &L, double *scal, const double *r, const double *wL, double *rnew,
+                        double *partials, float *r32, hipStream_t s) {
+  const int nb = update_r_dss_blocks(L.n);
+  hipLaunchKernelGGL((update_r_dss_kernel<2>), dim3(nb), dim3(256), 0, s, mkbox(L), L.n, scal, r, wL, rnew, partials,
+                     r32);
+  return nb;
 }
 
 template <int N, typename T, typename GT>
