@@ -9,7 +9,8 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsemcheb.so")
+# SEMCHEB_LIB selects another build of the same library (the host-sanitizer test uses it)
+LIB_PATH = os.environ.get("SEMCHEB_LIB", os.path.join(_HERE, "libsemcheb.so"))
 
 SEM_OK, SEM_EINVAL, SEM_ENOMEM, SEM_EHIP, SEM_EMESH = 0, -1, -2, -3, -4
 SEM_ENOTCONV, SEM_EBREAKDOWN, SEM_ENAN, SEM_ENODEV = -5, -6, -7, -8

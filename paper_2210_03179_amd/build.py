@@ -53,6 +53,37 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+# Host code of the library under AddressSanitizer and UndefinedBehaviorSanitizer: the
+# setup, validation and host-array code (api.cpp, host_setup.cpp, batched.cpp) is compiled
+# with the sanitizers on its host pass only; the device code is built as usual. The library
+# expects the sanitizer runtime to be preloaded into the process (tests/test_host_sanitizers.py).
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+
+
+def build_host_sanitized(out_dir: str) -> str:
+    os.makedirs(out_dir, exist_ok=True)
+
+    def comp(src):
+        obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
+        extra = SANITIZE if src != "kernels.hip" else []
+        cmd = [HIPCC, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + extra
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compiling {src} failed:\n{' '.join(cmd)}\n{r.stderr}")
+        return obj
+
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(comp, SOURCES))
+    out = os.path.join(out_dir, "libsemcheb_sanitized.so")
+    cmd = [HIPCC, "-shared", "-fopenmp", f"--offload-arch={ARCH}", *objs, "-o", out, *SANITIZE,
+           "-Wl,-rpath,/opt/rocm/lib/llvm/lib", "-Wl,-rpath,/opt/rocm/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"linking the sanitized library failed:\n{' '.join(cmd)}\n{r.stderr}")
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
