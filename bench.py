@@ -208,11 +208,15 @@ def bench_batched(steps, nsys=64):
         uq = u[bs.offsets[q]:bs.offsets[q + 1]].contiguous()
         worst = max(worst, float(torch.linalg.vector_norm(bq - s.apply_A(uq)) / torch.linalg.vector_norm(bq)))
     ns = [bs.offsets[q + 1] - bs.offsets[q] for q in range(nsys)]
+    # operator variants chosen by the batched autotuner: (level, order) -> (variant, us); level -1
+    # is the FP64 Krylov operator
+    tune = {f"{int(r[0])}:{int(r[1])}": [int(r[2]), round(float(r[3 + int(r[2])]), 1)]
+            for r in bs.host_array("ax_tuning").reshape(-1, 9)}
     return {"systems": nsys, "unknowns": bs.n, "ms_per_batch_solve": round(t_batch * 1e3, 3),
             "ms_fp64_one_by_one": round(t_seq * 1e3, 3), "speedup_vs_fp64": round(t_seq / t_batch, 3),
             "gdof_iter_per_s": round(sum(n * i for n, i in zip(ns, its)) / t_batch / 1e9, 4),
             "iterations_min_max": [min(its), max(its)], "fp64_iterations_min_max": [min(its64), max(its64)],
-            "worst_true_relres": worst, "status": st,
+            "worst_true_relres": worst, "status": st, "operator_variants": tune,
             "setup_s": {"fp64_systems": round(t_setup64, 1), "batched": round(t_setupb, 1)}}
 
 

@@ -301,6 +301,9 @@ sem_status sem_reset_counts(sem_ctx *ctx);
  * and the sparse A_j and interpolation P_j (level j+1 -> j; Sec. 3: bilinear
  * interpolation, A_{j+1} = P_j^T A_j P_j) in CSR form as "csr_rowptr", "csr_col",
  * "csr_val", "interp_rowptr", "interp_col", "interp_val" (indices as exact doubles).
+ * Batched contexts: "ax_tuning" only, one row per (level, order) of the single-precision cycle
+ * operators and per order of the FP64 Krylov operator (level -1): level, order, the chosen
+ * variant and the six variants' times in microseconds on the batched launch (-1: not timed).
  * Returns SEM_EINVAL if `n` does not equal the array size, with the size
  * written to *needed when it is not NULL. */
 sem_status sem_host_array(const sem_ctx *ctx, const char *what, int32_t level, double *out,
@@ -318,7 +321,9 @@ sem_status sem_set_smoothing(sem_ctx *ctx, int32_t smoother, int32_t pre_order, 
  * own orders (orders[s] in 4..12, schedule N, floor(N/2), 1), all with the smoother,
  * cycle and Krylov settings of *opt and a mixed-precision cycle (FP32 arithmetic,
  * BF16 geometric factors, FP64 Krylov and coarse solve). lambda_max is estimated per
- * system and level. meshes, orders: host arrays of nsys entries. Same errors as
+ * system and level. The setup times the six operator variants on the batched launches of
+ * every order and level and keeps the fastest (SEMCHEB_AX_VARIANT / SEMCHEB_AUTOTUNE as for
+ * single systems). meshes, orders: host arrays of nsys entries. Same errors as
  * sem_setup_box, plus SEM_EINVAL for pre_order < 1, pre_order or post_order > 16, a
  * given lambda_max/schedule, or an outer method other than SEM_PCG and SEM_FCG. */
 sem_status sem_setup_batched(int32_t nsys, const sem_box_mesh *meshes, const int32_t *orders,

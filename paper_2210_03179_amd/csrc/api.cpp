@@ -2042,6 +2042,31 @@ sem_status sem_reset_counts(sem_ctx *c) {
 sem_status sem_host_array(const sem_ctx *c, const char *what, int32_t j, double *out, int64_t n,
                           int64_t *needed) {
   if (!c || !what) return SEM_EINVAL;
+  if (c->batch) {
+    // batched contexts: "ax_tuning" only, rows (level, order, chosen variant, six timings in us)
+    // for the single-precision cycle operators, level -1 for the FP64 Krylov operator
+    if (std::string(what) != "ax_tuning") return SEM_EINVAL;
+    std::vector<double> tmp;
+    auto row = [&](int lev, int N, int v, const std::vector<double> &t) {
+      tmp.push_back(lev);
+      tmp.push_back(N);
+      tmp.push_back(v);
+      for (int q = 0; q < 6; ++q) tmp.push_back(q < (int)t.size() ? t[q] : -1.0);
+    };
+    for (int lev = 0; lev < kBatchLevels; ++lev)
+      for (auto &kv : c->batch->var32[lev]) {
+        auto it = c->batch->time32[lev].find(kv.first);
+        row(lev, kv.first, kv.second, it == c->batch->time32[lev].end() ? std::vector<double>() : it->second);
+      }
+    for (auto &kv : c->batch->var64) {
+      auto it = c->batch->time64.find(kv.first);
+      row(-1, kv.first, kv.second, it == c->batch->time64.end() ? std::vector<double>() : it->second);
+    }
+    if (needed) *needed = (int64_t)tmp.size();
+    if (n != (int64_t)tmp.size() || (!out && n > 0)) return SEM_EINVAL;
+    std::copy(tmp.begin(), tmp.end(), out);
+    return SEM_OK;
+  }
   std::vector<double> tmp;
   const std::vector<double> *src = nullptr;
   const std::string w(what);

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -125,6 +126,16 @@ Tables build_tables(const sem_batch &B, const std::vector<int> &act) {
   return T;
 }
 
+int var32(const sem_ctx *c, int j, int N) {
+  const auto &m = c->batch->var32[j];
+  auto it = m.find(N);
+  return it == m.end() ? 5 : it->second;
+}
+int var64(const sem_ctx *c, int N) {
+  auto it = c->batch->var64.find(N);
+  return it == c->batch->var64.end() ? 0 : it->second;
+}
+
 void smooth_b(const sem_ctx *c, const Tables &T, const BatchSysDev *d, int j, int k, bool zero_guess,
               hipStream_t s) {
   if (k <= 0) return;
@@ -132,7 +143,7 @@ void smooth_b(const sem_ctx *c, const Tables &T, const BatchSysDev *d, int j, in
   const int mode = (kind == SEM_CHEB4 || kind == SEM_CHEB4_OPT) ? 4 : 1;
   const int pp = zero_guess ? 0 : 1;
   auto ax = [&](int src) {
-    for (auto &g : T.ax[j]) launch_b_ax32(g.first, g.second, d, j, src, s);
+    for (auto &g : T.ax[j]) launch_b_ax32(g.first, var32(c, j, g.first), g.second, d, j, src, s);
   };
   int f0;
   if (mode == 4) {
@@ -156,7 +167,7 @@ void vcycle_b(const sem_ctx *c, const Tables &T, const BatchSysDev *d, hipStream
   const int pre = c->opt.pre_order, post = c->opt.post_order;
   for (int j = 0; j + 1 < kBatchLevels; ++j) {
     smooth_b(c, T, d, j, pre, true, s);
-    for (auto &g : T.ax[j]) launch_b_ax32(g.first, g.second, d, j, 1, s);
+    for (auto &g : T.ax[j]) launch_b_ax32(g.first, var32(c, j, g.first), g.second, d, j, 1, s);
     launch_b_resid(T.node4[j], d, j, 1, s);
     launch_b_restrict(T.elem[j], d, j, T.lds_restrict[j], s);
     launch_b_dss(T.node1[j + 1], d, j + 1, s);
@@ -169,6 +180,84 @@ void vcycle_b(const sem_ctx *c, const Tables &T, const BatchSysDev *d, hipStream
     if (post > 0) smooth_b(c, T, d, j, post, false, s);
   }
   if (post > 0) launch_b_convert(T.fine_nodes, d, 3, 0, s);
+}
+
+// Batched autotuner: every operator variant is timed on the batched launch itself (all systems
+// of one order on one level, FP32 cycle operators and the FP64 Krylov operator), best of three
+// rounds of three launches after a warm-up; the fastest is kept per order and level. The
+// variants compute the same sums and differ in scheduling, so results agree to rounding.
+// SEMCHEB_AX_VARIANT=v fixes variant v everywhere; SEMCHEB_AUTOTUNE=0 keeps the defaults
+// (DMA-staged factors in FP32, register columns in FP64).
+sem_status autotune_batched(sem_ctx *c, hipStream_t s) {
+  sem_batch &B = *c->batch;
+  const int nsys = (int)B.sys.size();
+  std::vector<int> all(nsys);
+  for (int q = 0; q < nsys; ++q) all[q] = q;
+  const Tables T = build_tables(B, all);
+  const char *fv = std::getenv("SEMCHEB_AX_VARIANT");
+  const char *at = std::getenv("SEMCHEB_AUTOTUNE");
+  if (fv || (at && at[0] == '0')) {
+    const int v = fv ? std::atoi(fv) : -1;
+    if (fv && (v < 0 || v > 5)) { c->err = "SEMCHEB_AX_VARIANT must be in [0, 6)"; return SEM_EINVAL; }
+    for (int j = 0; j + 1 < kBatchLevels; ++j)
+      for (auto &g : T.ax[j]) B.var32[j][g.first] = v >= 0 ? v : 5;
+    for (auto &g : T.ax64) B.var64[g.first] = v >= 0 ? v : 0;
+    return SEM_OK;
+  }
+  // defined inputs for the timed launches
+  for (int q = 0; q < nsys; ++q) {
+    for (int j = 0; j + 1 < kBatchLevels; ++j) {
+      const BatchLevelDev &L = B.host[q].lev[j];
+      BHIP(c, hipMemsetAsync(L.d, 0, L.n * sizeof(float), s));
+      BHIP(c, hipMemsetAsync(L.x, 0, L.n * sizeof(float), s));
+    }
+    BHIP(c, hipMemsetAsync(B.host[q].p, 0, B.host[q].lev[0].n * sizeof(double), s));
+  }
+  hipEvent_t e0, e1;
+  BHIP(c, hipEventCreate(&e0));
+  BHIP(c, hipEventCreate(&e1));
+  sem_status st = SEM_OK;
+  auto time_it = [&](auto launch) -> double {
+    double best = 1e30;
+    for (int round = 0; round < 3 && st == SEM_OK; ++round) {
+      launch();
+      hipEventRecord(e0, s);
+      for (int r = 0; r < 3; ++r) launch();
+      hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) { st = SEM_EHIP; break; }
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      best = std::min(best, ms * 1000.0 / 3.0);
+    }
+    return best;
+  };
+  for (int j = 0; j + 1 < kBatchLevels && st == SEM_OK; ++j)
+    for (auto &g : T.ax[j]) {
+      std::vector<double> t(6, -1.0);
+      int bestv = 5;
+      for (int v = 0; v < 6 && st == SEM_OK; ++v) {
+        t[v] = time_it([&] { launch_b_ax32(g.first, v, g.second, B.dev, j, 0, s); });
+        if (t[v] < t[bestv] || t[bestv] < 0) bestv = v;
+      }
+      B.var32[j][g.first] = bestv;
+      B.time32[j][g.first] = t;
+    }
+  for (auto &g : T.ax64) {
+    if (st != SEM_OK) break;
+    std::vector<double> t(6, -1.0);
+    int bestv = 0;
+    for (int v = 0; v < 6 && st == SEM_OK; ++v) {
+      if (v == 5 && g.first != 7) continue;  // variant 5 is variant 0 at other FP64 orders
+      t[v] = time_it([&] { launch_b_ax64(g.first, v, g.second, B.dev, s); });
+      if (t[v] < t[bestv]) bestv = v;
+    }
+    B.var64[g.first] = bestv;
+    B.time64[g.first] = t;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != SEM_OK) c->err = "timing the batched operator variants failed";
+  return st;
 }
 
 sem_status setup_batched_impl(int nsys, const sem_box_mesh *meshes, const int32_t *orders, const sem_options *opt,
@@ -257,7 +346,9 @@ sem_status setup_batched_impl(int nsys, const sem_box_mesh *meshes, const int32_
   B->partials_cap = cap;
   BHIP(c, hipHostMalloc((void **)&B->pinned, sizeof(double) * S_COUNT * nsys, hipHostMallocDefault));
   for (int q = 0; q < nsys; ++q) B->host[q].scal = B->scal + (size_t)q * S_COUNT;
-  return SEM_OK;
+  BHIP(c, hipMemcpyAsync(B->dev, B->host.data(), sizeof(BatchSysDev) * nsys, hipMemcpyHostToDevice, s));
+  BHIP(c, hipStreamSynchronize(s));
+  return autotune_batched(c, s);
 }
 
 sem_status solve_batched_impl(sem_ctx *c, const double *b, double *u, double rtol, int maxit, int32_t *iters,
@@ -307,7 +398,7 @@ sem_status solve_batched_impl(sem_ctx *c, const double *b, double *u, double rto
   launch_b_vec(T.fine_nodes, d, 1, s);
   int par = 0;
   for (int it = 1; it <= maxit && !act.empty(); ++it) {
-    for (auto &g : T.ax64) launch_b_ax64(g.first, g.second, d, s);
+    for (auto &g : T.ax64) launch_b_ax64(g.first, var64(c, g.first), g.second, d, s);
     launch_b_dssdot(T.fine_dot2, d, B.partials, s);
     launch_b_finalize(T.fine_dot2, d, B.partials, 1, S_PW, FIN_NONE, s);
     launch_b_update_xr(T.fine_nodes, d, par, B.partials, s);

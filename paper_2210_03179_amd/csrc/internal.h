@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -296,4 +297,9 @@ struct sem_batch {
   double *pinned = nullptr;                     // host mirror of scal
   double *partials = nullptr;                   // reduction partials of a batched launch
   int64_t partials_cap = 0;
+  // operator variant per (level, order) for the single-precision cycle and per order for the
+  // FP64 Krylov operator, chosen at setup by timing the batched launches; the timings (us) of
+  // the six variants are kept for inspection (-1 where not timed)
+  std::map<int, int> var32[semcheb::kBatchLevels], var64;
+  std::map<int, std::vector<double>> time32[semcheb::kBatchLevels], time64;
 };

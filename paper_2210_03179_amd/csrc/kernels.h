@@ -164,8 +164,11 @@ namespace semcheb {
 // ---------------------------------------------------------------- batched launchers
 // The grid of every batched launch is t.begin[t.count] blocks (finalize: t.count).
 int batch_ax_elements_per_block(int N);
-bool launch_b_ax32(int N, const LaunchTable &t, const BatchSysDev *sys, int level, int src, hipStream_t s);
-bool launch_b_ax64(int N, const LaunchTable &t, const BatchSysDev *sys, hipStream_t s);
+// batched operators in variant `variant` (the numbering of the single-system autotuner);
+// false for orders without batched kernels
+bool launch_b_ax32(int N, int variant, const LaunchTable &t, const BatchSysDev *sys, int level, int src,
+                   hipStream_t s);
+bool launch_b_ax64(int N, int variant, const LaunchTable &t, const BatchSysDev *sys, hipStream_t s);
 void launch_b_cheb(const LaunchTable &t, const BatchSysDev *sys, int level, int pp, int step, int flags, int mode,
                    hipStream_t s);
 void launch_b_resid(const LaunchTable &t, const BatchSysDev *sys, int level, int has_w, hipStream_t s);

@@ -1245,23 +1245,42 @@ __device__ __forceinline__ Box lbox(const BatchLevelDev &L) {
   const BatchSysDev &S = sys[tab.sys[slot_]];              \
   const unsigned blk = blockIdx.x - (unsigned)tab.begin[slot_];
 
+// Operator variants of the batched kernels, numbered as the single-system autotuner's:
+// 0 (prefetch, compiler's registers), 1 (no prefetch, min_waves), 2 (prefetch, min_waves),
+// 3 (u tile in LDS, prefetch), 4 (u tile in LDS, min_waves), 5 (single precision: factors
+// staged in LDS by DMA; FP64 at N = 7: ring of factor planes in LDS; other FP64 orders: 0).
+// The batched setup times them on the batched launch of every order and level.
+template <int N, int V>
+struct BVar {
+  static constexpr int pf = (V == 0 || V == 2 || V == 3) ? 1 : 0;
+  static constexpr int occ = (V == 0 || V == 3) ? 1 : AxShape<N>::min_waves;
+  static constexpr int tile = (V == 3 || V == 4) ? 1 : (V == 5 ? 2 : 0);
+};
+
 // single-precision operator of a cycle level: src 0 applies to d, 1 to x
-template <int N>
-__global__ void __launch_bounds__(AxShape<N>::block)
+template <int N, int V>
+__global__ void __launch_bounds__(AxShape<N>::block, (BVar<N, V>::occ))
 b_ax32_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, int level, int src) {
   SEMCHEB_BATCH_SYS
   const BatchLevelDev &L = S.lev[level];
-  // BF16 factors staged in LDS by DMA (the variant the single-system autotuner prefers)
-  ax_body_dma<N>(blk, lbox(L), L.E, src == 0 ? L.d : L.x, L.G, L.D, L.w);
+  const float *u = src == 0 ? L.d : L.x;
+  constexpr int TILE = BVar<N, V>::tile, PF = BVar<N, V>::pf;
+  if constexpr (TILE == 2) ax_body_dma<N>(blk, lbox(L), L.E, u, L.G, L.D, L.w);
+  else if constexpr (TILE == 1) ax_body_tile<N, float, uint16_t, PF>(blk, lbox(L), L.E, u, L.G, L.D, L.w);
+  else ax_body<N, float, uint16_t, PF>(blk, lbox(L), L.E, u, L.G, L.D, L.w);
 }
 
 // FP64 operator on the finest level applied to the Krylov direction p
-template <int N>
-__global__ void __launch_bounds__(AxShape<N>::block)
+template <int N, int V>
+__global__ void __launch_bounds__(AxShape<N>::block, ((V == 5 && N == 7) ? 4 : BVar<N, V>::occ))
 b_ax64_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys) {
   SEMCHEB_BATCH_SYS
   const BatchLevelDev &L = S.lev[0];
-  ax_body<N, double, double>(blk, lbox(L), L.E, S.p, L.G64, L.D64, L.w64);
+  constexpr int TILE = BVar<N, V>::tile, PF = BVar<N, V>::pf;
+  if constexpr (V == 5 && N == 7) ax_body_ring64<N>(blk, lbox(L), L.E, S.p, L.G64, L.D64, L.w64);
+  else if constexpr (TILE == 1) ax_body_tile<N, double, double, PF>(blk, lbox(L), L.E, S.p, L.G64, L.D64, L.w64);
+  else if constexpr (TILE == 2) ax_body<N, double, double, 1>(blk, lbox(L), L.E, S.p, L.G64, L.D64, L.w64);
+  else ax_body<N, double, double, PF>(blk, lbox(L), L.E, S.p, L.G64, L.D64, L.w64);
 }
 
 __global__ void __launch_bounds__(256)
@@ -1930,12 +1949,28 @@ namespace semcheb {
 namespace {
 inline unsigned tgrid(const LaunchTable &t) { return (unsigned)t.begin[t.count]; }
 template <int N>
-void b_ax32_n(const LaunchTable &t, const BatchSysDev *sys, int level, int src, hipStream_t s) {
-  hipLaunchKernelGGL((b_ax32_kernel<N>), dim3(tgrid(t)), dim3(AxShape<N>::block), 0, s, t, sys, level, src);
+void b_ax32_n(const LaunchTable &t, const BatchSysDev *sys, int level, int src, int v, hipStream_t s) {
+  const dim3 g(tgrid(t)), b(AxShape<N>::block);
+  switch (v) {
+    case 1: hipLaunchKernelGGL((b_ax32_kernel<N, 1>), g, b, 0, s, t, sys, level, src); break;
+    case 2: hipLaunchKernelGGL((b_ax32_kernel<N, 2>), g, b, 0, s, t, sys, level, src); break;
+    case 3: hipLaunchKernelGGL((b_ax32_kernel<N, 3>), g, b, 0, s, t, sys, level, src); break;
+    case 4: hipLaunchKernelGGL((b_ax32_kernel<N, 4>), g, b, 0, s, t, sys, level, src); break;
+    case 5: hipLaunchKernelGGL((b_ax32_kernel<N, 5>), g, b, 0, s, t, sys, level, src); break;
+    default: hipLaunchKernelGGL((b_ax32_kernel<N, 0>), g, b, 0, s, t, sys, level, src); break;
+  }
 }
 template <int N>
-void b_ax64_n(const LaunchTable &t, const BatchSysDev *sys, hipStream_t s) {
-  hipLaunchKernelGGL((b_ax64_kernel<N>), dim3(tgrid(t)), dim3(AxShape<N>::block), 0, s, t, sys);
+void b_ax64_n(const LaunchTable &t, const BatchSysDev *sys, int v, hipStream_t s) {
+  const dim3 g(tgrid(t)), b(AxShape<N>::block);
+  switch (v) {
+    case 1: hipLaunchKernelGGL((b_ax64_kernel<N, 1>), g, b, 0, s, t, sys); break;
+    case 2: hipLaunchKernelGGL((b_ax64_kernel<N, 2>), g, b, 0, s, t, sys); break;
+    case 3: hipLaunchKernelGGL((b_ax64_kernel<N, 3>), g, b, 0, s, t, sys); break;
+    case 4: hipLaunchKernelGGL((b_ax64_kernel<N, 4>), g, b, 0, s, t, sys); break;
+    case 5: hipLaunchKernelGGL((b_ax64_kernel<N, 5>), g, b, 0, s, t, sys); break;
+    default: hipLaunchKernelGGL((b_ax64_kernel<N, 0>), g, b, 0, s, t, sys); break;
+  }
 }
 }  // namespace
 
@@ -1950,25 +1985,27 @@ int batch_ax_elements_per_block(int N) {
   }
 }
 
-bool launch_b_ax32(int N, const LaunchTable &t, const BatchSysDev *sys, int level, int src, hipStream_t s) {
+// batched orders: finest levels 4..12, the level below 2..6 (the order-1 level is solved densely)
+bool launch_b_ax32(int N, int variant, const LaunchTable &t, const BatchSysDev *sys, int level, int src,
+                   hipStream_t s) {
   if (t.count == 0) return true;
   switch (N) {
 #define SEMCHEB_BAX(n) \
-  case n: b_ax32_n<n>(t, sys, level, src, s); return true;
-    SEMCHEB_BAX(1) SEMCHEB_BAX(2) SEMCHEB_BAX(3) SEMCHEB_BAX(4) SEMCHEB_BAX(5) SEMCHEB_BAX(6)
+  case n: b_ax32_n<n>(t, sys, level, src, variant, s); return true;
+    SEMCHEB_BAX(2) SEMCHEB_BAX(3) SEMCHEB_BAX(4) SEMCHEB_BAX(5) SEMCHEB_BAX(6)
     SEMCHEB_BAX(7) SEMCHEB_BAX(8) SEMCHEB_BAX(9) SEMCHEB_BAX(10) SEMCHEB_BAX(11) SEMCHEB_BAX(12)
 #undef SEMCHEB_BAX
     default: return false;
   }
 }
 
-bool launch_b_ax64(int N, const LaunchTable &t, const BatchSysDev *sys, hipStream_t s) {
+bool launch_b_ax64(int N, int variant, const LaunchTable &t, const BatchSysDev *sys, hipStream_t s) {
   if (t.count == 0) return true;
   switch (N) {
 #define SEMCHEB_BAX(n) \
-  case n: b_ax64_n<n>(t, sys, s); return true;
-    SEMCHEB_BAX(1) SEMCHEB_BAX(2) SEMCHEB_BAX(3) SEMCHEB_BAX(4) SEMCHEB_BAX(5) SEMCHEB_BAX(6)
-    SEMCHEB_BAX(7) SEMCHEB_BAX(8) SEMCHEB_BAX(9) SEMCHEB_BAX(10) SEMCHEB_BAX(11) SEMCHEB_BAX(12)
+  case n: b_ax64_n<n>(t, sys, variant, s); return true;
+    SEMCHEB_BAX(4) SEMCHEB_BAX(5) SEMCHEB_BAX(6) SEMCHEB_BAX(7) SEMCHEB_BAX(8) SEMCHEB_BAX(9) SEMCHEB_BAX(10)
+    SEMCHEB_BAX(11) SEMCHEB_BAX(12)
 #undef SEMCHEB_BAX
     default: return false;
   }

@@ -35,7 +35,9 @@ def _rhs(box, seed):
 
 
 @pytest.mark.parametrize("pre,post,kind", [(4, 0, "cheb4opt"), (2, 2, "cheb4"), (3, 0, "cheb1opt")])
-def test_batched_matches_single_and_oracle(pre, post, kind):
+def test_batched_matches_single_and_oracle(pre, post, kind, monkeypatch):
+    # the same operator variant on both sides (their single-precision roundings differ)
+    monkeypatch.setenv("SEMCHEB_AX_VARIANT", "5")
     specs = _systems(7, 300)
     boxes = [SemBox(V, N) for V, N, _ in specs]
     rhs = [_rhs(bx, sd) for bx, (_, _, sd) in zip(boxes, specs)]
@@ -70,3 +72,40 @@ def test_batched_zero_rhs_and_errors():
     assert float(u[bs.offsets[0]:bs.offsets[1]].abs().max()) == 0.0
     with pytest.raises(L.SemError):
         BatchedSolver([specs[0][0]], [3])  # order 3 has only two levels
+
+
+def test_batched_operator_autotuning():
+    """The batched setup times the six operator variants on the batched launches of every
+    (level, order) and keeps the fastest; every variant, fixed through the environment,
+    solves every system to a true 1e-8 in the same number of iterations (within one: the
+    single-precision roundings differ between variants)."""
+    import os
+    specs = _systems(6, 500)
+    boxes = [SemBox(V, N) for V, N, _ in specs]
+    rhs = [_rhs(bx, sd) for bx, (_, _, sd) in zip(boxes, specs)]
+    b = torch.from_numpy(np.concatenate(rhs)).cuda()
+    bs = BatchedSolver([V for V, _, _ in specs], [N for _, N, _ in specs])
+    rows = bs.host_array("ax_tuning").reshape(-1, 9)
+    orders = sorted({N for _, N, _ in specs})
+    assert sorted(int(r[1]) for r in rows if r[0] == 0) == orders
+    assert sorted(int(r[1]) for r in rows if r[0] == 1) == sorted({N // 2 for N in orders})
+    assert sorted(int(r[1]) for r in rows if r[0] == -1) == orders
+    for r in rows:
+        t = r[3:]
+        assert t[int(r[2])] == min(x for x in t if x >= 0), r
+    print("batched tuning (level, order, variant):", [tuple(int(x) for x in r[:3]) for r in rows], flush=True)
+    _, st, its_auto, _ = bs.solve(b)
+    assert st == L.SEM_OK
+    for v in range(6):
+        os.environ["SEMCHEB_AX_VARIANT"] = str(v)
+        try:
+            bv = BatchedSolver([V for V, _, _ in specs], [N for _, N, _ in specs])
+        finally:
+            del os.environ["SEMCHEB_AX_VARIANT"]
+        u, st, its, _ = bv.solve(b)
+        assert st == L.SEM_OK
+        assert all(abs(a - c) <= 1 for a, c in zip(its, its_auto)), (v, its, its_auto)
+        uh = u.cpu().numpy()
+        for q, (bx, bq) in enumerate(zip(boxes, rhs)):
+            uq = uh[bv.offsets[q]:bv.offsets[q + 1]]
+            assert np.linalg.norm(bq - bx.apply(uq)) <= 1.01e-8 * np.linalg.norm(bq), (v, q)
