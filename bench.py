@@ -50,6 +50,9 @@ def parse():
                     help="skip the measurement with factors formed in the operator")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the 64-system batched measurement (for profiler runs)")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="set up the FP64 and mixed contexts and run --steps solves of each, nothing else "
+                         "(short runs for profilers)")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--kernel-only", action="store_true",
                     help="set up the FP64 and mixed contexts with fixed lambda_max and only launch the "
@@ -296,6 +299,13 @@ def main():
     b0 = s64.mass_apply(torch.from_numpy(f).cuda()).cpu().numpy()
     bh = b0 + 1e-3 * np.max(np.abs(b0)) * wl.uniform_noise(n, 0)
     b = torch.from_numpy(bh).cuda()
+    if args.solve_only:
+        _, i64, d64, _, _ = time_solves(s64, b, args.steps, 0)
+        _, imx, dmx, _, _ = time_solves(smx, b, args.steps, 0)
+        print(json.dumps({"solve_only": True, "unknowns": n, "fp64": {"iterations": i64.iterations,
+                                                                     "ms_per_solve": d64 * 1e3},
+                          "mixed": {"iterations": imx.iterations, "ms_per_solve": dmx * 1e3}}), flush=True)
+        return
 
     u64, info64, dt64, its64, each64 = time_solves(s64, b, args.steps, args.warmup)
     log(f"fp64: {info64.iterations} its, {dt64 * 1e3:.2f} ms/solve")
@@ -345,7 +355,7 @@ def main():
     nvar = (len(tune64) // s64.num_levels - 2) // 2  # per level: variant, times (FP64), variant, times
     v64, vmx = int(tune64[0]), int(tunemx[1 + nvar])
     k64 = "ax_local_kernel<%d, double, double, %d, %d, %d>" % ((N,) + _variant_args(v64, N, fp64=True))
-    kmx = "ax_local_kernel<%d, float, bf16, %d, %d, %d>" % ((N,) + _variant_args(vmx, N))
+    kmx = "ax_local_kernel<%d, float, unsigned short, %d, %d, %d>" % ((N,) + _variant_args(vmx, N))  # BF16 storage
     log(f"operator variants (us) fp64 {[round(x, 1) for x in tune64[1:1 + nvar]]} -> {v64}, "
         f"bf16 {[round(x, 1) for x in tunemx[2 + nvar:2 + 2 * nvar]]} -> {vmx}")
     per = 2 * (1 + nvar)
@@ -353,7 +363,7 @@ def main():
         t64, tmx = tune64[j * per:(j + 1) * per], tunemx[j * per:(j + 1) * per]
         log(f"level {j} operator variants (us) fp64 {[round(x, 1) for x in t64[1:1 + nvar]]} -> {int(t64[0])}, "
             f"bf16 {[round(x, 1) for x in tmx[2 + nvar:2 + 2 * nvar]]} -> {int(tmx[1 + nvar])}")
-    kdss = "dss_kernel<double, double>"
+    kdss = "dss_kernel<double, double, 2>"
     tr_ax = measured_traffic(k64) if N == 7 and m == 32 else None
     tr_dss = measured_traffic(kdss) if N == 7 and m == 32 else None
     tr_apply = tr_ax + tr_dss if (tr_ax is not None and tr_dss is not None) else None
