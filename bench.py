@@ -126,7 +126,10 @@ def _variant_args(variant, N, fp64=False):
     mw = 4 if N <= 7 else 2
     if variant == 5 and fp64:  # the FP64 factor ring (N = 7); other orders launch variant 0
         return (0, mw, 3) if N == 7 else (1, 1, 0)
-    return {0: (1, 1, 0), 1: (0, mw, 0), 2: (1, mw, 0), 3: (1, 1, 1), 4: (0, mw, 1), 5: (0, mw, 2)}[variant]
+    if variant == 6 and N == 7:  # matrix-core contractions (BF16 factors at N = 7)
+        return (0, mw, 4)
+    return {0: (1, 1, 0), 1: (0, mw, 0), 2: (1, mw, 0), 3: (1, 1, 1), 4: (0, mw, 1), 5: (0, mw, 2),
+            6: (0, mw, 2)}[variant]
 
 
 def measured_traffic(kernel):
@@ -220,6 +223,7 @@ def bench_batched(steps, nsys=64):
             "gdof_iter_per_s": round(sum(n * i for n, i in zip(ns, its)) / t_batch / 1e9, 4),
             "iterations_min_max": [min(its), max(its)], "fp64_iterations_min_max": [min(its64), max(its64)],
             "worst_true_relres": worst, "status": st, "operator_variants": tune,
+            "launches_per_solve": int(bs.host_array("launches")[0]),
             "setup_s": {"fp64_systems": round(t_setup64, 1), "batched": round(t_setupb, 1)}}
 
 

@@ -176,7 +176,7 @@ void sem_options_default(sem_options *opt);
  * coarse (order 1) operator. Setup also times the element-operator kernel
  * variants on every smoothed level and keeps the fastest per precision
  * (environment: SEMCHEB_AUTOTUNE=0 keeps variant 0, SEMCHEB_AX_VARIANT=v fixes
- * variant v). Errors: SEM_EINVAL (orders, sizes, opt-4th order > 16, variant
+ * variant v). Errors: SEM_EINVAL (orders, sizes, opt-4th order > 32, variant
  * out of range), SEM_EMESH (det J <= 0), SEM_ENOMEM, SEM_EHIP, SEM_ENODEV. */
 sem_status sem_setup_box(const sem_box_mesh *mesh, const sem_options *opt, void *stream,
                          sem_ctx **out);
@@ -296,14 +296,17 @@ sem_status sem_reset_counts(sem_ctx *ctx);
  * "diag", "mass", "coords", "lambda_max", "coarse_matrix" (dense, small
  * problems only), "ax_tuning" (all levels, `level` ignored: per level the
  * chosen FP64 operator variant, the measured time in microseconds of each of
- * the 6 variants (-1 where not timed), then the same for single precision).
+ * the 7 variants (-1 where not timed; variant 6, the r and t contractions on
+ * the matrix cores, exists for BF16 factors at N = 7 only, and FP64 has six),
+ * then the same for single precision).
  * FD contexts: "diag", "matrix" (dense A_j, small problems only), "lambda_max",
  * and the sparse A_j and interpolation P_j (level j+1 -> j; Sec. 3: bilinear
  * interpolation, A_{j+1} = P_j^T A_j P_j) in CSR form as "csr_rowptr", "csr_col",
  * "csr_val", "interp_rowptr", "interp_col", "interp_val" (indices as exact doubles).
- * Batched contexts: "ax_tuning" only, one row per (level, order) of the single-precision cycle
+ * Batched contexts: "ax_tuning", one row per (level, order) of the single-precision cycle
  * operators and per order of the FP64 Krylov operator (level -1): level, order, the chosen
- * variant and the six variants' times in microseconds on the batched launch (-1: not timed).
+ * variant and the six variants' times in microseconds on the batched launch (-1: not timed);
+ * "launches" (n = 1), the number of kernel launches the last sem_solve_batched issued.
  * Returns SEM_EINVAL if `n` does not equal the array size, with the size
  * written to *needed when it is not NULL. */
 sem_status sem_host_array(const sem_ctx *ctx, const char *what, int32_t level, double *out,

@@ -785,7 +785,9 @@ sem_status autotune_operator(sem_ctx *c, hipStream_t s) {
       if (!fp64 && !(mixed && (L.Gbf || L.tri32) && L.w32)) continue;
       if (fp64 && !L.w64) continue;
       const bool trilinear = fp64 ? L.tri64 != nullptr : L.tri32 != nullptr;
-      const int nvar = trilinear ? kAxTriVariants : (fp64 ? kAxVariants64 : kAxVariants);
+      // the matrix-core variant exists for BF16 factors at N = 7 only
+      const int nvar = trilinear ? kAxTriVariants
+                                 : (fp64 ? kAxVariants64 : (L.N == 7 ? kAxVariants : kAxVariantMfma));
       float *times = fp64 ? L.ax_time64_us : L.ax_time32_us;
       for (int v = 0; v < kAxVariants; ++v) times[v] = v < nvar ? 1e30f : -1.0f;
       const double nodes = (double)L.E * (L.N + 1) * (L.N + 1) * (L.N + 1);
@@ -2043,10 +2045,18 @@ sem_status sem_host_array(const sem_ctx *c, const char *what, int32_t j, double 
                           int64_t *needed) {
   if (!c || !what) return SEM_EINVAL;
   if (c->batch) {
-    // batched contexts: "ax_tuning" only, rows (level, order, chosen variant, six timings in us)
-    // for the single-precision cycle operators, level -1 for the FP64 Krylov operator
-    if (std::string(what) != "ax_tuning") return SEM_EINVAL;
+    // batched contexts: "ax_tuning", rows (level, order, chosen variant, six timings in us) for
+    // the single-precision cycle operators, level -1 for the FP64 Krylov operator; "launches",
+    // the number of kernel launches the last batched solve issued
     std::vector<double> tmp;
+    if (std::string(what) == "launches") {
+      tmp.push_back((double)c->batch->last_launches);
+      if (needed) *needed = 1;
+      if (n != 1 || !out) return SEM_EINVAL;
+      out[0] = tmp[0];
+      return SEM_OK;
+    }
+    if (std::string(what) != "ax_tuning") return SEM_EINVAL;
     auto row = [&](int lev, int N, int v, const std::vector<double> &t) {
       tmp.push_back(lev);
       tmp.push_back(N);

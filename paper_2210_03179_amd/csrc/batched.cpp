@@ -478,7 +478,10 @@ sem_status sem_solve_batched(sem_ctx *c, const double *b, double *u, double rtol
   if (!c || !c->batch) return SEM_EINVAL;
   if (!b || !u || maxit < 0 || !(rtol >= 0)) { c->err = "invalid batched solve arguments"; return SEM_EINVAL; }
   if (hipSetDevice(c->device) != hipSuccess) { c->err = "hipSetDevice failed"; return SEM_EHIP; }
-  return solve_batched_impl(c, b, u, rtol, maxit, iters, relres, (hipStream_t)stream);
+  const int64_t l0 = batched_launch_count();
+  const sem_status st = solve_batched_impl(c, b, u, rtol, maxit, iters, relres, (hipStream_t)stream);
+  c->batch->last_launches = batched_launch_count() - l0;
+  return st;
 }
 
 }  // extern "C"

@@ -843,6 +843,155 @@ __device__ __forceinline__ void ax_body_dma(unsigned blk, const Box &b, int64_t 
   }
 }
 
+// Single-precision operator at N = 7 with every tensor contraction on the matrix cores:
+// v_mfma_f32_4x4x1f32 runs 16 independent 4x4 outer products per instruction (lane l feeds
+// A[l % 4] and B[l % 4] of block l / 4, and holds row r of its block's output column l % 4 in
+// register r), so one 8 x 8 x 8 product is two instructions per K step with no padding. One
+// element per wave, lane L owning the (i, j) = (L % 8, L / 8) column; register r of
+// accumulator s holds plane k = 4 s + r:
+//   r-derivative  block (j, i-half): rows k, columns i   A = u[k][j][m] (LDS), B = D[i][m]
+//   t-derivative  block (4 columns):  rows k, columns ij  A = D[k][m],          B = u[m] (own)
+// and the transposes the same way with D^T (r) and wt (t) accumulated into one output. No
+// single lane layout lets all three directions be outer products (the s index would be split
+// between lane bits and block bits here), so the s-direction and its transpose run in the
+// transposed layout (lane 8 i + j) and are moved back by one ds_bpermute per value. The
+// vector ALU keeps only the pointwise factor products and the BF16 widening. Factors: the
+// element's BF16 block copied to LDS by DMA as in ax_body_dma.
+typedef float mfma_v4f __attribute__((ext_vector_type(4)));
+
+template <int N>
+__device__ __forceinline__ void ax_body_mfma(unsigned blk, const Box &b, int64_t E, const float *__restrict__ u,
+                                             const uint16_t *__restrict__ G, const float *__restrict__ Dm,
+                                             float *__restrict__ wL) {
+  static_assert(N == 7, "the matrix-core operator covers one 8^3 element per wave");
+  using T = float;
+  constexpr int n1 = 8, n3 = 512;
+  constexpr int kElemBytes = 6 * n3 * 2;
+  __shared__ __align__(16) uint16_t sG[6 * n3];
+  // rows padded to 9 words: the operand reads of a matrix-core instruction (lanes spread over
+  // four planes and eight rows, or four planes and eight columns) then hit 32 distinct banks
+  constexpr int rp = n1 + 1;
+  __shared__ T sD[n1][rp];
+  __shared__ T su[n1][n1][rp];  // u, then (after the forward pass) the r-direction products wr
+  __shared__ T ss[n1][n1][rp];  // s-direction products ws
+  const int L = threadIdx.x;
+  const int i = L & 7, j = L >> 3, q = L & 3;
+  const int64_t e = blk;
+  const bool active = e < E;
+  sD[j][i] = Dm[L];
+  T ureg[n1];
+  int ex = 0, ey = 0, ez = 0;
+  if (active) {
+    const Exyz ec = elem_xyz(b, e);
+    ex = ec.x;
+    ey = ec.y;
+    ez = ec.z;
+  }
+  const int I = ex * N + i, J = ey * N + j;
+  const bool inIJ = active && I >= 1 && I <= b.nx && J >= 1 && J <= b.ny;
+  const int64_t gIJ = (int64_t)(I - 1) + (int64_t)b.nx * (J - 1);
+  const int64_t plane = (int64_t)b.nx * b.ny;
+#pragma unroll
+  for (int k = 0; k < n1; ++k) {
+    const int K = ez * N + k;
+    const bool ok = inIJ && K >= 1 && K <= b.nz;
+    const T v = u[ok ? gIJ + plane * (K - 1) : 0];
+    ureg[k] = ok ? v : T(0);
+  }
+  if (active) {  // the element's factor block -> sG (16 bytes per lane and load)
+    const char *src = reinterpret_cast<const char *>(G + e * 6 * n3);
+    for (int c0 = 0; c0 < kElemBytes / 16; c0 += 64) {
+      const void *gp = src + (int64_t)(c0 + L) * 16;
+      auto *lp = (__attribute__((address_space(3))) void *)(reinterpret_cast<char *>(sG) + c0 * 16);
+      __builtin_amdgcn_global_load_lds(gp, lp, 16, 0, kFactorCpol);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < n1; ++k) su[k][j][i] = ureg[k];
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  // t-derivative: A = D[4s + q][m], B = u[m] of this lane's column
+  mfma_v4f at[2], ar[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    at[s] = mfma_v4f{0.f, 0.f, 0.f, 0.f};
+    ar[s] = mfma_v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int m = 0; m < n1; ++m)
+      at[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(sD[4 * s + q][m], ureg[m], at[s], 0, 0, 0);
+  }
+  // r-derivative: A = u[4s + q][j][m], B = D[i][m]
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int m = 0; m < n1; ++m)
+      ar[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(su[4 * s + q][j][m], sD[i][m], ar[s], 0, 0, 0);
+  // s-derivative: in the transposed lane layout (block (i, j-half): A = u[4s + q][m][L / 8],
+  // B = D[L % 8][m], so lane L' = 8 i + j holds node (i, j)), brought back to lane 8 j + i
+  // by ds_bpermute
+  T us[n1];
+  const int src = 4 * (8 * i + j);  // byte address of the lane holding this lane's node
+  {
+    mfma_v4f as[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      as[s] = mfma_v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int m = 0; m < n1; ++m)
+        as[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(su[4 * s + q][m][j], sD[i][m], as[s], 0, 0, 0);
+    }
+#pragma unroll
+    for (int k = 0; k < n1; ++k)
+      us[k] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(as[k >> 2][k & 3])));
+  }
+  __syncthreads();  // every read of su happened: it now takes wr
+  T wt[n1];
+  const uint16_t *Ge = sG + j * n1 + i;
+#pragma unroll
+  for (int k = 0; k < n1; ++k) {
+    const int qk = k * n1 * n1;
+    const T g0 = bf16_to_float(Ge[0 * n3 + qk]), g1 = bf16_to_float(Ge[1 * n3 + qk]);
+    const T g2 = bf16_to_float(Ge[2 * n3 + qk]), g3 = bf16_to_float(Ge[3 * n3 + qk]);
+    const T g4 = bf16_to_float(Ge[4 * n3 + qk]), g5 = bf16_to_float(Ge[5 * n3 + qk]);
+    const T ur = ar[k >> 2][k & 3], ut = at[k >> 2][k & 3], vs = us[k];
+    su[k][j][i] = g0 * ur + g1 * vs + g2 * ut;
+    ss[k][j][i] = g1 * ur + g3 * vs + g4 * ut;
+    wt[k] = g2 * ur + g4 * vs + g5 * ut;
+  }
+  __syncthreads();
+  // transposes: r (A = wr[4s + q][j][l], B = D[l][i]) and t (A = D[l][4s + q], B = wt[l])
+  // accumulate into one output
+  mfma_v4f ao[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    ao[s] = mfma_v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int l = 0; l < n1; ++l)
+      ao[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(su[4 * s + q][j][l], sD[l][i], ao[s], 0, 0, 0);
+#pragma unroll
+    for (int l = 0; l < n1; ++l)
+      ao[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(sD[l][4 * s + q], wt[l], ao[s], 0, 0, 0);
+  }
+  // s transpose in the transposed lane layout, then back by ds_bpermute
+  mfma_v4f ab[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    ab[s] = mfma_v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int l = 0; l < n1; ++l)
+      ab[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(ss[4 * s + q][l][j], sD[l][i], ab[s], 0, 0, 0);
+  }
+  T sv[n1];
+#pragma unroll
+  for (int k = 0; k < n1; ++k)
+    sv[k] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(ab[k >> 2][k & 3])));
+  if (active) {
+    T *we = wL + e * n3;
+#pragma unroll
+    for (int k = 0; k < n1; ++k) we[k * n1 * n1 + L] = ao[k >> 2][k & 3] + sv[k];
+  }
+}
+
 // FP64 operator at N = 7 (one element per wave) with the factors streamed through a
 // ring of kRing planes in LDS by global-to-LDS DMA: while plane k computes, planes
 // k+1 .. k+kRing-1 are in flight, and no factor lives in registers. A plane is six

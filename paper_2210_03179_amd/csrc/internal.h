@@ -169,13 +169,16 @@ struct Level {
   float *swS32 = nullptr, *swD32 = nullptr, *swY32 = nullptr, *swT32 = nullptr;
   // operator kernel variant per precision, chosen at setup by timing (kAxVariants)
   int ax_variant64 = 0, ax_variant32 = 0;
-  float ax_time64_us[6] = {}, ax_time32_us[6] = {};  // kAxVariants
+  float ax_time64_us[7] = {}, ax_time32_us[7] = {};  // kAxVariants
 };
 constexpr int kGmresScalars = 2 * 32 + 2;  // projections (<= 32), ||w||^2, y (<= 32)
 // variant 5 stages factors by DMA: the whole element block for BF16 factors, a ring of
-// planes for FP64 factors at N = 7 (other FP64 orders launch variant 0 for it)
-constexpr int kAxVariants = 6;
+// planes for FP64 factors at N = 7 (other FP64 orders launch variant 0 for it); variant 6
+// (BF16 factors at N = 7 only; variant 5 elsewhere) runs the contractions on the matrix
+// cores
+constexpr int kAxVariants = 7;
 constexpr int kAxVariants64 = 6;
+constexpr int kAxVariantMfma = 6;
 constexpr int kAxTriVariants = 3;  // trilinear operator: (min_waves | 1 wave per SIMD) x register column, LDS tile
 
 struct CoarseSolver {
@@ -302,4 +305,5 @@ struct sem_batch {
   // the six variants are kept for inspection (-1 where not timed)
   std::map<int, int> var32[semcheb::kBatchLevels], var64;
   std::map<int, std::vector<double>> time32[semcheb::kBatchLevels], time64;
+  int64_t last_launches = 0;  // kernel launches issued by the last batched solve
 };

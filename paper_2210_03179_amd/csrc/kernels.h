@@ -166,6 +166,7 @@ namespace semcheb {
 int batch_ax_elements_per_block(int N);
 // batched operators in variant `variant` (the numbering of the single-system autotuner);
 // false for orders without batched kernels
+int64_t batched_launch_count();
 bool launch_b_ax32(int N, int variant, const LaunchTable &t, const BatchSysDev *sys, int level, int src,
                    hipStream_t s);
 bool launch_b_ax64(int N, int variant, const LaunchTable &t, const BatchSysDev *sys, hipStream_t s);

@@ -10,6 +10,7 @@
 // are bitwise reproducible run to run.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 
 #include "device_ops.h"
@@ -22,13 +23,15 @@ using namespace dev;
 // PF (factor prefetch), OCC (waves per SIMD requested from the register allocator)
 // and TILE (0: u column in registers with one LDS plane, 1: whole u tile in LDS,
 // 2: u tile and the element's BF16 factors in LDS, single precision only; 3: u tile and a
-// ring of FP64 factor planes in LDS, N = 7 only).
+// ring of FP64 factor planes in LDS, N = 7 only; 4: as 2 with every contraction on the
+// matrix cores, BF16 factors at N = 7 only).
 // pdot (FP64 variants, optional): per-block partials of u . A_L u (see ax_body).
 template <int N, typename T, typename GT, int PF, int OCC, int TILE = 0>
 __global__ void __launch_bounds__(AxShape<N>::block, OCC)
 ax_local_kernel(Box b, int64_t E, const T *__restrict__ u, const GT *__restrict__ G,
                 const T *__restrict__ Dm, T *__restrict__ wL, double *__restrict__ pdot) {
-  if constexpr (TILE == 3) ax_body_ring64<N>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL, pdot);
+  if constexpr (TILE == 4) ax_body_mfma<N>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
+  else if constexpr (TILE == 3) ax_body_ring64<N>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL, pdot);
   else if constexpr (TILE == 2) ax_body_dma<N>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
   else if constexpr (TILE == 1)
     ax_body_tile<N, T, GT, PF>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL, pdot);
@@ -1475,8 +1478,15 @@ void launch_ax_n(const Level &L, const T *u, const GT *G, const T *D, T *wL, int
       return;
     }
   }
+  if constexpr (sizeof(GT) == 2 && N == 7) {
+    if (variant == 6) {
+      hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, S::min_waves, 4>), dim3(grid), dim3(S::block), 0, s,
+                         mkbox(L), L.E, u, G, D, wL, pdot);
+      return;
+    }
+  }
   if constexpr (sizeof(GT) == 2) {
-    if (variant == 5) {
+    if (variant >= 5) {
       hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, S::min_waves, 2>), dim3(grid), dim3(S::block), 0, s,
                          mkbox(L), L.E, u, G, D, wL, pdot);
       return;
@@ -1998,9 +2008,14 @@ int batch_ax_elements_per_block(int N) {
 }
 
 // batched orders: finest levels 4..12, the level below 2..6 (the order-1 level is solved densely)
+// batched kernel launches issued so far (all contexts; a batched solve reports the difference)
+std::atomic<int64_t> g_batched_launches{0};
+int64_t batched_launch_count() { return g_batched_launches.load(); }
+
 bool launch_b_ax32(int N, int variant, const LaunchTable &t, const BatchSysDev *sys, int level, int src,
                    hipStream_t s) {
   if (t.count == 0) return true;
+  ++g_batched_launches;
   switch (N) {
 #define SEMCHEB_BAX(n) \
   case n: b_ax32_n<n>(t, sys, level, src, variant, s); return true;
@@ -2013,6 +2028,7 @@ bool launch_b_ax32(int N, int variant, const LaunchTable &t, const BatchSysDev *
 
 bool launch_b_ax64(int N, int variant, const LaunchTable &t, const BatchSysDev *sys, hipStream_t s) {
   if (t.count == 0) return true;
+  ++g_batched_launches;
   switch (N) {
 #define SEMCHEB_BAX(n) \
   case n: b_ax64_n<n>(t, sys, variant, s); return true;
@@ -2025,41 +2041,76 @@ bool launch_b_ax64(int N, int variant, const LaunchTable &t, const BatchSysDev *
 
 void launch_b_cheb(const LaunchTable &t, const BatchSysDev *sys, int level, int pp, int step, int flags, int mode,
                    hipStream_t s) {
-  if (t.count) hipLaunchKernelGGL(b_cheb_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, level, pp, step, flags, mode);
+  if (t.count) {
+    ++g_batched_launches;
+    hipLaunchKernelGGL(b_cheb_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, level, pp, step, flags, mode);
+  }
 }
 void launch_b_resid(const LaunchTable &t, const BatchSysDev *sys, int level, int has_w, hipStream_t s) {
-  if (t.count) hipLaunchKernelGGL(b_resid_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, level, has_w);
+  if (t.count) {
+    ++g_batched_launches;
+    hipLaunchKernelGGL(b_resid_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, level, has_w);
+  }
 }
 void launch_b_restrict(const LaunchTable &t, const BatchSysDev *sys, int level, size_t lds, hipStream_t s) {
-  if (t.count) hipLaunchKernelGGL(b_restrict_kernel, dim3(tgrid(t)), dim3(128), lds, s, t, sys, level);
+  if (t.count) {
+    ++g_batched_launches;
+    hipLaunchKernelGGL(b_restrict_kernel, dim3(tgrid(t)), dim3(128), lds, s, t, sys, level);
+  }
 }
 void launch_b_dss(const LaunchTable &t, const BatchSysDev *sys, int level, hipStream_t s) {
-  if (t.count) hipLaunchKernelGGL(b_dss_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, level);
+  if (t.count) {
+    ++g_batched_launches;
+    hipLaunchKernelGGL(b_dss_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, level);
+  }
 }
 void launch_b_prolong(const LaunchTable &t, const BatchSysDev *sys, int level, int to_z, size_t lds, hipStream_t s) {
-  if (t.count) hipLaunchKernelGGL(b_prolong_kernel, dim3(tgrid(t)), dim3(128), lds, s, t, sys, level, to_z);
+  if (t.count) {
+    ++g_batched_launches;
+    hipLaunchKernelGGL(b_prolong_kernel, dim3(tgrid(t)), dim3(128), lds, s, t, sys, level, to_z);
+  }
 }
 void launch_b_convert(const LaunchTable &t, const BatchSysDev *sys, int op, int par, hipStream_t s) {
-  if (t.count) hipLaunchKernelGGL(b_convert_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, op, par);
+  if (t.count) {
+    ++g_batched_launches;
+    hipLaunchKernelGGL(b_convert_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, op, par);
+  }
 }
 void launch_b_coarse(const LaunchTable &t, const BatchSysDev *sys, hipStream_t s) {
-  if (t.count) hipLaunchKernelGGL(b_coarse_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys);
+  if (t.count) {
+    ++g_batched_launches;
+    hipLaunchKernelGGL(b_coarse_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys);
+  }
 }
 void launch_b_dssdot(const LaunchTable &t, const BatchSysDev *sys, double *partials, hipStream_t s) {
-  if (t.count) hipLaunchKernelGGL(b_dssdot_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, partials);
+  if (t.count) {
+    ++g_batched_launches;
+    hipLaunchKernelGGL(b_dssdot_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, partials);
+  }
 }
 void launch_b_finalize(const LaunchTable &t, const BatchSysDev *sys, const double *partials, int nd, int slot, int op,
                        hipStream_t s) {
-  if (t.count)
+  if (t.count) {
+    ++g_batched_launches;
     hipLaunchKernelGGL(b_finalize_kernel, dim3((unsigned)t.count), dim3(256), 0, s, t, sys, partials, nd, slot, op);
+  }
 }
 void launch_b_update_xr(const LaunchTable &t, const BatchSysDev *sys, int par, double *partials, hipStream_t s) {
-  if (t.count) hipLaunchKernelGGL(b_update_xr_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, par, partials);
+  if (t.count) {
+    ++g_batched_launches;
+    hipLaunchKernelGGL(b_update_xr_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, par, partials);
+  }
 }
 void launch_b_dots(const LaunchTable &t, const BatchSysDev *sys, int par, int what, double *partials, hipStream_t s) {
-  if (t.count) hipLaunchKernelGGL(b_dots_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, par, what, partials);
+  if (t.count) {
+    ++g_batched_launches;
+    hipLaunchKernelGGL(b_dots_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, par, what, partials);
+  }
 }
 void launch_b_vec(const LaunchTable &t, const BatchSysDev *sys, int op, hipStream_t s) {
-  if (t.count) hipLaunchKernelGGL(b_vec_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, op);
+  if (t.count) {
+    ++g_batched_launches;
+    hipLaunchKernelGGL(b_vec_kernel, dim3(tgrid(t)), dim3(256), 0, s, t, sys, op);
+  }
 }
 }  // namespace semcheb

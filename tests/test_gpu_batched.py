@@ -70,6 +70,10 @@ def test_batched_zero_rhs_and_errors():
     u, st, its, rel = bs.solve(b)
     assert st == L.SEM_OK and its[0] == 0 and its[2] == 0 and its[1] > 0
     assert float(u[bs.offsets[0]:bs.offsets[1]].abs().max()) == 0.0
+    # the launch count of a solve is reported and repeats for the same input
+    n1 = int(bs.host_array("launches")[0])
+    bs.solve(b)
+    assert n1 > 0 and int(bs.host_array("launches")[0]) == n1
     with pytest.raises(L.SemError):
         BatchedSolver([specs[0][0]], [3])  # order 3 has only two levels
 

@@ -48,7 +48,7 @@ def test_apply_A_parity(m, N):
     assert relmax(w, box.apply(u)) < 1e-14 * (N + 1) ** 2
 
 
-@pytest.mark.parametrize("variant", range(6))
+@pytest.mark.parametrize("variant", range(7))
 @pytest.mark.parametrize("N", [2, 3, 4, 5, 7, 9])
 def test_operator_variants_parity(N, variant, monkeypatch):
     # every operator kernel variant the autotuner may pick, FP64 and FP32/BF16, against the oracle
@@ -447,3 +447,21 @@ def test_fused_krylov_apply_matches_separate_pass(cfg2, precision, monkeypatch):
     assert i1.iterations == i2.iterations
     assert np.max(np.abs(i1.history - i2.history)) <= tol * np.linalg.norm(b)
     assert np.linalg.norm(host(u1) - host(u2)) <= 10 * tol * np.linalg.norm(host(u2))
+
+
+def test_matrix_core_operator_matches_vector_variant(monkeypatch):
+    """The BF16 operator with its contractions on the matrix cores (variant 6, N = 7) against
+    the vector-ALU variant with the same BF16 factors in LDS (variant 5): the
+    same FP32 products summed in another order, so element by element within a few FP32
+    rounding units of the largest entry; 5 x 4 x 3 elements, all boundary cases."""
+    V = wl.deformed_box((5, 4, 3), 0.07)
+    u = dev(wl.uniform_noise(SemBox(V, 7).n, 21)).float()
+    out = {}
+    for v in (5, 6):
+        monkeypatch.setenv("SEMCHEB_AX_VARIANT", str(v))
+        s = SemSolver(V, N=7, lambda_max=[1.0] * 3, precision="mixed")
+        out[v] = s.apply_local(u).double().cpu().numpy()
+        s.close()
+    d = relmax(out[6], out[5])
+    print(f"matrix-core vs vector BF16 operator: max rel {d:.2e}", flush=True)
+    assert d < 2e-6
