@@ -945,9 +945,9 @@ dots_kernel(int64_t n, int nd, const T *__restrict__ x0, const T *__restrict__ y
 // Sum over b = threadIdx.x, +blockDim.x, ... < nblocks of partials[b*nd + q], in that order,
 // with eight loads in flight per round instead of one (reductions with tens of thousands of
 // partials are otherwise a chain of dependent memory latencies).
+template <int kRound = 8>
 __device__ __forceinline__ double strided_partial_sum(const double *__restrict__ partials, int nblocks, int nd,
                                                       int q) {
-  constexpr int kRound = 8;
   double a = 0.0;
   for (int b0 = threadIdx.x; b0 < nblocks; b0 += kRound * blockDim.x) {
     double v[kRound];
@@ -963,16 +963,26 @@ __device__ __forceinline__ double strided_partial_sum(const double *__restrict__
 }
 
 // out[slot + q] = sum_b partials[b*nd + q], fixed order; then an optional scalar
-// step for the Krylov recurrences (see finalize_op).
-__global__ void __launch_bounds__(256)
+// step for the Krylov recurrences (see finalize_op). One block of 1024 threads, each loading
+// 16 partials per round: the 32,768 partials of the FP64 operator's p.Ap take two dependent
+// rounds (256 threads with 8 per round took 16, about 8 us).
+constexpr int kFinThreads = 1024;
+__global__ void __launch_bounds__(kFinThreads)
 finalize_kernel(int nblocks, int nd, const double *__restrict__ partials, double *__restrict__ scal,
                 int slot, int op) {
-  __shared__ double sm[4];
+  __shared__ double sm[kFinThreads / 64];
   __shared__ double res[3];
   for (int q = 0; q < nd; ++q) {
-    const double a = strided_partial_sum(partials, nblocks, nd, q);
-    const double s = block_sum(a, sm);
-    if (threadIdx.x == 0) res[q] = s;
+    double v = strided_partial_sum<16>(partials, nblocks, nd, q);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kFinThreads / 64; ++w) t += sm[w];
+      res[q] = t;
+    }
+    __syncthreads();
   }
   if (threadIdx.x != 0) return;
   for (int q = 0; q < nd; ++q) scal[slot + q] = res[q];
@@ -1862,7 +1872,7 @@ template void launch_dots<double>(int64_t, int, const double *, const double *, 
 
 void launch_finalize(int nblocks, int nd, const double *partials, double *scal, int slot, int op,
                      hipStream_t s) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, nblocks, nd, partials, scal, slot, op);
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, s, nblocks, nd, partials, scal, slot, op);
 }
 
 
