@@ -305,13 +305,17 @@ void smooth(const sem_ctx *c, Level &L, int k, bool zero_guess, hipStream_t s) {
     const double *beta = kind == SEM_CHEB4_OPT ? beta_row(k) : nullptr;
     auto B = [&](int i) { return beta ? beta[i - 1] : 1.0; };  // beta_i, 1-based
     const double c0 = (4.0 / 3.0) * (1.0 / lmax);
+    // from a zero guess the first step stores no x when a second step follows (x = B(1) d,
+    // formed there from d)
+    const int nox = zero_guess && k > 1 ? CHEB_NO_X : 0;
+    const int last0 = k == 1 ? CHEB_LAST : 0;  // the last step stores only x
     if (zero_guess) {
       launch_cheb<T>(L, nullptr, b, nullptr, nullptr, d, x, inv, 0.0, c0, B(1),
-                     CHEB_R_FROM_B | CHEB_D_INIT | CHEB_X_INIT, 4, s);
+                     CHEB_R_FROM_B | CHEB_D_INIT | CHEB_X_INIT | nox | last0, 4, s);
     } else {
       apply_level<T>(L, x, w, s);
       launch_cheb<T>(L, w, b, nullptr, r, d, x, inv, 0.0, c0, B(1),
-                     CHEB_R_FROM_B | CHEB_SUB_AD | CHEB_D_INIT | CHEB_WRITE_R, 4, s);
+                     CHEB_R_FROM_B | CHEB_SUB_AD | CHEB_D_INIT | CHEB_WRITE_R | last0, 4, s);
     }
     for (int i = 1; i < k; ++i) {
       apply_level<T>(L, d, w, s);
@@ -319,7 +323,9 @@ void smooth(const sem_ctx *c, Level &L, int k, bool zero_guess, hipStream_t s) {
       const double a = (2.0 * i - 1.0) / (2.0 * i + 3.0);
       const double bc = ((8.0 * i + 4.0) / (2.0 * i + 3.0)) * (1.0 / lmax);
       launch_cheb<T>(L, w, b, r, r, d, x, inv, a, bc, B(i + 1),
-                     CHEB_SUB_AD | CHEB_WRITE_R | (from_b ? CHEB_R_FROM_B : 0), 4, s);
+                     CHEB_SUB_AD | CHEB_WRITE_R | (from_b ? CHEB_R_FROM_B | (nox ? CHEB_X_FROM_D : 0) : 0) |
+                         (i == k - 1 ? CHEB_LAST : 0),
+                     4, s, B(1));
     }
   } else {
     const double frac = kind == SEM_CHEB1 ? 0.1 : 1.69 / (std::pow((double)k, 1.68) + 2.11 * k + 1.98);
@@ -327,19 +333,22 @@ void smooth(const sem_ctx *c, Level &L, int k, bool zero_guess, hipStream_t s) {
     const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
     const double sigma = theta / delta;
     double rho = 1.0 / sigma;
+    const int nox = zero_guess && k > 1 ? CHEB_NO_X : 0;  // x = d after the first step
+    const int last0 = k == 1 ? CHEB_LAST : 0;
     if (zero_guess) {
       launch_cheb<T>(L, nullptr, b, nullptr, r, d, x, inv, 0.0, 1.0 / theta, 1.0,
-                     CHEB_R_FROM_B | CHEB_S_ON_R | CHEB_D_INIT | CHEB_X_INIT | CHEB_WRITE_R, 1, s);
+                     CHEB_R_FROM_B | CHEB_S_ON_R | CHEB_D_INIT | CHEB_X_INIT | CHEB_WRITE_R | nox | last0, 1, s);
     } else {
       apply_level<T>(L, x, w, s);
       launch_cheb<T>(L, w, b, nullptr, r, d, x, inv, 0.0, 1.0 / theta, 1.0,
-                     CHEB_R_FROM_B | CHEB_S_ON_R | CHEB_SUB_AD | CHEB_D_INIT | CHEB_WRITE_R, 1, s);
+                     CHEB_R_FROM_B | CHEB_S_ON_R | CHEB_SUB_AD | CHEB_D_INIT | CHEB_WRITE_R | last0, 1, s);
     }
     for (int i = 1; i < k; ++i) {
       apply_level<T>(L, d, w, s);
       const double rho_new = 1.0 / (2.0 * sigma - rho);
       launch_cheb<T>(L, w, b, r, r, d, x, inv, rho_new * rho, 2.0 * rho_new / delta, 1.0,
-                     CHEB_SUB_AD | CHEB_WRITE_R, 1, s);
+                     CHEB_SUB_AD | CHEB_WRITE_R | (i == 1 && nox ? CHEB_X_FROM_D : 0) | (i == k - 1 ? CHEB_LAST : 0),
+                     1, s, 1.0);
       rho = rho_new;
     }
   }

@@ -153,11 +153,16 @@ void smooth_b(const sem_ctx *c, const Tables &T, const BatchSysDev *d, int j, in
     f0 = zero_guess ? (CHEB_R_FROM_B | CHEB_S_ON_R | CHEB_D_INIT | CHEB_X_INIT | CHEB_WRITE_R)
                     : (CHEB_R_FROM_B | CHEB_S_ON_R | CHEB_SUB_AD | CHEB_D_INIT | CHEB_WRITE_R);
   }
+  // from a zero guess the first step stores no x when a second follows (the kernel forms
+  // x = c_0 d there from the direction it reads)
+  // and the last step stores only x (the residual that follows is formed from x)
+  const int nox = zero_guess && k > 1 ? CHEB_NO_X : 0;
   if (!zero_guess) ax(1);
-  launch_b_cheb(T.node4[j], d, j, pp, 0, f0, mode, s);
+  launch_b_cheb(T.node4[j], d, j, pp, 0, f0 | nox | (k == 1 ? CHEB_LAST : 0), mode, s);
   for (int i = 1; i < k; ++i) {
     ax(0);
-    const int f = CHEB_SUB_AD | CHEB_WRITE_R | ((mode == 4 && zero_guess && i == 1) ? CHEB_R_FROM_B : 0);
+    const int f = CHEB_SUB_AD | CHEB_WRITE_R | ((mode == 4 && zero_guess && i == 1) ? CHEB_R_FROM_B : 0) |
+                  (nox && i == 1 ? CHEB_X_FROM_D : 0) | (i == k - 1 ? CHEB_LAST : 0);
     launch_b_cheb(T.node4[j], d, j, pp, i, f, mode, s);
   }
 }

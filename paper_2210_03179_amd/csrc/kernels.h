@@ -17,7 +17,10 @@ enum {
   CHEB_WRITE_R = 8,   // store the updated residual
   CHEB_D_INIT = 16,   // previous direction is zero
   CHEB_X_INIT = 32,   // previous iterate is zero
-  CHEB_R_ONLY = 64    // only form and store the residual (a non-diagonal smoother follows)
+  CHEB_R_ONLY = 64,   // only form and store the residual (a non-diagonal smoother follows)
+  CHEB_NO_X = 128,     // do not store x (the first step from a zero guess: x = c d is implied)
+  CHEB_X_FROM_D = 256, // previous iterate is cprev * (previous direction), x is not read
+  CHEB_LAST = 512      // last step of a smoothing: r and d are not read again, store only x
 };
 // Schwarz smoother modes of the fused gather (Chebyshev recurrences of Algorithms 1 and 2
 // with z = S v in place of diag(A)^{-1} r)
@@ -65,7 +68,8 @@ int launch_dss_dot(const Level &L, const double *wL, double *out, const double *
                    hipStream_t s);
 template <typename T>
 void launch_cheb(const Level &L, const T *wsrc, const T *b, const T *r_in, T *r_out, T *d, T *x,
-                 const T *invdiag, double a, double bc, double c, int flags, int mode, hipStream_t s);
+                 const T *invdiag, double a, double bc, double c, int flags, int mode, hipStream_t s,
+                 double cprev = 0.0);
 template <typename T>
 void launch_resid_weight(const Level &L, const T *wL, const T *b, T *rw, hipStream_t s);
 template <typename T>

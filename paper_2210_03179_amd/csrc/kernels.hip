@@ -205,13 +205,18 @@ dss_dot_kernel(Box b, int64_t n, const T *__restrict__ wL, T *__restrict__ out,
 //   rr = R_FROM_B ? b : r_in;  if S_ON_R: rr *= invdiag
 //   if SUB_AD:  rr -= (mode 1 ? invdiag * Ad : Ad)
 //   dd = (D_INIT ? 0 : d) * a + bc * (mode 4 ? invdiag * rr : rr)
-//   x  = (X_INIT ? 0 : x) + c * dd
+//   x  = (X_INIT ? 0 : X_FROM_D ? cprev * d : x) + c * dd   (not stored with NO_X)
+// A smoother started from a zero guess stores no x in its first step (x = c d there) and
+// forms it in the second from the direction it reads anyway: the same products, so the
+// same results, with one vector write and one read less. The last step of a smoothing
+// stores only x (LAST): the residual that follows is formed from x.
 // One thread updates VEC unknowns spaced a wavefront apart (see strided_first).
 template <typename T, bool SEM, int VEC>
 __device__ __forceinline__ void cheb_body(unsigned blk, const Box &b, int64_t n, const T *__restrict__ wsrc,
                                           const T *__restrict__ bvec, const T *__restrict__ r_in,
                                           T *__restrict__ r_out, T *__restrict__ d, T *__restrict__ x,
-                                          const T *__restrict__ invdiag, T a, T bc, T c, int flags, int mode) {
+                                          const T *__restrict__ invdiag, T a, T bc, T c, int flags, int mode,
+                                          T cprev = T(0)) {
   const int64_t g0 = strided_first<VEC>(blk);
   if (g0 >= n) return;
   const T *rsrc = (flags & CHEB_R_FROM_B) ? bvec : r_in;
@@ -223,7 +228,7 @@ __device__ __forceinline__ void cheb_body(unsigned blk, const Box &b, int64_t n,
     sv[q] = (ok && !(flags & CHEB_R_ONLY)) ? invdiag[g] : T(0);
     rr[q] = ok ? rsrc[g] : T(0);
     dd[q] = (ok && !(flags & CHEB_D_INIT)) ? d[g] : T(0);
-    xx[q] = (ok && !(flags & CHEB_X_INIT)) ? x[g] : T(0);
+    xx[q] = (ok && !(flags & (CHEB_X_INIT | CHEB_X_FROM_D))) ? x[g] : T(0);
     ad[q] = (!SEM && ok && (flags & CHEB_SUB_AD)) ? wsrc[g] : T(0);
   }
   if (SEM && (flags & CHEB_SUB_AD)) {
@@ -249,12 +254,17 @@ __device__ __forceinline__ void cheb_body(unsigned blk, const Box &b, int64_t n,
     if (flags & CHEB_SUB_AD) r = (mode == 1) ? r - sv[q] * ad[q] : r - ad[q];
     T dn = (flags & CHEB_D_INIT) ? T(0) : a * dd[q];
     dn = dn + bc * (mode == 4 ? sv[q] * r : r);
-    const T xn = ((flags & CHEB_X_INIT) ? T(0) : xx[q]) + c * dn;
+    // cprev * d rounded on its own, as the first step's x was (no contraction into the fma below)
+    T xd;
+    if constexpr (sizeof(T) == 8) xd = __dmul_rn(cprev, dd[q]);
+    else xd = __fmul_rn(cprev, dd[q]);
+    const T xp = (flags & CHEB_X_INIT) ? T(0) : (flags & CHEB_X_FROM_D) ? xd : xx[q];
+    const T xn = xp + c * dn;
     const int64_t g = g0 + 64 * q;
     if (g < n) {
-      if (flags & CHEB_WRITE_R) r_out[g] = r;
-      d[g] = dn;
-      x[g] = xn;
+      if ((flags & CHEB_WRITE_R) && !(flags & CHEB_LAST)) r_out[g] = r;
+      if (!(flags & CHEB_LAST)) d[g] = dn;
+      if (!(flags & CHEB_NO_X)) x[g] = xn;
     }
   }
 }
@@ -264,8 +274,8 @@ __global__ void __launch_bounds__(256)
 cheb_kernel(Box b, int64_t n, const T *__restrict__ wsrc, const T *__restrict__ bvec,
             const T *__restrict__ r_in, T *__restrict__ r_out, T *__restrict__ d,
             T *__restrict__ x, const T *__restrict__ invdiag, T a, T bc, T c, int flags,
-            int mode) {
-  cheb_body<T, SEM, VEC>(blockIdx.x, b, n, wsrc, bvec, r_in, r_out, d, x, invdiag, a, bc, c, flags, mode);
+            int mode, T cprev) {
+  cheb_body<T, SEM, VEC>(blockIdx.x, b, n, wsrc, bvec, r_in, r_out, d, x, invdiag, a, bc, c, flags, mode, cprev);
 }
 
 // rw = (b - DSS(wL)) / multiplicity  (or b / multiplicity when wL is null): the
@@ -1312,8 +1322,9 @@ b_cheb_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, int level, i
   SEMCHEB_BATCH_SYS
   const BatchLevelDev &L = S.lev[level];
   const double *cf = L.coef[pp][step];
+  const float cprev = step > 0 ? (float)L.coef[pp][step - 1][2] : 0.0f;  // used with CHEB_X_FROM_D
   cheb_body<float, true, 4>(blk, lbox(L), L.n, L.w, L.b, L.r, L.r, L.d, L.x, L.inv, (float)cf[0], (float)cf[1],
-                            (float)cf[2], flags, mode);
+                            (float)cf[2], flags, mode, cprev);
 }
 
 __global__ void __launch_bounds__(256)
@@ -1698,30 +1709,32 @@ int launch_dss_dot(const Level &L, const double *wL, double *out, const double *
 
 template <typename T, int VEC>
 void launch_cheb_v(const Level &L, const T *wsrc, const T *b, const T *r_in, T *r_out, T *d, T *x,
-                   const T *invdiag, double a, double bc, double c, int flags, int mode, hipStream_t s) {
+                   const T *invdiag, double a, double bc, double c, int flags, int mode, hipStream_t s,
+                   double cprev) {
   const unsigned grid = nblk((L.n + VEC - 1) / VEC);
   if (L.type == LVL_SEM)
     hipLaunchKernelGGL((cheb_kernel<T, true, VEC>), dim3(grid), dim3(256), 0, s, mkbox(L), L.n, wsrc, b, r_in,
-                       r_out, d, x, invdiag, (T)a, (T)bc, (T)c, flags, mode);
+                       r_out, d, x, invdiag, (T)a, (T)bc, (T)c, flags, mode, (T)cprev);
   else
     hipLaunchKernelGGL((cheb_kernel<T, false, VEC>), dim3(grid), dim3(256), 0, s, mkbox(L), L.n, wsrc, b, r_in,
-                       r_out, d, x, invdiag, (T)a, (T)bc, (T)c, flags, mode);
+                       r_out, d, x, invdiag, (T)a, (T)bc, (T)c, flags, mode, (T)cprev);
 }
 
 template <typename T>
 void launch_cheb(const Level &L, const T *wsrc, const T *b, const T *r_in, T *r_out, T *d, T *x,
-                 const T *invdiag, double a, double bc, double c, int flags, int mode, hipStream_t s) {
+                 const T *invdiag, double a, double bc, double c, int flags, int mode, hipStream_t s,
+                 double cprev) {
   // 16-byte packs need every streamed vector 16-byte aligned (device allocations are)
   const bool ok = al16(b) && al16(r_in) && al16(r_out) && al16(d) && al16(x) && al16(invdiag) &&
                   (L.type == LVL_SEM || al16(wsrc));
-  if (ok) launch_cheb_v<T, 16 / sizeof(T)>(L, wsrc, b, r_in, r_out, d, x, invdiag, a, bc, c, flags, mode, s);
-  else launch_cheb_v<T, 1>(L, wsrc, b, r_in, r_out, d, x, invdiag, a, bc, c, flags, mode, s);
+  if (ok) launch_cheb_v<T, 16 / sizeof(T)>(L, wsrc, b, r_in, r_out, d, x, invdiag, a, bc, c, flags, mode, s, cprev);
+  else launch_cheb_v<T, 1>(L, wsrc, b, r_in, r_out, d, x, invdiag, a, bc, c, flags, mode, s, cprev);
 }
 template void launch_cheb<double>(const Level &, const double *, const double *, const double *, double *,
                                   double *, double *, const double *, double, double, double, int, int,
-                                  hipStream_t);
+                                  hipStream_t, double);
 template void launch_cheb<float>(const Level &, const float *, const float *, const float *, float *, float *,
-                                 float *, const float *, double, double, double, int, int, hipStream_t);
+                                 float *, const float *, double, double, double, int, int, hipStream_t, double);
 
 template <typename T>
 void launch_resid_weight(const Level &L, const T *wL, const T *b, T *rw, hipStream_t s) {
