@@ -1934,6 +1934,34 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
   // (SEMCHEB_FUSED_KRYLOV=0 in the environment keeps the separate summation pass)
   const char *fk = std::getenv("SEMCHEB_FUSED_KRYLOV");
   const bool fused = L0.type == LVL_SEM && !L0.tri64 && L0.G64 && !(fk && fk[0] == '0');
+  // One step of lookahead: the next preconditioner application and the direction update are
+  // queued before the host waits for this iteration's scalars, so the GPU does not idle while
+  // the host checks convergence. If the iteration turns out to be the last, the queued update
+  // has applied x += alpha p, which was due anyway, and the new p is not used. The lookahead
+  // is skipped when the last reduction rate predicts convergence within a factor of 4 (a
+  // wasted cycle would cost more than the waits it saves); the results are the same either way.
+  struct EventGuard {
+    hipEvent_t e = nullptr;
+    ~EventGuard() {
+      if (e) hipEventDestroy(e);
+    }
+  } sev;
+  HIPCHK(c, hipEventCreateWithFlags(&sev.e, hipEventDisableTiming));
+  double rn_prev = bnorm, rate = 1.0;  // last residual norm and reduction factor
+  // z = M r with z . r (and z . r_old for the flexible beta), reduced inside the cycle when it
+  // can; then beta, x += alpha p and p = z + beta p
+  auto next_direction = [&]() -> sem_status {
+    int zb = 0;
+    TRY(vcycle_replay(c, r, z, s, mixed, r, flexible ? r2 : nullptr, &zb));
+    if (zb == 0) {
+      if (flexible) launch_dots<double>(n, 2, z, r, z, r2, nullptr, nullptr, c->partials, kReduceBlocks, s);
+      else launch_dots<double>(n, 1, z, r, nullptr, nullptr, nullptr, nullptr, c->partials, kReduceBlocks, s);
+      zb = kReduceBlocks;
+    }
+    launch_finalize(zb, flexible ? 2 : 1, c->partials, c->scal, S_ZR, flexible ? FIN_BETA_FCG : FIN_BETA_PCG, s);
+    launch_update_xp(n, c->scal, u, z, p, s);
+    return SEM_OK;
+  };
   for (it = 1; it <= maxit; ++it) {
     if (fused) {
       L0.applies++;
@@ -1948,7 +1976,15 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
       launch_finalize(kReduceBlocks, 1, c->partials, c->scal, S_RR, FIN_NONE, s);
     }
     x_pending = true;
-    TRY(read_scalars(c, s));
+    HIPCHK(c, hipMemcpyAsync(c->pinned, c->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipEventRecord(sev.e, s));
+    std::swap(r, r2);  // r: new residual, r2: previous residual
+    const bool ahead = it < maxit && rn_prev * rate > 4.0 * rtol * bnorm;
+    if (ahead) {
+      TRY(next_direction());
+      x_pending = false;
+    }
+    HIPCHK(c, hipEventSynchronize(sev.e));
     const double rz = c->pinned[S_RZ], pw = c->pinned[S_PW], rr = c->pinned[S_RR];
     if (!std::isfinite(rr) || !std::isfinite(pw) || !std::isfinite(rz)) {
       c->err = "non-finite value in the Krylov iteration";
@@ -1960,7 +1996,6 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
       status = SEM_EBREAKDOWN;
       break;
     }
-    std::swap(r, r2);  // r: new residual, r2: previous residual
     rn = std::sqrt(rr);
     if (history) history[it] = rn;
     if (iters) *iters = it;
@@ -1970,17 +2005,12 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
       break;
     }
     if (it == maxit) break;
-    // z . r (and z . r_old for the flexible beta), reduced inside the cycle when it can
-    int zb = 0;
-    TRY(vcycle_replay(c, r, z, s, mixed, r, flexible ? r2 : nullptr, &zb));
-    if (zb == 0) {
-      if (flexible) launch_dots<double>(n, 2, z, r, z, r2, nullptr, nullptr, c->partials, kReduceBlocks, s);
-      else launch_dots<double>(n, 1, z, r, nullptr, nullptr, nullptr, nullptr, c->partials, kReduceBlocks, s);
-      zb = kReduceBlocks;
+    rate = std::min(1.0, rn / rn_prev);
+    rn_prev = rn;
+    if (!ahead) {  // the cycle and direction update after the check
+      TRY(next_direction());
+      x_pending = false;
     }
-    launch_finalize(zb, flexible ? 2 : 1, c->partials, c->scal, S_ZR, flexible ? FIN_BETA_FCG : FIN_BETA_PCG, s);
-    launch_update_xp(n, c->scal, u, z, p, s);  // x += alpha p, p = z + beta p
-    x_pending = false;
   }
   if (x_pending) launch_update_x(n, c->scal, u, p, s);
   HIPCHK(c, hipStreamSynchronize(s));

@@ -870,59 +870,69 @@ struct GemvJobs {
 // loads of the row in flight and the row sum is a fixed-order wave reduction
 // (no LDS, no barrier).
 constexpr int kRowUnroll = 16;
+// Each wave takes RPW consecutive rows of one job (the job's last wave may have fewer): the
+// x values a lane loads for one chunk of columns serve all of its rows, so x is read from
+// L2 once per RPW rows, and a lane keeps RPW * kRowUnroll matrix loads in flight.
+template <int RPW>
 __global__ void __launch_bounds__(256) gemv_jobs_kernel(const GemvJobs J) {
   const int lane = threadIdx.x & 63;
-  int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t total = J.job[0].nrows + (J.njobs > 1 ? J.job[1].nrows : 0);
-  if (row >= total) return;
-  const bool second = J.njobs > 1 && row >= J.job[0].nrows;  // wave-uniform
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t w0 = (J.job[0].nrows + RPW - 1) / RPW;
+  const int64_t w1 = J.njobs > 1 ? (J.job[1].nrows + RPW - 1) / RPW : 0;
+  if (wave >= w0 + w1) return;
+  const bool second = wave >= w0;  // wave-uniform
   const GemvJob jb = second ? J.job[1] : J.job[0];
-  if (second) row -= J.job[0].nrows;
-  double acc = 0.0;
+  const int64_t row0 = (second ? wave - w0 : wave) * RPW;
+  const int nr = (int)(jb.nrows - row0 < RPW ? jb.nrows - row0 : RPW);  // rows of this wave, wave-uniform
+  double acc[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) acc[r] = 0.0;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     if (q >= jb.nseg) break;
     const GemvSeg g = jb.seg[q];
     const int64_t last = g.ncols - 1;
-    double part = 0.0;
+    double part[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) part[r] = 0.0;
     // loads are unconditional (past the end: the row's last entry, weighted by 0 when
-    // summed) so a whole chunk of the row is in flight without a branch or wait per load;
-    // the factor blocks are streamed once per solve (non-temporal), x is shared by all rows
-    if (g.M32) {  // wave-uniform: single-precision storage, double products and sums
-      const float *Mr = g.M32 + row * g.ncols;
+    // summed; a missing row of the last wave re-reads the wave's first row, unused) so a
+    // whole chunk is in flight without a branch or wait per load; the factor blocks are
+    // streamed once per solve (non-temporal), x is shared by all rows
+    auto rows = [&](auto *M) {  // M: the segment's matrix in its storage precision
       for (int64_t c0 = 0; c0 < g.ncols; c0 += 64 * kRowUnroll) {
-        float mv[kRowUnroll];
         double xv[kRowUnroll];
 #pragma unroll
         for (int u = 0; u < kRowUnroll; ++u) {
           const int64_t c = c0 + lane + 64 * u;
-          const int64_t cc = c < last ? c : last;
-          mv[u] = __builtin_nontemporal_load(Mr + cc);
-          xv[u] = g.x[cc];
+          xv[u] = g.x[c < last ? c : last];
         }
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u)
-          part += (c0 + lane + 64 * u <= last ? 1.0 : 0.0) * ((double)mv[u] * xv[u]);
-      }
-    } else {
-      const double *Mr = g.M + row * g.ncols;
-      for (int64_t c0 = 0; c0 < g.ncols; c0 += 64 * kRowUnroll) {
-        double mv[kRowUnroll], xv[kRowUnroll];
+        for (int r = 0; r < RPW; ++r) {
+          const int64_t row = row0 + (r < nr ? r : 0);
+          double mv[kRowUnroll];
 #pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) {
-          const int64_t c = c0 + lane + 64 * u;
-          const int64_t cc = c < last ? c : last;
-          mv[u] = __builtin_nontemporal_load(Mr + cc);
-          xv[u] = g.x[cc];
+          for (int u = 0; u < kRowUnroll; ++u) {
+            const int64_t c = c0 + lane + 64 * u;
+            mv[u] = (double)__builtin_nontemporal_load(M + row * g.ncols + (c < last ? c : last));
+          }
+#pragma unroll
+          for (int u = 0; u < kRowUnroll; ++u)
+            part[r] += (c0 + lane + 64 * u <= last ? 1.0 : 0.0) * (mv[u] * xv[u]);
         }
-#pragma unroll
-        for (int u = 0; u < kRowUnroll; ++u) part += (c0 + lane + 64 * u <= last ? 1.0 : 0.0) * (mv[u] * xv[u]);
       }
-    }
-    acc += g.sign * part;
+    };
+    if (g.M32) rows(g.M32);  // wave-uniform: single-precision storage, double products and sums
+    else rows(g.M);
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) acc[r] += g.sign * part[r];
   }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) jb.y[row] = (jb.b ? jb.b[row] : 0.0) + acc;
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    double a = acc[r];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+    if (lane == 0 && r < nr) jb.y[row0 + r] = (jb.b ? jb.b[row0 + r] : 0.0) + a;
+  }
 }
 
 // ------------------------------------------------------------------ reductions
@@ -1871,7 +1881,11 @@ void launch_gemv_jobs(int njobs, const GemvJob *jobs, hipStream_t s) {
     rows += jobs[q].nrows;
   }
   if (rows == 0) return;
-  hipLaunchKernelGGL(gemv_jobs_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, J);
+  // two rows per wave (32^3 coarse chain: 0.4 ms less per FP64 solve than one; four rows per
+  // wave need 251 VGPRs and were slower)
+  constexpr int kRpw = 2;
+  const int64_t waves = (jobs[0].nrows + kRpw - 1) / kRpw + (njobs > 1 ? (jobs[1].nrows + kRpw - 1) / kRpw : 0);
+  hipLaunchKernelGGL((gemv_jobs_kernel<kRpw>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, J);
 }
 
 template <typename T>
