@@ -503,7 +503,7 @@ void vcycle(sem_ctx *c, int j, hipStream_t s) {
   // can be reduced on the way
   const bool last = j == 0 && post == 0;
   double *zout = last ? c->zout : nullptr;
-  const bool zdots = last && (zout || sizeof(T) == sizeof(double));
+  const bool zdots = last && (zout || c->zout32 || sizeof(T) == sizeof(double));
   if (L.type == LVL_SEM) {
     const int nb = launch_prolong<T>(L, C, V<T>::x(C), V<T>::J(L), x, zout, s, zdots ? c->zdot_r1 : nullptr,
                                      zdots ? c->zdot_r2 : nullptr, c->partials, c->partials_cap,
@@ -534,9 +534,12 @@ int vcycle_top(sem_ctx *c, const double *r, double *z, hipStream_t s, bool r32_r
   if (c->opt.precision == SEM_MIXED) {
     if (!r32_ready) launch_convert(L0.n, r, L0.b32, s);
     fused_out = c->opt.post_order == 0 && L0.type == LVL_SEM && c->levels.size() > 1;
+    // z == nullptr (only when fused_out): the result stays in FP32 in L0.x32
     c->zout = fused_out ? z : nullptr;
+    c->zout32 = fused_out && !z;
     vcycle<float>(c, 0, s);
     c->zout = nullptr;
+    c->zout32 = false;
     if (!fused_out) launch_convert(L0.n, L0.x32, z, s);
   } else {
     double *sb = L0.b64, *sx = L0.x64;
@@ -1949,17 +1952,24 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
   HIPCHK(c, hipEventCreateWithFlags(&sev.e, hipEventDisableTiming));
   double rn_prev = bnorm, rate = 1.0;  // last residual norm and reduction factor
   // z = M r with z . r (and z . r_old for the flexible beta), reduced inside the cycle when it
-  // can; then beta, x += alpha p and p = z + beta p
+  // can; then beta, x += alpha p and p = z + beta p. A one-sided mixed cycle leaves z in FP32
+  // (its values are single-precision numbers; widening them for storage would only add bytes)
+  const bool z32 = mixed && c->opt.post_order == 0 && L0.type == LVL_SEM && c->levels.size() > 1;
   auto next_direction = [&]() -> sem_status {
     int zb = 0;
-    TRY(vcycle_replay(c, r, z, s, mixed, r, flexible ? r2 : nullptr, &zb));
+    TRY(vcycle_replay(c, r, z32 ? nullptr : z, s, mixed, r, flexible ? r2 : nullptr, &zb));
     if (zb == 0) {
+      if (z32) {
+        c->err = "the single-precision cycle did not reduce z . r";
+        return SEM_EINVAL;
+      }
       if (flexible) launch_dots<double>(n, 2, z, r, z, r2, nullptr, nullptr, c->partials, kReduceBlocks, s);
       else launch_dots<double>(n, 1, z, r, nullptr, nullptr, nullptr, nullptr, c->partials, kReduceBlocks, s);
       zb = kReduceBlocks;
     }
     launch_finalize(zb, flexible ? 2 : 1, c->partials, c->scal, S_ZR, flexible ? FIN_BETA_FCG : FIN_BETA_PCG, s);
-    launch_update_xp(n, c->scal, u, z, p, s);
+    if (z32) launch_update_xp32(n, c->scal, u, L0.x32, p, s);
+    else launch_update_xp(n, c->scal, u, z, p, s);
     return SEM_OK;
   };
   for (it = 1; it <= maxit; ++it) {

@@ -262,6 +262,7 @@ struct sem_ctx {
   double *pinned = nullptr;    // host-pinned scalar mirror
   int64_t partials_cap = 0;    // doubles in partials
   double *zout = nullptr;      // set during a mixed one-sided cycle: widened output target
+  bool zout32 = false;         // or: the cycle's FP32 result stays in levels[0].x32 (no widening)
   // optional Krylov reductions fused into that cycle's last kernel: z . zdot_r1 (and z . zdot_r2)
   // reduced over zdot_blocks partials (0 when the cycle could not fuse them)
   const double *zdot_r1 = nullptr, *zdot_r2 = nullptr;

@@ -126,6 +126,7 @@ void launch_resid_norm(int64_t n, const double *b, const double *w, double *r, d
 void launch_update_r(int64_t n, double *scal, const double *r, const double *w, double *rnew, double *partials,
                      int nblocks, float *r32, hipStream_t s);
 void launch_update_xp(int64_t n, const double *scal, double *x, const double *z, double *p, hipStream_t s);
+void launch_update_xp32(int64_t n, const double *scal, double *x, const float *z, double *p, hipStream_t s);
 void launch_update_x(int64_t n, const double *scal, double *x, const double *p, hipStream_t s);
 void launch_convert(int64_t n, const double *in, float *out, hipStream_t s);
 void launch_convert(int64_t n, const float *in, double *out, hipStream_t s);

@@ -1167,6 +1167,16 @@ __global__ void update_xp_kernel(int64_t n, const double *__restrict__ scal, dou
   p[g] = z[g] + scal[S_BETA] * pg;
 }
 
+// The same with the single-precision cycle's result z (its exact FP64 value is the widened one)
+__global__ void update_xp32_kernel(int64_t n, const double *__restrict__ scal, double *__restrict__ x,
+                                   const float *__restrict__ z, double *__restrict__ p) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const double pg = p[g];
+  x[g] = x[g] + scal[S_ALPHA] * pg;
+  p[g] = (double)z[g] + scal[S_BETA] * pg;
+}
+
 __global__ void update_x_kernel(int64_t n, const double *__restrict__ scal, double *__restrict__ x,
                                 const double *__restrict__ p) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1914,6 +1924,9 @@ void launch_update_r(int64_t n, double *scal, const double *r, const double *w, 
 }
 void launch_update_xp(int64_t n, const double *scal, double *x, const double *z, double *p, hipStream_t s) {
   hipLaunchKernelGGL(update_xp_kernel, dim3(nblk(n)), dim3(256), 0, s, n, scal, x, z, p);
+}
+void launch_update_xp32(int64_t n, const double *scal, double *x, const float *z, double *p, hipStream_t s) {
+  hipLaunchKernelGGL(update_xp32_kernel, dim3(nblk(n)), dim3(256), 0, s, n, scal, x, z, p);
 }
 void launch_update_x(int64_t n, const double *scal, double *x, const double *p, hipStream_t s) {
   hipLaunchKernelGGL(update_x_kernel, dim3(nblk(n)), dim3(256), 0, s, n, scal, x, p);
