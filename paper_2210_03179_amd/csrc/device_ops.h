@@ -33,6 +33,14 @@ __device__ __forceinline__ float load_factor<float, float>(const float *p) { ret
 // cache-policy operand of the global-to-LDS loads for the same streams (non-temporal)
 constexpr int kFactorCpol = 2;
 
+// Element-local operator outputs are written non-temporally: the summation that consumes
+// them reads each line once, and streaming them out keeps L2 for the gathered input
+// vector (order-3 BF16 operator 13.6 -> 10.9 us, order-7 58.2 -> 57.1 us at 32^3).
+template <typename T>
+__device__ __forceinline__ void st_out(T *p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 // ------------------------------------------------------------------ box geometry helpers
 // Division by the (small) element order with a precomputed multiply-high reciprocal
 // (Granlund-Montgomery, rounding the reciprocal up): with l = ceil(log2 d) and
@@ -364,7 +372,7 @@ __device__ __forceinline__ void ax_body(unsigned blk, const Box &b, int64_t E, c
   if (active) {
     T *we = wL + e * n3;
 #pragma unroll
-    for (int k = 0; k < n1; ++k) we[(k * n1 + j) * n1 + i] = wreg[k];
+    for (int k = 0; k < n1; ++k) st_out(we + (k * n1 + j) * n1 + i, wreg[k]);
   }
   if (pdot) block_sum_store(dacc, pdot + blockIdx.x);
 }
@@ -512,7 +520,7 @@ __device__ __forceinline__ void ax_body_tri(unsigned blk, const Box &b, int64_t 
   if (active) {
     T *we = wL + e * n3;
 #pragma unroll
-    for (int k = 0; k < n1; ++k) we[(k * n1 + j) * n1 + i] = wreg[k];
+    for (int k = 0; k < n1; ++k) st_out(we + (k * n1 + j) * n1 + i, wreg[k]);
   }
 }
 
@@ -596,7 +604,7 @@ __device__ __forceinline__ void ax_body_tri_tile(unsigned blk, const Box &b, int
   if (active) {
     T *we = wL + e * n3;
 #pragma unroll
-    for (int k = 0; k < n1; ++k) we[(k * n1 + j) * n1 + i] = su[lec][k][j][i] + tt[k];
+    for (int k = 0; k < n1; ++k) st_out(we + (k * n1 + j) * n1 + i, su[lec][k][j][i] + tt[k]);
   }
 }
 
@@ -719,7 +727,7 @@ __device__ __forceinline__ void ax_body_tile(unsigned blk, const Box &b, int64_t
   if (active) {
     T *we = wL + e * n3;
 #pragma unroll
-    for (int k = 0; k < n1; ++k) we[(k * n1 + j) * n1 + i] = su[lec][k][j][i] + tt[k];
+    for (int k = 0; k < n1; ++k) st_out(we + (k * n1 + j) * n1 + i, su[lec][k][j][i] + tt[k]);
   }
   if (pdot) block_sum_store(dacc, pdot + blockIdx.x);
 }
@@ -839,7 +847,7 @@ __device__ __forceinline__ void ax_body_dma(unsigned blk, const Box &b, int64_t 
   if (active) {
     T *we = wL + e * n3;
 #pragma unroll
-    for (int k = 0; k < n1; ++k) we[(k * n1 + j) * n1 + i] = su[lec][k][j][i] + tt[k];
+    for (int k = 0; k < n1; ++k) st_out(we + (k * n1 + j) * n1 + i, su[lec][k][j][i] + tt[k]);
   }
 }
 
@@ -988,7 +996,7 @@ __device__ __forceinline__ void ax_body_mfma(unsigned blk, const Box &b, int64_t
   if (active) {
     T *we = wL + e * n3;
 #pragma unroll
-    for (int k = 0; k < n1; ++k) we[k * n1 * n1 + L] = ao[k >> 2][k & 3] + sv[k];
+    for (int k = 0; k < n1; ++k) st_out(we + k * n1 * n1 + L, ao[k >> 2][k & 3] + sv[k]);
   }
 }
 
@@ -1092,7 +1100,7 @@ __device__ __forceinline__ void ax_body_ring64(unsigned blk, const Box &b, int64
   }
   T *we = wL + e * n3;
 #pragma unroll
-  for (int k = 0; k < n1; ++k) we[(k * n1 + j) * n1 + i] = su[k][j][i] + tt[k];
+  for (int k = 0; k < n1; ++k) st_out(we + (k * n1 + j) * n1 + i, su[k][j][i] + tt[k]);
   if (pdot) block_sum_store(dacc, pdot + blockIdx.x);
 }
 
