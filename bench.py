@@ -126,6 +126,8 @@ def _variant_args(variant, N, fp64=False):
     mw = 4 if N <= 7 else 2
     if variant == 5 and fp64:  # the FP64 factor ring (N = 7); other orders launch variant 0
         return (0, mw, 3) if N == 7 else (1, 1, 0)
+    if variant == 6 and fp64:  # variant 2 with elements in launch order
+        return (1, mw, 5)
     if variant == 6 and N == 7:  # matrix-core contractions (BF16 factors at N = 7)
         return (0, mw, 4)
     return {0: (1, 1, 0), 1: (0, mw, 0), 2: (1, mw, 0), 3: (1, 1, 1), 4: (0, mw, 1), 5: (0, mw, 2),

@@ -296,9 +296,10 @@ sem_status sem_reset_counts(sem_ctx *ctx);
  * "diag", "mass", "coords", "lambda_max", "coarse_matrix" (dense, small
  * problems only), "ax_tuning" (all levels, `level` ignored: per level the
  * chosen FP64 operator variant, the measured time in microseconds of each of
- * the 7 variants (-1 where not timed; variant 6, the r and t contractions on
- * the matrix cores, exists for BF16 factors at N = 7 only, and FP64 has six),
- * then the same for single precision).
+ * the 7 variants (-1 where not timed; variant 6 is, for BF16 factors at N = 7
+ * only, the operator with its contractions on the matrix cores and, for FP64
+ * factors, variant 2 with the elements taken in launch order), then the same
+ * for single precision).
  * FD contexts: "diag", "matrix" (dense A_j, small problems only), "lambda_max",
  * and the sparse A_j and interpolation P_j (level j+1 -> j; Sec. 3: bilinear
  * interpolation, A_{j+1} = P_j^T A_j P_j) in CSR form as "csr_rowptr", "csr_col",

@@ -174,10 +174,10 @@ struct Level {
 constexpr int kGmresScalars = 2 * 32 + 2;  // projections (<= 32), ||w||^2, y (<= 32)
 // variant 5 stages factors by DMA: the whole element block for BF16 factors, a ring of
 // planes for FP64 factors at N = 7 (other FP64 orders launch variant 0 for it); variant 6
-// (BF16 factors at N = 7 only; variant 5 elsewhere) runs the contractions on the matrix
-// cores
+// runs the contractions on the matrix cores for BF16 factors at N = 7 (variant 5 at other
+// orders) and is variant 2 with elements taken in launch order for FP64 factors
 constexpr int kAxVariants = 7;
-constexpr int kAxVariants64 = 6;
+constexpr int kAxVariants64 = 7;
 constexpr int kAxVariantMfma = 6;
 constexpr int kAxTriVariants = 3;  // trilinear operator: (min_waves | 1 wave per SIMD) x register column, LDS tile
 

@@ -24,13 +24,17 @@ using namespace dev;
 // and TILE (0: u column in registers with one LDS plane, 1: whole u tile in LDS,
 // 2: u tile and the element's BF16 factors in LDS, single precision only; 3: u tile and a
 // ring of FP64 factor planes in LDS, N = 7 only; 4: as 2 with every contraction on the
-// matrix cores, BF16 factors at N = 7 only).
+// matrix cores, BF16 factors at N = 7 only; 5: as 0 with the blocks taking elements in
+// launch order instead of keeping runs of consecutive elements on one XCD: the FP64
+// operator at 32^3, N = 7 then streams its factors as one front through memory and runs
+// 5 % faster, although neighbouring elements share fewer u lines in L2).
 // pdot (FP64 variants, optional): per-block partials of u . A_L u (see ax_body).
 template <int N, typename T, typename GT, int PF, int OCC, int TILE = 0>
 __global__ void __launch_bounds__(AxShape<N>::block, OCC)
 ax_local_kernel(Box b, int64_t E, const T *__restrict__ u, const GT *__restrict__ G,
                 const T *__restrict__ Dm, T *__restrict__ wL, double *__restrict__ pdot) {
-  if constexpr (TILE == 4) ax_body_mfma<N>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
+  if constexpr (TILE == 5) ax_body<N, T, GT, PF>(blockIdx.x, b, E, u, G, Dm, wL, nullptr, pdot);
+  else if constexpr (TILE == 4) ax_body_mfma<N>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
   else if constexpr (TILE == 3) ax_body_ring64<N>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL, pdot);
   else if constexpr (TILE == 2) ax_body_dma<N>(xcd_block(blockIdx.x, gridDim.x), b, E, u, G, Dm, wL);
   else if constexpr (TILE == 1)
@@ -1512,6 +1516,13 @@ void launch_ax_n(const Level &L, const T *u, const GT *G, const T *D, T *wL, int
                  double *pdot = nullptr) {
   using S = AxShape<N>;
   const unsigned grid = (unsigned)((L.E + S::epb - 1) / S::epb);
+  if constexpr (sizeof(GT) == 8) {
+    if (variant == 6) {
+      hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 1, S::min_waves, 5>), dim3(grid), dim3(S::block), 0, s,
+                         mkbox(L), L.E, u, G, D, wL, pdot);
+      return;
+    }
+  }
   if constexpr (sizeof(GT) == 8 && N == 7) {
     if (variant == 5) {
       hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, 4, 3>), dim3(grid), dim3(S::block), 0, s, mkbox(L), L.E, u,
