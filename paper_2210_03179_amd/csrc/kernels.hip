@@ -1322,9 +1322,14 @@ b_ax32_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, int level, i
   const BatchLevelDev &L = S.lev[level];
   const float *u = src == 0 ? L.d : L.x;
   constexpr int TILE = BVar<N, V>::tile, PF = BVar<N, V>::pf;
-  if constexpr (TILE == 2) ax_body_dma<N>(blk, lbox(L), L.E, u, L.G, L.D, L.w);
-  else if constexpr (TILE == 1) ax_body_tile<N, float, uint16_t, PF>(blk, lbox(L), L.E, u, L.G, L.D, L.w);
-  else ax_body<N, float, uint16_t, PF>(blk, lbox(L), L.E, u, L.G, L.D, L.w);
+  // runs of consecutive elements of the system on one XCD, as in the single-system
+  // single-precision operator (the block range of a system starts anywhere: its XCDs are
+  // shifted, not mixed); order 7: 83.2 -> 78.9 us per batched launch of 64 systems
+  // (the FP64 operator keeps launch order, which the single-system FP64 one prefers)
+  const unsigned xb = xcd_block(blk, (unsigned)(tab.begin[slot_ + 1] - tab.begin[slot_]));
+  if constexpr (TILE == 2) ax_body_dma<N>(xb, lbox(L), L.E, u, L.G, L.D, L.w);
+  else if constexpr (TILE == 1) ax_body_tile<N, float, uint16_t, PF>(xb, lbox(L), L.E, u, L.G, L.D, L.w);
+  else ax_body<N, float, uint16_t, PF>(xb, lbox(L), L.E, u, L.G, L.D, L.w);
 }
 
 // FP64 operator on the finest level applied to the Krylov direction p
