@@ -273,7 +273,7 @@ def cpu_baseline(m, N, n_global):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of this build",
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is a design only",
               file=sys.stderr)
         sys.exit(2)
     import torch
