@@ -294,7 +294,10 @@ sem_status sem_reset_counts(sem_ctx *ctx);
 /* Host copies of setup arrays, for inspection and testing. `what` is one of
  * "gll_nodes", "gll_weights", "deriv", "interp" (to level+1), "factors",
  * "diag", "mass", "coords", "lambda_max", "coarse_matrix" (dense, small
- * problems only), "ax_tuning" (all levels, `level` ignored: per level the
+ * problems only), "krylov_operator_us" (the durations in microseconds of the
+ * Krylov operator launches of the last sem_solve, one per iteration, timed with
+ * events on the solve's stream when the environment sets SEMCHEB_TIME_KRYLOV_OP=1;
+ * empty otherwise; box meshes with stored factors), "ax_tuning" (all levels, `level` ignored: per level the
  * chosen FP64 operator variant, the measured time in microseconds of each of
  * the 7 variants (-1 where not timed; variant 6 is, for BF16 factors at N = 7
  * only, the operator with its contractions on the matrix cores and, for FP64

@@ -288,6 +288,13 @@ void smooth_schwarz(const sem_ctx *c, Level &L, int k, bool zero_guess, hipStrea
   }
 }
 
+// SEMCHEB_TIME_KRYLOV_OP=1: sem_solve times its Krylov operator launches with events (host
+// array "krylov_operator_us" of the context then holds the last solve's durations).
+bool krylov_op_timing_enabled() {
+  const char *v = std::getenv("SEMCHEB_TIME_KRYLOV_OP");
+  return v && v[0] == '1';
+}
+
 // Order-k Chebyshev smoothing of A x = b on level L (Algorithms 1 and 2).
 // zero_guess: x starts at 0 (k-1 applies); otherwise from the current x (k applies).
 template <typename T>
@@ -1576,6 +1583,8 @@ void release(sem_ctx *c) {
     hipDeviceSynchronize();
     for (auto &g : c->graphs) hipGraphExecDestroy(g.exec);
     c->graphs.clear();
+    for (hipEvent_t e : c->kop_events) hipEventDestroy(e);
+    c->kop_events.clear();
     if (c->capture_stream) hipStreamDestroy(c->capture_stream);
     for (void *p : c->allocations) hipFree(p);
     if (c->pinned) hipHostFree(c->pinned);
@@ -1884,6 +1893,7 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
   double *r = c->kr, *r2 = c->kr2, *z = c->kz, *p = c->kp, *w = c->kw;
   if (iters) *iters = 0;
   if (relres) *relres = 0.0;
+  c->kop_us.clear();
   // ||b||^2 and ||u0||^2
   launch_dots<double>(n, 2, b, b, u, u, nullptr, nullptr, c->partials, kReduceBlocks, s);
   launch_finalize(kReduceBlocks, 2, c->partials, c->scal, S_BB, FIN_NONE, s);
@@ -1972,10 +1982,25 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
     else launch_update_xp(n, c->scal, u, z, p, s);
     return SEM_OK;
   };
+  // the Krylov operator's own duration inside the solve, on request: an event pair around each
+  // launch on the solve's stream, read after the solve (the events add two stream markers per
+  // iteration and no synchronisation)
+  const bool kop_time = krylov_op_timing_enabled() && fused;
+  int kop_n = 0;
+  if (kop_time) {
+    while ((int64_t)c->kop_events.size() < 2 * (int64_t)maxit) {
+      hipEvent_t e;
+      HIPCHK(c, hipEventCreate(&e));
+      c->kop_events.push_back(e);
+    }
+  }
   for (it = 1; it <= maxit; ++it) {
     if (fused) {
       L0.applies++;
+      if (kop_time) HIPCHK(c, hipEventRecord(c->kop_events[2 * kop_n], s));
       const int nb = launch_ax_dot(L0, p, L0.w64, c->partials, s);
+      if (kop_time) HIPCHK(c, hipEventRecord(c->kop_events[2 * kop_n + 1], s));
+      if (kop_time) ++kop_n;
       launch_finalize(nb, 1, c->partials, c->scal, S_PW, FIN_NONE, s);
       const int nr = launch_update_r_dss(L0, c->scal, r, L0.w64, r2, c->partials, mixed ? L0.b32 : nullptr, s);
       launch_finalize(nr, 1, c->partials, c->scal, S_RR, FIN_NONE, s);
@@ -2025,6 +2050,14 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
   if (x_pending) launch_update_x(n, c->scal, u, p, s);
   HIPCHK(c, hipStreamSynchronize(s));
   HIPCHK(c, hipGetLastError());
+  if (kop_time) {
+    c->kop_us.clear();
+    for (int i = 0; i < kop_n; ++i) {
+      float ms = 0.0f;
+      HIPCHK(c, hipEventElapsedTime(&ms, c->kop_events[2 * i], c->kop_events[2 * i + 1]));
+      c->kop_us.push_back(1e3 * ms);
+    }
+  }
   if (status == SEM_ENOTCONV) c->err = "maximum number of iterations reached";
   return status;
 }
@@ -2130,7 +2163,10 @@ sem_status sem_host_array(const sem_ctx *c, const char *what, int32_t j, double 
   const std::vector<double> *src = nullptr;
   const std::string w(what);
   const bool sem = c->kind == LVL_SEM;
-  if (w == "ax_tuning") {
+  if (w == "krylov_operator_us") {
+    tmp = c->kop_us;
+    src = &tmp;
+  } else if (w == "ax_tuning") {
     // per level: variant64, kAxVariants timings (us), variant32, kAxVariants timings (us)
     for (auto &L : c->levels) {
       tmp.push_back(L.ax_variant64);

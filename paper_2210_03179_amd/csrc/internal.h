@@ -283,6 +283,10 @@ struct sem_ctx {
     std::vector<int64_t> applies;  // operator applications per level of one cycle
   };
   std::vector<CycleGraph> graphs;
+  // optional timing of the Krylov operator launches inside sem_solve (SEMCHEB_TIME_KRYLOV_OP=1):
+  // an event pair per iteration on the solve's stream, and the last solve's durations (us)
+  std::vector<hipEvent_t> kop_events;
+  std::vector<double> kop_us;
   bool use_graphs = true;
   hipStream_t capture_stream = nullptr;
   std::string err;

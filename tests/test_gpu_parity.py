@@ -465,3 +465,24 @@ def test_matrix_core_operator_matches_vector_variant(monkeypatch):
     d = relmax(out[6], out[5])
     print(f"matrix-core vs vector BF16 operator: max rel {d:.2e}", flush=True)
     assert d < 2e-6
+
+
+def test_krylov_operator_timing(small_case, monkeypatch):
+    """SEMCHEB_TIME_KRYLOV_OP=1 makes sem_solve time each Krylov operator launch with an event
+    pair on its stream: one positive duration per iteration in "krylov_operator_us", the same
+    solve bitwise, and an empty array once a solve runs without the switch."""
+    V, N, lmax = small_case
+    s = SemSolver(V, N=N, lambda_max=lmax, krylov="fcg")
+    b = dev(wl.uniform_noise(s.n, 41))
+    u0, info0 = s.solve(b)
+    assert s.host_array("krylov_operator_us").size == 0
+    monkeypatch.setenv("SEMCHEB_TIME_KRYLOV_OP", "1")
+    u1, info1 = s.solve(b)
+    t = s.host_array("krylov_operator_us")
+    print(f"Krylov operator: {t.size} launches timed, mean {t.mean():.1f} us", flush=True)
+    assert t.size == info1.iterations and np.all(t > 0)
+    assert torch.equal(u0, u1) and np.array_equal(info0.history, info1.history)
+    monkeypatch.delenv("SEMCHEB_TIME_KRYLOV_OP")
+    s.solve(b)
+    assert s.host_array("krylov_operator_us").size == 0
+    s.close()
