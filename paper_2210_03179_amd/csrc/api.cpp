@@ -1982,9 +1982,9 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
     else launch_update_xp(n, c->scal, u, z, p, s);
     return SEM_OK;
   };
-  // the Krylov operator's own duration inside the solve, on request: an event pair around each
-  // launch on the solve's stream, read after the solve (the events add two stream markers per
-  // iteration and no synchronisation)
+  // the Krylov operator's own duration inside the solve, on request: each launch takes an event
+  // pair as its kernel's start and end timestamps (no markers of their own on the stream, no
+  // synchronisation), read after the solve
   const bool kop_time = krylov_op_timing_enabled() && fused;
   int kop_n = 0;
   if (kop_time) {
@@ -1997,9 +1997,8 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
   for (it = 1; it <= maxit; ++it) {
     if (fused) {
       L0.applies++;
-      if (kop_time) HIPCHK(c, hipEventRecord(c->kop_events[2 * kop_n], s));
+      if (kop_time) set_ax_launch_events(c->kop_events[2 * kop_n], c->kop_events[2 * kop_n + 1]);
       const int nb = launch_ax_dot(L0, p, L0.w64, c->partials, s);
-      if (kop_time) HIPCHK(c, hipEventRecord(c->kop_events[2 * kop_n + 1], s));
       if (kop_time) ++kop_n;
       launch_finalize(nb, 1, c->partials, c->scal, S_PW, FIN_NONE, s);
       const int nr = launch_update_r_dss(L0, c->scal, r, L0.w64, r2, c->partials, mixed ? L0.b32 : nullptr, s);

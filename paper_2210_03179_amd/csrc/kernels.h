@@ -40,6 +40,9 @@ constexpr int kReduceBlocks = 1024;  // fixed grid of the reduction kernels (det
 
 bool launch_ax(const Level &L, const double *u, double *wL, hipStream_t s);
 bool launch_ax(const Level &L, const float *u, float *wL, hipStream_t s);
+// The next operator launch of this host thread fills start and stop with its kernel's own start
+// and end timestamps (used to time the Krylov operator inside a solve).
+void set_ax_launch_events(hipEvent_t start, hipEvent_t stop);
 // FP64 operator of a box level with stored factors that also reduces u . A_L u (p . Ap) into
 // one partial per block; returns the number of partials, 0 (nothing launched) when the level
 // cannot (trilinear factors, other level types)

@@ -8,6 +8,7 @@
 // stiffness summation) by the kernel that consumes them, reading the 1, 2, 4
 // or 8 element copies of each unknown in a fixed order: no atomics, results
 // are bitwise reproducible run to run.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -1512,6 +1513,19 @@ b_vec_kernel(LaunchTable tab, const BatchSysDev *__restrict__ sys, int op) {
 inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
 inline Box mkbox(const Level &L) { return Box{L.N, L.nex, L.ney, L.nez, L.nx, L.ny, L.nz, make_fastdiv(L.N)}; }
+
+// Events that the next operator launch of this host thread takes as the kernel's own start and
+// end timestamps (hipExtLaunchKernelGGL: no markers of their own on the stream), then clears.
+thread_local hipEvent_t t_ax_start = nullptr, t_ax_stop = nullptr;
+template <typename K, typename... Args>
+void ax_launch(K kernel, dim3 grid, dim3 block, hipStream_t s, Args... args) {
+  if (t_ax_start) {
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, t_ax_start, t_ax_stop, 0, args...);
+    t_ax_start = t_ax_stop = nullptr;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+  }
+}
 inline bool al16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 // variant 0: prefetch, compiler's register choice; 1: no prefetch, AxShape::min_waves;
@@ -1523,46 +1537,42 @@ void launch_ax_n(const Level &L, const T *u, const GT *G, const T *D, T *wL, int
   const unsigned grid = (unsigned)((L.E + S::epb - 1) / S::epb);
   if constexpr (sizeof(GT) == 8) {
     if (variant == 6) {
-      hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 1, S::min_waves, 5>), dim3(grid), dim3(S::block), 0, s,
-                         mkbox(L), L.E, u, G, D, wL, pdot);
+      ax_launch((ax_local_kernel<N, T, GT, 1, S::min_waves, 5>), dim3(grid), dim3(S::block), s, mkbox(L), L.E, u, G, D, wL, pdot);
       return;
     }
   }
   if constexpr (sizeof(GT) == 8 && N == 7) {
     if (variant == 5) {
-      hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, 4, 3>), dim3(grid), dim3(S::block), 0, s, mkbox(L), L.E, u,
+      ax_launch((ax_local_kernel<N, T, GT, 0, 4, 3>), dim3(grid), dim3(S::block), s, mkbox(L), L.E, u,
                          G, D, wL, pdot);
       return;
     }
   }
   if constexpr (sizeof(GT) == 2 && N == 7) {
     if (variant == 6) {
-      hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, S::min_waves, 4>), dim3(grid), dim3(S::block), 0, s,
-                         mkbox(L), L.E, u, G, D, wL, pdot);
+      ax_launch((ax_local_kernel<N, T, GT, 0, S::min_waves, 4>), dim3(grid), dim3(S::block), s, mkbox(L), L.E, u, G, D, wL, pdot);
       return;
     }
   }
   if constexpr (sizeof(GT) == 2) {
     if (variant >= 5) {
-      hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, S::min_waves, 2>), dim3(grid), dim3(S::block), 0, s,
-                         mkbox(L), L.E, u, G, D, wL, pdot);
+      ax_launch((ax_local_kernel<N, T, GT, 0, S::min_waves, 2>), dim3(grid), dim3(S::block), s, mkbox(L), L.E, u, G, D, wL, pdot);
       return;
     }
   }
   if (variant == 3)
-    hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 1, 1, 1>), dim3(grid), dim3(S::block), 0, s, mkbox(L), L.E, u,
+    ax_launch((ax_local_kernel<N, T, GT, 1, 1, 1>), dim3(grid), dim3(S::block), s, mkbox(L), L.E, u,
                        G, D, wL, pdot);
   else if (variant == 4)
-    hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, S::min_waves, 1>), dim3(grid), dim3(S::block), 0, s,
-                       mkbox(L), L.E, u, G, D, wL, pdot);
+    ax_launch((ax_local_kernel<N, T, GT, 0, S::min_waves, 1>), dim3(grid), dim3(S::block), s, mkbox(L), L.E, u, G, D, wL, pdot);
   else if (variant == 1)
-    hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 0, S::min_waves>), dim3(grid), dim3(S::block), 0, s, mkbox(L),
+    ax_launch((ax_local_kernel<N, T, GT, 0, S::min_waves>), dim3(grid), dim3(S::block), s, mkbox(L),
                        L.E, u, G, D, wL, pdot);
   else if (variant == 2)
-    hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 1, S::min_waves>), dim3(grid), dim3(S::block), 0, s, mkbox(L),
+    ax_launch((ax_local_kernel<N, T, GT, 1, S::min_waves>), dim3(grid), dim3(S::block), s, mkbox(L),
                        L.E, u, G, D, wL, pdot);
   else
-    hipLaunchKernelGGL((ax_local_kernel<N, T, GT, 1, 1>), dim3(grid), dim3(S::block), 0, s, mkbox(L), L.E, u, G,
+    ax_launch((ax_local_kernel<N, T, GT, 1, 1>), dim3(grid), dim3(S::block), s, mkbox(L), L.E, u, G,
                        D, wL, pdot);
 }
 
@@ -1642,6 +1652,11 @@ bool launch_ax(const Level &L, const double *u, double *wL, hipStream_t s) {
 bool launch_ax(const Level &L, const float *u, float *wL, hipStream_t s) {
   if (L.tri32) return launch_ax_tri<float>(L, u, L.tri32, L.gxw32, L.D32, wL, s);
   return launch_ax_t<float, uint16_t>(L, u, L.Gbf, L.D32, wL, s);
+}
+
+void set_ax_launch_events(hipEvent_t start, hipEvent_t stop) {
+  t_ax_start = start;
+  t_ax_stop = stop;
 }
 
 int launch_ax_dot(const Level &L, const double *u, double *wL, double *partials, hipStream_t s) {
