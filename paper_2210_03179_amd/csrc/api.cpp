@@ -1999,7 +1999,10 @@ sem_status sem_solve(sem_ctx *c, const double *b, double *u, double rtol, int32_
       L0.applies++;
       if (kop_time) set_ax_launch_events(c->kop_events[2 * kop_n], c->kop_events[2 * kop_n + 1]);
       const int nb = launch_ax_dot(L0, p, L0.w64, c->partials, s);
-      if (kop_time) ++kop_n;
+      if (kop_time) {
+        set_ax_launch_events(nullptr, nullptr);  // consumed by that launch; never left pending
+        ++kop_n;
+      }
       launch_finalize(nb, 1, c->partials, c->scal, S_PW, FIN_NONE, s);
       const int nr = launch_update_r_dss(L0, c->scal, r, L0.w64, r2, c->partials, mixed ? L0.b32 : nullptr, s);
       launch_finalize(nr, 1, c->partials, c->scal, S_RR, FIN_NONE, s);
